@@ -1,0 +1,177 @@
+/*
+ * dirprec: directional-preconditioned CFIE solves for 2-D high-frequency
+ * obstacle scattering on AMD MI355X (gfx950).
+ *
+ * Method: L. Ying, "Directional preconditioner for high frequency obstacle
+ * scattering".  The problem statement (Sec. 1) is a smooth closed boundary,
+ * sampled at n quadrature points with outward normals and weights, a
+ * frequency omega, a coupling parameter eta = O(omega), a boundary condition
+ * (sound-soft or sound-hard) and incident data; the unknown is the density q
+ * of the combined-field integral equation
+ *     soft (eq. (1)/(3)):  (1/2 I + D - i eta S) q = -u_I
+ *     hard (eq. (2)):      (1/2 I - D' + (1/(i eta)) N) q = -du_I/dn
+ * solved by right-preconditioned restarted GMRES (Sec. 3) with the
+ * directional preconditioner of Sec. 2.
+ *
+ * Conventions for every call below
+ *   - all sizes are int64_t; complex numbers are interleaved (re, im) pairs
+ *     of double; an n x nrhs complex array is column-major (column c starts
+ *     at complex offset c*n);
+ *   - pointers documented as "device" must point to device memory of the
+ *     context's GPU; the library reads/writes them on the context stream and
+ *     returns after that work has completed (every call is synchronous);
+ *   - "host" pointers are read/written before the call returns;
+ *   - the caller owns every buffer it passes; the library copies what it
+ *     keeps and frees its own allocations in the matching destroy call;
+ *   - return value: DP_OK (0) on success, DP_ENOCONV (> 0, a warning) when a
+ *     solve stopped before reaching the tolerance, a negative DP_E* code on
+ *     error; dp_last_error() then describes it (thread-local string);
+ *   - one dp_problem must not be used from two threads at once.
+ */
+#ifndef DIRPREC_H
+#define DIRPREC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dp_ctx dp_ctx;
+typedef struct dp_problem dp_problem;
+
+enum {
+  DP_OK = 0,
+  DP_ENOCONV = 1,     /* solve stopped at max_iters; q holds the last iterate */
+  DP_EINVAL = -1,     /* invalid argument (see dp_last_error) */
+  DP_ENOMEM = -2,     /* device allocation failed */
+  DP_EDEVICE = -3,    /* HIP runtime error */
+  DP_ESINGULAR = -4,  /* zero pivot in the sparse LU of floor(W) */
+  DP_ESTATE = -5      /* call order violated (e.g. apply before build) */
+};
+
+enum { DP_SOFT = 0, DP_HARD = 1 };
+
+/* Single operators for tests (Sec. 1 definitions, Kress-corrected Nystrom
+ * matrices): S, D, D', and the arclength derivative D_s of the trigonometric
+ * interpolant (used in Maue's form of N). */
+enum { DP_OP_S = 2, DP_OP_D = 3, DP_OP_DP = 4, DP_OP_DS = 5 };
+
+/* ------------------------------------------------------------------ context */
+/* device: HIP device ordinal.  stream: a hipStream_t to run on (e.g. the
+ * caller's current stream) or NULL for a library-owned stream.  Errors:
+ * DP_EINVAL (bad ordinal, out == NULL), DP_EDEVICE. */
+int dp_ctx_create(int device, void* stream, dp_ctx** out);
+void dp_ctx_destroy(dp_ctx* ctx);
+const char* dp_last_error(void);
+
+/* ------------------------------------------------------------------ problem */
+/* Boundary samples of Sec. 1 / Sec. 2 (host pointers, copied):
+ *   xy    n x 2 row-major node positions, counter-clockwise, equispaced in a
+ *         2*pi-periodic parameter t_j = 2*pi*j/n;
+ *   nrm   n x 2 row-major outward unit normals;
+ *   w     n quadrature weights w_j = (2*pi/n)|x'(t_j)| (trapezoid weights);
+ *   kappa n signed curvatures (positive where convex); needed by the
+ *         diagonal of D and D'.
+ * omega > 0 frequency, eta > 0 coupling (typically omega), kind DP_SOFT or
+ * DP_HARD.  Errors (DP_EINVAL): n odd or n < 16, DP_HARD with n not a power
+ * of two (the spectral derivative uses a radix-2 FFT), a non-finite entry,
+ * |nrm_j| differing from 1 by more than 1e-10, w_j <= 0, omega <= 0,
+ * eta <= 0.  The problem keeps device copies of the geometry and the Kress
+ * correction table C_k (k = 0..n-1). */
+int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nrm,
+                      const double* w, const double* kappa, double omega, double eta,
+                      int kind, dp_problem** out);
+void dp_problem_destroy(dp_problem* p);
+
+/* Incident plane waves u_I = exp(i omega d_k . x), d_k = (cos a_k, sin a_k)
+ * (Sec. 3 uses a_0 = 0).  angles: host, nrhs doubles.  f: device n x nrhs
+ * complex output, f = -u_I (soft) or -du_I/dn (hard). */
+int dp_rhs_plane_wave(dp_problem* p, int64_t nrhs, const double* angles, double* f);
+
+/* y = A q for the problem's CFIE matrix A (Sec. 1; hard via Maue's identity
+ * N = D_s S D_s + omega^2 (nu_1 S nu_1 + nu_2 S nu_2)).  q, y: device n x nrhs
+ * complex, must not overlap.  nrhs >= 1. */
+int dp_matvec(dp_problem* p, int64_t nrhs, const double* q, double* y);
+
+/* y = OP q for one operator (DP_OP_S, DP_OP_D, DP_OP_DP, DP_OP_DS); device
+ * n x nrhs complex arrays.  Exposed for parity tests of the single layers. */
+int dp_layer_apply(dp_problem* p, int op, int64_t nrhs, const double* q, double* y);
+
+/* ------------------------------------------------------------------ preconditioner */
+typedef struct {
+  double m_ell;    /* non-planar leaf length in wavelengths (Sec. 2.1: 2 or 4); default 4 */
+  int min_pts;     /* never split a segment below this many points; default 8 */
+  int m_c;         /* Chebyshev grid size for e_ij (Sec. 3: 10); default 10 */
+  double t_keep;   /* floor(T_i) keeps ~t_keep*|K_i| entries (Sec. 2.2); 0 = all; default 3 */
+} dp_precond_opts;
+
+typedef struct {
+  int64_t m;          /* number of segments */
+  int64_t n_classes;  /* distinct segment sizes */
+  int64_t NW;         /* dimension of floor(W) = sum_i |K_i| */
+  int64_t nnzE;       /* m (m - 1) */
+  int64_t nnzW;       /* non-zeros of floor(W) */
+  int64_t nnzLU;      /* non-zeros of its sparse LU factors */
+  int64_t levels;     /* dependency levels of the two triangular solves */
+  double t_setup;     /* seconds spent in dp_precond_build */
+} dp_precond_info;
+
+/* Build the directional preconditioner of Sec. 2 (segments, flat blocks B_j,
+ * partial Fourier factors U_i, S_i = U_i^t B_i^{-1} U_i, T_i = S_i^{-1},
+ * floor(T_i), rank-1 entries e_ij of eq. (14), floor(W) = E + antidiag(T) and
+ * its sparse LU).  opts may be NULL (defaults).  Requires arclength-
+ * equispaced nodes (all w_j equal within 1e-12 relative), else DP_EINVAL;
+ * DP_ESINGULAR on a zero pivot. */
+int dp_precond_build(dp_problem* p, const dp_precond_opts* opts);
+
+/* z = P v: the first block of eq. (19) applied to (v, 0, 0).  Device n x nrhs
+ * complex arrays (must not overlap).  DP_ESTATE before dp_precond_build. */
+int dp_precond_apply(dp_problem* p, int64_t nrhs, const double* v, double* z);
+
+int dp_precond_get_info(dp_problem* p, dp_precond_info* info);
+
+/* Structure export for tests (host arrays, caller-allocated):
+ * seg_off, seg_len: m entries; e_idx: 4*m*(m-1) entries (i, j, k^i_ij,
+ * k^j_ij for each ordered pair, row-major in (i, j)); e_val: 2*m*(m-1)
+ * doubles (e_ij).  Any pointer may be NULL. */
+int dp_precond_export(dp_problem* p, int64_t* seg_off, int64_t* seg_len, int64_t* e_idx,
+                      double* e_val);
+
+/* ------------------------------------------------------------------ solve */
+typedef struct {
+  double tol;       /* relative residual ||f - A q|| / ||f|| per column; default 1e-8 */
+  int restart;      /* GMRES restart length; default 80 (Sec. 3) */
+  int max_iters;    /* total Arnoldi steps per column; default 2000 */
+  int use_precond;  /* 1: right-precondition with the built preconditioner */
+} dp_solve_opts;
+
+typedef struct {
+  int64_t iters_max;   /* largest iteration count over the columns */
+  int64_t matvecs;     /* operator applications (including true-residual checks) */
+  int64_t applies;     /* preconditioner applications */
+  double relres_max;   /* largest true relative residual at exit */
+  double t_total, t_matvec, t_apply, t_krylov;  /* seconds */
+} dp_solve_info;
+
+/* Solve A q = f for nrhs right-hand sides by restarted GMRES (x0 = 0, CGS2
+ * Arnoldi, Givens rotations), right-preconditioned when requested; the
+ * preconditioned vectors are stored (flexible form) so q = Z y needs no extra
+ * apply.  f, q: device n x nrhs complex.  opts/info may be NULL.  iters,
+ * relres: optional host arrays of nrhs entries (per-column iteration counts
+ * and true relative residuals).  Returns DP_OK or DP_ENOCONV. */
+int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_solve_opts* opts,
+             dp_solve_info* info, int64_t* iters, double* relres);
+
+/* ------------------------------------------------------------------ test hooks */
+/* H_0^(1)(z), H_1^(1)(z) for m real z > 0: out[4k..4k+3] = Re H0, Im H0,
+ * Re H1, Im H1.  _dev: device arrays evaluated by the GPU kernel code;
+ * _host: host arrays evaluated by the same source compiled for the CPU. */
+int dp_hankel_dev(dp_ctx* ctx, int64_t m, const double* z, double* out);
+int dp_hankel_host(int64_t m, const double* z, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIRPREC_H */

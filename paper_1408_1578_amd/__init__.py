@@ -1,0 +1,284 @@
+"""Python binding of libdirprec (directional-preconditioned CFIE solves on MI355X).
+
+Argument marshalling only: every numerical step runs in the HIP library
+(`libdirprec.so`, built in-tree by `paper_1408_1578_amd.build`).  The
+functions carry the names of the C-ABI in include/dirprec.h.  Device arrays
+are torch complex128 CUDA tensors laid out as (nrhs, n) (i.e. column-major
+n x nrhs); torch is used for device memory and the stream only.
+
+Importing this package does not need a GPU; loading the library does not
+either, but every compute call does.  If the library is missing the calls
+raise instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdirprec.so")
+
+DP_OK, DP_ENOCONV = 0, 1
+DP_EINVAL, DP_ENOMEM, DP_EDEVICE, DP_ESINGULAR, DP_ESTATE = -1, -2, -3, -4, -5
+DP_SOFT, DP_HARD = 0, 1
+DP_OP_S, DP_OP_D, DP_OP_DP, DP_OP_DS = 2, 3, 4, 5
+
+# every symbol declared in include/dirprec.h
+EXPORTED = [
+    "dp_ctx_create", "dp_ctx_destroy", "dp_last_error", "dp_problem_create",
+    "dp_problem_destroy", "dp_rhs_plane_wave", "dp_matvec", "dp_layer_apply",
+    "dp_precond_build", "dp_precond_apply", "dp_precond_get_info", "dp_precond_export",
+    "dp_solve", "dp_hankel_dev", "dp_hankel_host",
+]
+
+
+class DpError(RuntimeError):
+    def __init__(self, func, code, msg):
+        super().__init__(f"{func} failed with code {code}: {msg}")
+        self.code = code
+
+
+class PrecondOpts(ctypes.Structure):
+    _fields_ = [("m_ell", ctypes.c_double), ("min_pts", ctypes.c_int),
+                ("m_c", ctypes.c_int), ("t_keep", ctypes.c_double)]
+
+
+class PrecondInfo(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n_classes", ctypes.c_int64), ("NW", ctypes.c_int64),
+                ("nnzE", ctypes.c_int64), ("nnzW", ctypes.c_int64), ("nnzLU", ctypes.c_int64),
+                ("levels", ctypes.c_int64), ("t_setup", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int),
+                ("max_iters", ctypes.c_int), ("use_precond", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters_max", ctypes.c_int64), ("matvecs", ctypes.c_int64),
+                ("applies", ctypes.c_int64), ("relres_max", ctypes.c_double),
+                ("t_total", ctypes.c_double), ("t_matvec", ctypes.c_double),
+                ("t_apply", ctypes.c_double), ("t_krylov", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdirprec.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "dp_ctx_create": (ci, [ci, vp, pp]),
+        "dp_ctx_destroy": (None, [vp]),
+        "dp_last_error": (ctypes.c_char_p, []),
+        "dp_problem_create": (ci, [vp, i64, vp, vp, vp, vp, dbl, dbl, ci, pp]),
+        "dp_problem_destroy": (None, [vp]),
+        "dp_rhs_plane_wave": (ci, [vp, i64, vp, vp]),
+        "dp_matvec": (ci, [vp, i64, vp, vp]),
+        "dp_layer_apply": (ci, [vp, ci, i64, vp, vp]),
+        "dp_precond_build": (ci, [vp, ctypes.POINTER(PrecondOpts)]),
+        "dp_precond_apply": (ci, [vp, i64, vp, vp]),
+        "dp_precond_get_info": (ci, [vp, ctypes.POINTER(PrecondInfo)]),
+        "dp_precond_export": (ci, [vp, vp, vp, vp, vp]),
+        "dp_solve": (ci, [vp, i64, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp, vp]),
+        "dp_hankel_dev": (ci, [vp, i64, vp, vp]),
+        "dp_hankel_host": (ci, [i64, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(name, rc, allow=()):
+    if rc < 0 and rc not in allow:
+        raise DpError(name, rc, lib().dp_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (complex128 or float64, contiguous)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _cols(t, n):
+    if t.dtype.__str__() != "torch.complex128":
+        raise TypeError("expected a complex128 tensor")
+    if t.dim() == 1:
+        if t.shape[0] != n:
+            raise ValueError("length mismatch")
+        return 1
+    if t.dim() != 2 or t.shape[1] != n:
+        raise ValueError("expected shape (nrhs, n)")
+    return t.shape[0]
+
+
+def _host(a, dtype=np.float64):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------- context
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        h = ctypes.c_void_p()
+        s = None if stream is None else ctypes.c_void_p(stream)
+        _check("dp_ctx_create", lib().dp_ctx_create(device, s, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().dp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dp_ctx_create(device=0, stream=None):
+    return Context(device, stream)
+
+
+def dp_ctx_destroy(ctx):
+    ctx.close()
+
+
+# ---------------------------------------------------------------- problem
+class Problem:
+    def __init__(self, ctx, x, nu, w, kappa, omega, eta, kind):
+        n = int(np.asarray(w).size)
+        xa, xp = _host(np.asarray(x).reshape(n, 2))
+        na, np_ = _host(np.asarray(nu).reshape(n, 2))
+        wa, wp = _host(w)
+        ka, kp = _host(kappa)
+        h = ctypes.c_void_p()
+        _check("dp_problem_create", lib().dp_problem_create(ctx.h, n, xp, np_, wp, kp, float(omega),
+                                                            float(eta), int(kind), ctypes.byref(h)))
+        self.h, self.n, self.kind, self.ctx = h, n, kind, ctx
+        self.omega, self.eta = float(omega), float(eta)
+
+    @classmethod
+    def from_boundary(cls, ctx, b, omega, eta, kind):
+        return cls(ctx, b.x, b.nu, b.w, b.kappa, omega, eta, kind)
+
+    def close(self):
+        if self.h:
+            lib().dp_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dp_problem_create(ctx, x, nu, w, kappa, omega, eta, kind):
+    return Problem(ctx, x, nu, w, kappa, omega, eta, kind)
+
+
+def dp_problem_destroy(p):
+    p.close()
+
+
+def dp_rhs_plane_wave(p, angles, f):
+    a, ap = _host(np.atleast_1d(angles))
+    nr = _cols(f, p.n)
+    if nr != a.size:
+        raise ValueError("angles / columns mismatch")
+    _check("dp_rhs_plane_wave", lib().dp_rhs_plane_wave(p.h, nr, ap, _ptr(f)))
+
+
+def dp_matvec(p, q, y):
+    nr = _cols(q, p.n)
+    if _cols(y, p.n) != nr:
+        raise ValueError("shape mismatch")
+    _check("dp_matvec", lib().dp_matvec(p.h, nr, _ptr(q), _ptr(y)))
+
+
+def dp_layer_apply(p, op, q, y):
+    nr = _cols(q, p.n)
+    if _cols(y, p.n) != nr:
+        raise ValueError("shape mismatch")
+    _check("dp_layer_apply", lib().dp_layer_apply(p.h, int(op), nr, _ptr(q), _ptr(y)))
+
+
+def dp_precond_build(p, m_ell=4.0, min_pts=8, m_c=10, t_keep=3.0):
+    o = PrecondOpts(m_ell, min_pts, m_c, t_keep)
+    _check("dp_precond_build", lib().dp_precond_build(p.h, ctypes.byref(o)))
+
+
+def dp_precond_apply(p, v, z):
+    nr = _cols(v, p.n)
+    if _cols(z, p.n) != nr:
+        raise ValueError("shape mismatch")
+    _check("dp_precond_apply", lib().dp_precond_apply(p.h, nr, _ptr(v), _ptr(z)))
+
+
+def dp_precond_get_info(p):
+    info = PrecondInfo()
+    _check("dp_precond_get_info", lib().dp_precond_get_info(p.h, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in PrecondInfo._fields_}
+
+
+def dp_precond_export(p):
+    info = dp_precond_get_info(p)
+    m = info["m"]
+    off = np.zeros(m, np.int64)
+    ln = np.zeros(m, np.int64)
+    ei = np.zeros(4 * m * (m - 1), np.int64)
+    ev = np.zeros(2 * m * (m - 1), np.float64)
+    _check("dp_precond_export", lib().dp_precond_export(
+        p.h, off.ctypes.data_as(ctypes.c_void_p), ln.ctypes.data_as(ctypes.c_void_p),
+        ei.ctypes.data_as(ctypes.c_void_p), ev.ctypes.data_as(ctypes.c_void_p)))
+    return off, ln, ei.reshape(-1, 4), ev.view(np.complex128)
+
+
+def dp_solve(p, f, q, tol=1e-8, restart=80, max_iters=2000, use_precond=False):
+    nr = _cols(f, p.n)
+    if _cols(q, p.n) != nr:
+        raise ValueError("shape mismatch")
+    o = SolveOpts(tol, restart, max_iters, 1 if use_precond else 0)
+    info = SolveInfo()
+    its = np.zeros(nr, np.int64)
+    rel = np.zeros(nr, np.float64)
+    rc = _check("dp_solve", lib().dp_solve(p.h, nr, _ptr(f), _ptr(q), ctypes.byref(o), ctypes.byref(info),
+                                           its.ctypes.data_as(ctypes.c_void_p),
+                                           rel.ctypes.data_as(ctypes.c_void_p)))
+    out = {f_: getattr(info, f_) for f_, _ in SolveInfo._fields_}
+    out["converged"] = rc == DP_OK
+    out["iters"] = its
+    out["relres"] = rel
+    return out
+
+
+def dp_hankel_dev(ctx, z, out):
+    _check("dp_hankel_dev", lib().dp_hankel_dev(ctx.h, z.numel(), _ptr(z), _ptr(out)))
+
+
+def dp_hankel_host(z):
+    za, zp = _host(np.atleast_1d(z))
+    out = np.zeros(4 * za.size)
+    _check("dp_hankel_host", lib().dp_hankel_host(za.size, zp, out.ctypes.data_as(ctypes.c_void_p)))
+    out = out.reshape(-1, 4)
+    return out[:, 0] + 1j * out[:, 1], out[:, 2] + 1j * out[:, 3]

@@ -1,0 +1,285 @@
+// C-ABI of the dirprec library: argument validation, ownership and error
+// reporting.  All numerical work is done by the HIP kernels in the other
+// translation units.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "dp_internal.hpp"
+
+namespace dp {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int DevBuf::reserve(size_t want) {
+  if (want <= bytes && p) return DP_OK;
+  release();
+  if (want == 0) want = 8;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    p = nullptr;
+    bytes = 0;
+    (void)hipGetLastError();
+    set_error("hipMalloc of %zu bytes failed", want);
+    return DP_ENOMEM;
+  }
+  bytes = want;
+  return DP_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+static bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace dp
+
+using namespace dp;
+
+#define DP_CHECK(cond, ...)        \
+  do {                             \
+    if (!(cond)) {                 \
+      ::dp::set_error(__VA_ARGS__); \
+      return DP_EINVAL;            \
+    }                              \
+  } while (0)
+
+#define DP_SETDEV(ctx) DP_HIP(hipSetDevice((ctx)->device))
+
+extern "C" {
+
+const char* dp_last_error(void) { return g_err; }
+
+int dp_ctx_create(int device, void* stream, dp_ctx** out) {
+  DP_CHECK(out != nullptr, "dp_ctx_create: out is NULL");
+  int ndev = 0;
+  DP_HIP(hipGetDeviceCount(&ndev));
+  DP_CHECK(device >= 0 && device < ndev, "dp_ctx_create: device %d out of range (%d devices)", device, ndev);
+  DP_HIP(hipSetDevice(device));
+  dp_ctx* c = new dp_ctx();
+  c->device = device;
+  if (stream) {
+    c->stream = static_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {  // blocking: orders with the null stream
+      delete c;
+      set_error("hipStreamCreate failed");
+      return DP_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return DP_OK;
+}
+
+void dp_ctx_destroy(dp_ctx* c) {
+  if (!c) return;
+  if (c->own_stream) {
+    (void)hipSetDevice(c->device);
+    (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nrm, const double* w,
+                      const double* kappa, double omega, double eta, int kind, dp_problem** out) {
+  DP_CHECK(ctx && out && xy && nrm && w && kappa, "dp_problem_create: NULL argument");
+  DP_CHECK(n >= 16 && n % 2 == 0 && n <= (1LL << 26), "dp_problem_create: n = %lld must be even, >= 16",
+           (long long)n);
+  DP_CHECK(kind == DP_SOFT || kind == DP_HARD, "dp_problem_create: kind %d", kind);
+  DP_CHECK(kind == DP_SOFT || is_pow2(n), "dp_problem_create: sound-hard needs a power-of-two n (got %lld)",
+           (long long)n);
+  DP_CHECK(std::isfinite(omega) && omega > 0, "dp_problem_create: omega must be > 0");
+  DP_CHECK(std::isfinite(eta) && eta > 0, "dp_problem_create: eta must be > 0");
+  const double w0 = w[0];
+  bool equi = true;
+  for (int64_t i = 0; i < n; ++i) {
+    const double v[6] = {xy[2 * i], xy[2 * i + 1], nrm[2 * i], nrm[2 * i + 1], w[i], kappa[i]};
+    for (double t : v) DP_CHECK(std::isfinite(t), "dp_problem_create: non-finite input at node %lld", (long long)i);
+    DP_CHECK(w[i] > 0, "dp_problem_create: weight %lld is not positive", (long long)i);
+    const double nn = std::hypot(nrm[2 * i], nrm[2 * i + 1]);
+    DP_CHECK(std::fabs(nn - 1.0) <= 1e-10, "dp_problem_create: normal %lld has length %.17g", (long long)i, nn);
+    if (std::fabs(w[i] - w0) > 1e-12 * w0) equi = false;
+  }
+  DP_SETDEV(ctx);
+  dp_problem* p = new dp_problem();
+  p->ctx = ctx;
+  p->n = n;
+  p->kind = kind;
+  p->omega = omega;
+  p->eta = eta;
+  p->equispaced = equi;
+  p->hx.resize(n);
+  p->hy.resize(n);
+  p->hnx.resize(n);
+  p->hny.resize(n);
+  p->hsp.resize(n);
+  p->hkap.resize(n);
+  std::vector<SrcRec> rec(n);
+  double L = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    p->hx[i] = xy[2 * i];
+    p->hy[i] = xy[2 * i + 1];
+    p->hnx[i] = nrm[2 * i];
+    p->hny[i] = nrm[2 * i + 1];
+    p->hsp[i] = w[i] * (double)n / (2.0 * kPi);
+    p->hkap[i] = kappa[i];
+    L += w[i];
+    rec[i] = {p->hx[i], p->hy[i], p->hnx[i], p->hny[i], p->hsp[i], p->hkap[i], 0.0, 0.0};
+  }
+  p->L = L;
+  int rc = p->src.reserve(n * sizeof(SrcRec));
+  if (rc == DP_OK && hipMemcpyAsync(p->src.p, rec.data(), n * sizeof(SrcRec), hipMemcpyHostToDevice,
+                                    ctx->stream) != hipSuccess) {
+    set_error("geometry upload failed");
+    rc = DP_EDEVICE;
+  }
+  if (rc == DP_OK) rc = build_tables(p);
+  if (rc != DP_OK) {
+    dp_problem_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return DP_OK;
+}
+
+void dp_problem_destroy(dp_problem* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->ctx->device);
+  (void)hipStreamSynchronize(p->ctx->stream);
+  if (p->pc) precond_destroy(p->pc);
+  p->src.release();
+  p->C.release();
+  p->twiddle.release();
+  p->dens.release();
+  p->partial.release();
+  p->tmp1.release();
+  p->tmp2.release();
+  p->tmp3.release();
+  delete p;
+}
+
+int dp_rhs_plane_wave(dp_problem* p, int64_t nrhs, const double* angles, double* f) {
+  DP_CHECK(p && angles && f && nrhs >= 1, "dp_rhs_plane_wave: bad argument");
+  DP_SETDEV(p->ctx);
+  DevBuf a;
+  DP_TRY(a.reserve(nrhs * sizeof(double)));
+  DP_HIP(hipMemcpyAsync(a.p, angles, nrhs * sizeof(double), hipMemcpyHostToDevice, p->ctx->stream));
+  int rc = rhs_plane_wave(p, (int)nrhs, a.as<double>(), reinterpret_cast<cplx*>(f));
+  DP_HIP(hipStreamSynchronize(p->ctx->stream));
+  a.release();
+  return rc;
+}
+
+int dp_matvec(dp_problem* p, int64_t nrhs, const double* q, double* y) {
+  DP_CHECK(p && q && y && nrhs >= 1 && q != y, "dp_matvec: bad argument");
+  DP_SETDEV(p->ctx);
+  DP_TRY(matvec(p, (int)nrhs, reinterpret_cast<const cplx*>(q), reinterpret_cast<cplx*>(y)));
+  DP_HIP(hipStreamSynchronize(p->ctx->stream));
+  return DP_OK;
+}
+
+int dp_layer_apply(dp_problem* p, int op, int64_t nrhs, const double* q, double* y) {
+  DP_CHECK(p && q && y && nrhs >= 1 && q != y, "dp_layer_apply: bad argument");
+  DP_CHECK(op == DP_OP_S || op == DP_OP_D || op == DP_OP_DP || op == DP_OP_DS, "dp_layer_apply: op %d", op);
+  DP_CHECK(op != DP_OP_DS || is_pow2(p->n), "dp_layer_apply: D_s needs a power-of-two n");
+  DP_SETDEV(p->ctx);
+  if (op == DP_OP_DS) {
+    DP_TRY(spectral_derivative(p, (int)nrhs, reinterpret_cast<const cplx*>(q), reinterpret_cast<cplx*>(y)));
+  } else {
+    DP_TRY(sweep_apply(p, op, (int)nrhs, reinterpret_cast<const cplx*>(q), reinterpret_cast<cplx*>(y)));
+  }
+  DP_HIP(hipStreamSynchronize(p->ctx->stream));
+  return DP_OK;
+}
+
+int dp_precond_build(dp_problem* p, const dp_precond_opts* opts) {
+  DP_CHECK(p != nullptr, "dp_precond_build: NULL problem");
+  DP_CHECK(p->equispaced, "dp_precond_build: nodes must be arclength-equispaced (equal weights)");
+  dp_precond_opts o = {4.0, 8, 10, 3.0};
+  if (opts) o = *opts;
+  DP_CHECK(o.m_ell > 0 && o.min_pts >= 2 && o.m_c >= 2 && o.m_c <= 32 && o.t_keep >= 0,
+           "dp_precond_build: bad options");
+  DP_SETDEV(p->ctx);
+  return precond_build(p, &o);
+}
+
+int dp_precond_apply(dp_problem* p, int64_t nrhs, const double* v, double* z) {
+  DP_CHECK(p && v && z && nrhs >= 1 && v != z, "dp_precond_apply: bad argument");
+  if (!p->pc) {
+    set_error("dp_precond_apply: call dp_precond_build first");
+    return DP_ESTATE;
+  }
+  DP_SETDEV(p->ctx);
+  DP_TRY(precond_apply(p, (int)nrhs, reinterpret_cast<const cplx*>(v), reinterpret_cast<cplx*>(z)));
+  DP_HIP(hipStreamSynchronize(p->ctx->stream));
+  return DP_OK;
+}
+
+int dp_precond_get_info(dp_problem* p, dp_precond_info* info) {
+  DP_CHECK(p && info, "dp_precond_get_info: NULL argument");
+  if (!p->pc) {
+    set_error("dp_precond_get_info: no preconditioner");
+    return DP_ESTATE;
+  }
+  return precond_info(p, info);
+}
+
+int dp_precond_export(dp_problem* p, int64_t* seg_off, int64_t* seg_len, int64_t* e_idx, double* e_val) {
+  DP_CHECK(p != nullptr, "dp_precond_export: NULL problem");
+  if (!p->pc) {
+    set_error("dp_precond_export: no preconditioner");
+    return DP_ESTATE;
+  }
+  return precond_export(p, seg_off, seg_len, e_idx, e_val);
+}
+
+int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_solve_opts* opts,
+             dp_solve_info* info, int64_t* iters, double* relres) {
+  DP_CHECK(p && f && q && nrhs >= 1 && f != q, "dp_solve: bad argument");
+  dp_solve_opts o = {1e-8, 80, 2000, 0};
+  if (opts) o = *opts;
+  DP_CHECK(o.tol > 0 && o.restart >= 1 && o.restart <= 1000 && o.max_iters >= 1, "dp_solve: bad options");
+  if (o.use_precond && !p->pc) {
+    set_error("dp_solve: use_precond set but no preconditioner was built");
+    return DP_ESTATE;
+  }
+  DP_SETDEV(p->ctx);
+  return solve(p, (int)nrhs, reinterpret_cast<const cplx*>(f), reinterpret_cast<cplx*>(q), &o, info, iters,
+               relres);
+}
+
+int dp_hankel_dev(dp_ctx* ctx, int64_t m, const double* z, double* out) {
+  DP_CHECK(ctx && z && out && m >= 0, "dp_hankel_dev: bad argument");
+  DP_SETDEV(ctx);
+  DP_TRY(hankel_eval_dev(m, z, out, ctx->stream));
+  DP_HIP(hipStreamSynchronize(ctx->stream));
+  return DP_OK;
+}
+
+int dp_hankel_host(int64_t m, const double* z, double* out) {
+  DP_CHECK(z && out && m >= 0, "dp_hankel_host: bad argument");
+  for (int64_t k = 0; k < m; ++k) {
+    DP_CHECK(z[k] > 0 && std::isfinite(z[k]), "dp_hankel_host: z must be finite and > 0");
+    const H01 h = hankel01(z[k]);
+    out[4 * k + 0] = h.h0.re;
+    out[4 * k + 1] = h.h0.im;
+    out[4 * k + 2] = h.h1.re;
+    out[4 * k + 3] = h.h1.im;
+  }
+  return DP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal structures of the dirprec library (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dirprec.h"
+#include "dp_math.hpp"
+
+namespace dp {
+
+void set_error(const char* fmt, ...);
+
+#define DP_HIP(call)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      ::dp::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call,                \
+                      hipGetErrorString(e_));                                   \
+      return DP_EDEVICE;                                                        \
+    }                                                                           \
+  } while (0)
+
+#define DP_TRY(call)            \
+  do {                          \
+    int r_ = (call);            \
+    if (r_ < 0) return r_;      \
+  } while (0)
+
+// Device buffer that grows on demand (hipMalloc'd, owned by the library).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int reserve(size_t want);
+  void release();
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// One source record: geometry of node j, 64 bytes so one scalar load fetches it.
+struct SrcRec {
+  double x, y, nx, ny, sp, kappa, pad0, pad1;
+};
+
+enum SweepOp { OP_SOFT = 0, OP_HARD = 1, OP_S = 2, OP_D = 3, OP_DP = 4 };
+
+struct SweepParams {
+  const SrcRec* src;       // n records
+  const double* C;         // n: Kress correction C_k (index (i - j) mod n)
+  const cplx* dens;        // [j][nd][nrp] source densities (transposed layout)
+  cplx* partial;           // [chunk][nd][nrp][n] partial sums
+  int n, nrp, nd, chunk_len, nchunks;
+  double omega, eta, dt;   // dt = 2 pi / n
+};
+
+struct Precond;
+
+}  // namespace dp
+
+struct dp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+};
+
+struct dp_problem {
+  dp_ctx* ctx = nullptr;
+  int64_t n = 0;
+  int kind = 0;
+  double omega = 0, eta = 0, L = 0, R0 = 0;
+  bool equispaced = false;
+  std::vector<double> hx, hy, hnx, hny, hsp, hkap;  // host copies
+  dp::DevBuf src;       // SrcRec[n]
+  dp::DevBuf C;         // double[n]
+  dp::DevBuf twiddle;   // cplx[n]   (e^{-2 pi i l/n})
+  dp::DevBuf dens;      // sweep operands
+  dp::DevBuf partial;   // sweep partial sums
+  dp::DevBuf tmp1, tmp2, tmp3;
+  dp::Precond* pc = nullptr;
+  double t_last_setup = 0;
+};
+
+namespace dp {
+// tables.hip
+int build_tables(dp_problem* p);
+// sweep.hip
+int sweep_apply(dp_problem* p, int op, int nrhs, const cplx* q, cplx* y);
+int matvec(dp_problem* p, int nrhs, const cplx* q, cplx* y);
+// fft.hip
+int spectral_derivative(dp_problem* p, int nrhs, const cplx* in, cplx* out);
+// rhs
+int rhs_plane_wave(dp_problem* p, int nrhs, const double* angles_dev, cplx* f);
+// hankel test hook
+int hankel_eval_dev(int64_t m, const double* z, double* out, hipStream_t s);
+// krylov.hip
+struct Gmres;
+int solve(dp_problem* p, int nrhs, const cplx* f, cplx* q, const dp_solve_opts* o, dp_solve_info* info,
+          int64_t* iters, double* relres);
+// precond
+int precond_build(dp_problem* p, const dp_precond_opts* o);
+int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* z);
+void precond_destroy(Precond* pc);
+int precond_info(dp_problem* p, dp_precond_info* info);
+int precond_export(dp_problem* p, int64_t* seg_off, int64_t* seg_len, int64_t* e_idx, double* e_val);
+}  // namespace dp

@@ -1,0 +1,190 @@
+// Device/host math for the CFIE kernels: sin/cos with Cody-Waite reduction
+// and the Hankel functions H_0^(1), H_1^(1) of a real positive argument.
+//
+// The Green's function of the Helmholtz equation is (i/4) H_0^(1)(omega r)
+// (Sec. 1); its normal derivatives bring in H_1^(1).  Both are evaluated
+// here from published formulas:
+//   * z >= DP_HANKEL_ZA: Hankel's asymptotic expansion (DLMF 10.17.5),
+//       H_nu(z) ~ sqrt(2/(pi z)) e^{i(z - nu pi/2 - pi/4)} sum_k i^k a_k(nu) z^-k,
+//       a_k(nu) = prod_{m=1..k} (4 nu^2 - (2m-1)^2) / (k! 8^k),
+//     truncated after DP_HANKEL_NTERMS terms (truncation error < 1e-17 at
+//     z = DP_HANKEL_ZA);
+//   * z < DP_HANKEL_ZA: J_0, J_1 by Miller's backward recurrence
+//     J_{k-1} = (2k/z) J_k - J_{k+1} normalised by J_0 + 2 sum J_{2k} = 1
+//     (DLMF 10.74(iv), 10.12.4), Y_0 by Neumann's series (DLMF 10.23.?:
+//     Y_0 = (2/pi)[(ln(z/2)+gamma) J_0 - 2 sum_{k>=1} (-1)^k J_{2k}/k]) and
+//     Y_1 = -Y_0' from the same series differentiated term by term,
+//       Y_1 = (2/pi)[-J_0/z + (ln(z/2)+gamma) J_1 - J_1
+//              + sum_{m>=1} (-1)^{m+1} (2m+1)/(m(m+1)) J_{2m+1}].
+// sin/cos: x = k pi/2 + r, |r| <= pi/4, with pi/2 split in two doubles and
+// fused multiply-adds, then the Taylor series of sin and cos in r.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#define DP_HD __host__ __device__ __forceinline__
+
+namespace dp {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kEulerGamma = 0.57721566490153286060651209008240243;
+// pi/2 = kPio2Hi + kPio2Lo; kPio2Hi is the double nearest to pi/2 and kPio2Lo
+// the double nearest to the remainder (pi/2 evaluated to 40 digits).
+constexpr double kPio2Hi = 1.5707963267948966192313216916397514;
+constexpr double kPio2Lo = 6.123233995736766035868820147291819e-17;
+constexpr double kTwoOverPi = 0.63661977236758134307553505349005745;
+constexpr double kSqrt2OverPi = 0.79788456080286535587989211986876373;
+constexpr double kInvSqrt2 = 0.70710678118654752440084436210484904;
+
+struct cplx {
+  double re, im;
+};
+
+DP_HD cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+DP_HD cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+DP_HD cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
+// acc += a * b
+DP_HD void cfma(cplx& acc, cplx a, cplx b) {
+  acc.re = fma(a.re, b.re, fma(-a.im, b.im, acc.re));
+  acc.im = fma(a.re, b.im, fma(a.im, b.re, acc.im));
+}
+
+// --------------------------------------------------------------- sin / cos
+// 1/(2k+1)! and 1/(2k)! built from their definition at compile time.
+constexpr double inv_fact(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return 1.0 / f;
+}
+
+DP_HD void sincos_reduced(double r, double& s, double& c) {
+  const double r2 = r * r;
+  // sin r = r + r^3 sum_{k=1..8} (-1)^k r^{2k-2}/(2k+1)!   (|r| <= pi/4)
+  double ps = inv_fact(17);
+#pragma unroll
+  for (int k = 7; k >= 1; --k) ps = fma(ps, r2, ((k & 1) ? -1.0 : 1.0) * inv_fact(2 * k + 1));
+  s = fma(ps * r2, r, r);
+  // cos r = 1 + r^2 sum_{k=1..9} (-1)^k r^{2k-2}/(2k)!
+  double pc = -inv_fact(18);
+#pragma unroll
+  for (int k = 8; k >= 1; --k) pc = fma(pc, r2, ((k & 1) ? -1.0 : 1.0) * inv_fact(2 * k));
+  c = fma(pc, r2, 1.0);
+}
+
+// sin and cos of x for |x| < 2^40.
+DP_HD void dp_sincos(double x, double& s, double& c) {
+  const double k = rint(x * kTwoOverPi);
+  double r = fma(-k, kPio2Hi, x);
+  r = fma(-k, kPio2Lo, r);
+  double sr, cr;
+  sincos_reduced(r, sr, cr);
+  const long long q = (long long)k & 3;
+  // x = k pi/2 + r: rotate (cos r, sin r) by q quarter turns
+  const double s1 = (q & 1) ? cr : sr;
+  const double c1 = (q & 1) ? sr : cr;
+  s = (q & 2) ? -s1 : s1;
+  c = ((q + 1) & 2) ? -c1 : c1;
+}
+
+DP_HD double dp_rsqrt(double z) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __ocml_rsqrt_f64(z);
+#else
+  return 1.0 / sqrt(z);
+#endif
+}
+
+// --------------------------------------------------------------- Hankel
+constexpr double DP_HANKEL_ZA = 25.0;
+constexpr int DP_HANKEL_NTERMS = 19;  // k = 0..18
+
+// a_k(nu) of the Hankel expansion, from its product definition.
+constexpr double hankel_a(int k, int nu) {
+  double p = 1.0;
+  for (int m = 1; m <= k; ++m) p *= (4.0 * nu * nu - (2.0 * m - 1) * (2.0 * m - 1)) / (8.0 * m);
+  return p;
+}
+
+struct H01 {
+  cplx h0, h1;
+};
+
+// Asymptotic branch, z >= DP_HANKEL_ZA.  P + iQ = sum_k i^k a_k t^k, t = 1/z.
+DP_HD H01 hankel01_far(double z) {
+  const double y = dp_rsqrt(z);
+  const double t = y * y;
+  const double t2 = t * t;
+  // P_nu = sum_j a_{2j} (-t^2)^j, Q_nu = t sum_j a_{2j+1} (-t^2)^j  (Horner in -t^2)
+  const double u = -t2;
+  double p0 = hankel_a(18, 0), p1 = hankel_a(18, 1);
+#pragma unroll
+  for (int k = 16; k >= 0; k -= 2) {
+    p0 = fma(p0, u, hankel_a(k, 0));
+    p1 = fma(p1, u, hankel_a(k, 1));
+  }
+  double q0 = hankel_a(17, 0), q1 = hankel_a(17, 1);
+#pragma unroll
+  for (int k = 15; k >= 1; k -= 2) {
+    q0 = fma(q0, u, hankel_a(k, 0));
+    q1 = fma(q1, u, hankel_a(k, 1));
+  }
+  q0 *= t;
+  q1 *= t;
+  double s, c;
+  dp_sincos(z, s, c);
+  const double m = kSqrt2OverPi * y * kInvSqrt2;
+  // e^{i(z - pi/4)} = ((c + s) + i (s - c))/sqrt2 ; e^{i(z - 3pi/4)} = ((s - c) - i (s + c))/sqrt2
+  const cplx e0 = {(c + s) * m, (s - c) * m};
+  const cplx e1 = {(s - c) * m, -(s + c) * m};
+  H01 h;
+  h.h0 = cmul(e0, cplx{p0, q0});
+  h.h1 = cmul(e1, cplx{p1, q1});
+  return h;
+}
+
+// Small/moderate argument branch, 0 < z < DP_HANKEL_ZA.
+DP_HD H01 hankel01_near(double z) {
+  const int N = 2 * (int)((z + 41.0) * 0.5);  // even start index, J_N(z) < 1e-19 J_0
+  const double tz = 2.0 / z;
+  double jp1 = 0.0, jk = 1e-30;  // J_{k+1}, J_k (unnormalised), k = N
+  double norm = 0.0, s0 = 0.0, s1 = 0.0;
+  for (int k = N; k >= 1; --k) {
+    const double jm1 = fma((double)k * tz, jk, -jp1);  // J_{k-1}
+    const int idx = k - 1;
+    if (idx >= 2 && !(idx & 1)) {
+      const int m = idx >> 1;
+      norm = fma(2.0, jm1, norm);
+      s0 += ((m & 1) ? 1.0 : -1.0) * jm1 / (double)m;  // (-1)^{m+1} J_{2m}/m
+    } else if (idx >= 3) {
+      const int m = (idx - 1) >> 1;
+      s1 += ((m & 1) ? 1.0 : -1.0) * (2.0 * m + 1.0) / ((double)m * (m + 1.0)) * jm1;
+    }
+    jp1 = jk;
+    jk = jm1;
+    if (fabs(jk) > 1e250) {
+      jp1 *= 1e-250;
+      jk *= 1e-250;
+      norm *= 1e-250;
+      s0 *= 1e-250;
+      s1 *= 1e-250;
+    }
+  }
+  // now jk = J_0, jp1 = J_1 (unnormalised)
+  norm += jk;
+  const double sc = 1.0 / norm;
+  const double J0 = jk * sc, J1 = jp1 * sc;
+  s0 *= sc;
+  s1 *= sc;
+  const double lg = log(0.5 * z) + kEulerGamma;
+  const double Y0 = (2.0 / kPi) * (lg * J0 + 2.0 * s0);
+  const double Y1 = (2.0 / kPi) * (-J0 / z + lg * J1 - J1 + s1);
+  H01 h;
+  h.h0 = {J0, Y0};
+  h.h1 = {J1, Y1};
+  return h;
+}
+
+DP_HD H01 hankel01(double z) { return z >= DP_HANKEL_ZA ? hankel01_far(z) : hankel01_near(z); }
+
+}  // namespace dp

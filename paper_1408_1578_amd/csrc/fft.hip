@@ -1,0 +1,175 @@
+// Arclength derivative of the trigonometric interpolant (Nyquist mode
+// dropped), used by Maue's form of the hypersingular operator:
+//   (D_s phi)_i = (1/|x'(t_i)|) * IDFT( i m DFT(phi) )_i,  m in (-n/2, n/2).
+// Radix-2 FFT for power-of-two n, batched over columns.  n <= 4096: one
+// line per column, transformed in LDS.  Larger n: four-step with
+// n = n1 * n2 (n1, n2 <= 4096): length-n1 transforms over the stride-n2
+// index with the twiddle e^{-+2 pi i j2 k1/n}, then length-n2 transforms of
+// contiguous lines; the spectrum is left in the transposed order
+// X[k1 + n1 k2] at position n2 k1 + k2, multiplied there, and the inverse
+// runs the two passes in reverse order.
+#include "dp_internal.hpp"
+
+namespace dp {
+
+constexpr int kFftLds = 4096;  // complex elements per block
+
+__device__ __forceinline__ unsigned bitrev(unsigned v, int bits) { return __brev(v) >> (32 - bits); }
+
+// In-LDS radix-2 DIT transform of `lines` lines of length Lf stored as
+// buf[e * lines + l] (element-major, so that loads over lines coalesce).
+// Input must be in bit-reversed element order.  dir = -1 forward, +1 inverse.
+__device__ void lds_fft(cplx* buf, int Lf, int lines, int logL, const cplx* tw, int ntw, int dir) {
+  for (int half = 1; half < Lf; half <<= 1) {
+    const int nb = (Lf >> 1) * lines;
+    const int stride = ntw / (2 * half);
+    for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+      const int l = t % lines;
+      const int b = t / lines;
+      const int pos = b & (half - 1);
+      const int i0 = ((b - pos) << 1) + pos;
+      const int i1 = i0 + half;
+      cplx w = tw[pos * stride];
+      if (dir > 0) w.im = -w.im;
+      const cplx a = buf[i0 * lines + l];
+      const cplx bb = cmul(buf[i1 * lines + l], w);
+      buf[i0 * lines + l] = {a.re + bb.re, a.im + bb.im};
+      buf[i1 * lines + l] = {a.re - bb.re, a.im - bb.im};
+    }
+    __syncthreads();
+  }
+  (void)logL;
+}
+
+// Column pass: for each column b and each j2 in [0, n2): line over j1 (stride
+// n2).  Optional twiddle e^{dir 2 pi i j2 k1/n}: applied after the transform
+// (forward) or before it (inverse).
+__global__ void fft_col_pass(cplx* data, int n, int n1, int n2, int logn1, int lines,
+                             const cplx* __restrict__ tw, int dir, int twiddle) {
+  extern __shared__ cplx sbuf[];
+  const int b = blockIdx.y;
+  const int j2_0 = blockIdx.x * lines;
+  cplx* base = data + (size_t)b * n;
+  for (int t = threadIdx.x; t < n1 * lines; t += blockDim.x) {
+    const int l = t % lines, j1 = t / lines;
+    cplx v = base[(size_t)n2 * j1 + j2_0 + l];
+    if (twiddle && dir > 0) {  // inverse: pre-twiddle e^{+2 pi i j2 k1/n} (k1 = j1 here)
+      cplx w = tw[((size_t)(j2_0 + l) * j1) % n];
+      w.im = -w.im;
+      v = cmul(v, w);
+    }
+    sbuf[bitrev(j1, logn1) * lines + l] = v;
+  }
+  __syncthreads();
+  lds_fft(sbuf, n1, lines, logn1, tw, n, dir);
+  for (int t = threadIdx.x; t < n1 * lines; t += blockDim.x) {
+    const int l = t % lines, k1 = t / lines;
+    cplx v = sbuf[k1 * lines + l];
+    if (twiddle && dir < 0) v = cmul(v, tw[((size_t)(j2_0 + l) * k1) % n]);
+    base[(size_t)n2 * k1 + j2_0 + l] = v;
+  }
+}
+
+// Row pass: lines of n2 contiguous elements starting at n2 * k1.
+__global__ void fft_row_pass(cplx* data, int n, int n2, int logn2, int lines, const cplx* __restrict__ tw,
+                             int dir) {
+  extern __shared__ cplx sbuf[];
+  const int b = blockIdx.y;
+  const int k1_0 = blockIdx.x * lines;
+  cplx* base = data + (size_t)b * n + (size_t)k1_0 * n2;
+  for (int t = threadIdx.x; t < n2 * lines; t += blockDim.x) {
+    const int e = t % n2, l = t / n2;
+    sbuf[bitrev(e, logn2) * lines + l] = base[(size_t)l * n2 + e];
+  }
+  __syncthreads();
+  lds_fft(sbuf, n2, lines, logn2, tw, n, dir);
+  for (int t = threadIdx.x; t < n2 * lines; t += blockDim.x) {
+    const int e = t % n2, l = t / n2;
+    base[(size_t)l * n2 + e] = sbuf[e * lines + l];
+  }
+}
+
+// Spectrum at position p = n2 k1 + k2 holds X[k1 + n1 k2]: multiply by
+// i m / n (m the signed frequency, Nyquist zeroed).
+__global__ void deriv_scale(cplx* data, int n, int n1, int n2, int nb) {
+  const size_t tot = (size_t)n * nb;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int p = idx % n;
+    const int k1 = p / n2, k2 = p % n2;
+    const int k = k1 + n1 * k2;
+    const int m = (k < n / 2) ? k : ((k == n / 2) ? 0 : k - n);
+    const cplx v = data[idx];
+    const double f = (double)m / n;
+    data[idx] = {-f * v.im, f * v.re};
+  }
+}
+
+__global__ void copy_div_speed(const cplx* __restrict__ in, cplx* __restrict__ out, const SrcRec* __restrict__ src,
+                               int n, size_t tot, int divide) {
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    cplx v = in[idx];
+    if (divide) {
+      const double s = 1.0 / src[idx % n].sp;
+      v = {v.re * s, v.im * s};
+    }
+    out[idx] = v;
+  }
+}
+
+static int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+static void fft_passes(dp_problem* p, cplx* d, int nb, int dir) {
+  const int n = (int)p->n;
+  const int logn = ilog2(n);
+  const int log1 = logn <= 12 ? logn : (logn + 1) / 2;
+  const int log2n = logn - log1;
+  const int n1 = 1 << log1, n2 = 1 << log2n;
+  const cplx* tw = p->twiddle.as<cplx>();
+  hipStream_t st = p->ctx->stream;
+  auto col = [&](int dirc) {
+    int lines = kFftLds / n1;
+    if (lines > n2) lines = n2;
+    dim3 g(n2 / lines, nb);
+    fft_col_pass<<<g, 256, (size_t)n1 * lines * sizeof(cplx), st>>>(d, n, n1, n2, log1, lines, tw, dirc,
+                                                                     n2 > 1);
+  };
+  auto row = [&](int dirc) {
+    if (n2 == 1) return;
+    int lines = kFftLds / n2;
+    if (lines > n1) lines = n1;
+    dim3 g(n1 / lines, nb);
+    fft_row_pass<<<g, 256, (size_t)n2 * lines * sizeof(cplx), st>>>(d, n, n2, log2n, lines, tw, dirc);
+  };
+  if (dir < 0) {
+    col(-1);
+    row(-1);
+  } else {
+    row(+1);
+    col(+1);
+  }
+}
+
+int spectral_derivative(dp_problem* p, int nrhs, const cplx* in, cplx* out) {
+  const int n = (int)p->n;
+  const size_t tot = (size_t)n * nrhs;
+  hipStream_t st = p->ctx->stream;
+  size_t g = (tot + 255) / 256;
+  const int grid = (int)(g > 8192 ? 8192 : g);
+  copy_div_speed<<<grid, 256, 0, st>>>(in, out, p->src.as<SrcRec>(), n, tot, 0);
+  fft_passes(p, out, nrhs, -1);
+  const int logn = ilog2(n);
+  const int log1 = logn <= 12 ? logn : (logn + 1) / 2;
+  deriv_scale<<<grid, 256, 0, st>>>(out, n, 1 << log1, 1 << (logn - log1), nrhs);
+  fft_passes(p, out, nrhs, +1);
+  copy_div_speed<<<grid, 256, 0, st>>>(out, out, p->src.as<SrcRec>(), n, tot, 1);
+  DP_HIP(hipGetLastError());
+  return DP_OK;
+}
+
+}  // namespace dp
