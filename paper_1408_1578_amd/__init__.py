@@ -74,6 +74,14 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -c 'import __graft_entry__ as g; g.build()'`")
+    # torch ships its own HIP runtime under the same soname; initialise it first
+    # so that the library binds to that one copy (one runtime per process).
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     pp = ctypes.POINTER(ctypes.c_void_p)

@@ -1,10 +1,959 @@
-// placeholder, replaced below
+// Directional preconditioner of Sec. 2 on the GPU.
+//
+// Setup (dp_precond_build), in the paper's order:
+//   Sec. 2.1  segments P_1..P_m (host, O(m)); per segment size class s:
+//             the flat block B_s (Kress-discretised operator on a straight
+//             segment of s points), B_s^{-1} (Gauss-Jordan, partial
+//             pivoting), the partial Fourier factor
+//             U_s(a, j) = exp(2 pi i j (a - (s-1)/2)/s), j = -J..J (eq. (12)),
+//             S_s = U_s^t B_s^{-1} U_s, T_s = S_s^{-1} (Sec. 2.2) and its
+//             thresholded floor(T_s);
+//             centres c_i, tangents t_i and m_c first-kind Chebyshev points of
+//             every segment by trigonometric interpolation of the nodes;
+//             for every ordered pair i != j: the rounded directions
+//             k^i_ij = [omega a_ij . t_i]_i, k^j_ij = [-omega a_ij . t_j]_j and
+//             e_ij = alpha_i^t M~_ij(R_i, R_j) alpha_j (eq. (14)), one block
+//             per pair.
+//   Sec. 2.2  floor(W) = E + antidiag(T) assembled and LU-factored on the
+//             host (sparse, see sparse_lu.cpp); factors copied to the device.
+// Apply (eq. (19) on (v, 0, 0)), all on the device:
+//   y = B^{-1} v; g = U^t y; z = floor(T) g; u = floor(W)^{-1} z;
+//   h = z - floor(T) u; q = y - B^{-1} (U h).
+// The per-segment dense products are batched complex GEMMs whose left operand
+// is shared by all segments of a size class.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <vector>
+
 #include "dp_internal.hpp"
+#include "sparse_lu.hpp"
+
 namespace dp {
-struct Precond {};
-int precond_build(dp_problem* p, const dp_precond_opts* o) { set_error("not built"); return DP_ESTATE; }
-int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* z) { set_error("not built"); return DP_ESTATE; }
-void precond_destroy(Precond* pc) { delete pc; }
-int precond_info(dp_problem* p, dp_precond_info* info) { return DP_ESTATE; }
-int precond_export(dp_problem* p, int64_t* a, int64_t* b, int64_t* c, double* d) { return DP_ESTATE; }
+
+using zc = std::complex<double>;
+constexpr double kInv4Pi_p = 0.079577471545947667884441881686257181;
+
+struct SizeClass {
+  int s = 0, J = 0, K = 0;
+  DevBuf Binv, U, Ut, Tt, alpha;
+  std::vector<cplx> T;  // full T_s on the host (antidiagonal goes into floor(W))
+};
+
+struct Precond {
+  int m = 0, NW = 0, m_c = 10;
+  std::vector<int> off, len, cls, J, offK;
+  std::vector<SizeClass> classes;
+  DevBuf d_segs;    // int4 per segment: off, len, offK, cls
+  DevBuf d_ptrs;    // per class: Binv, U, Ut, Tt pointers
+  DevBuf d_dims;    // per class: s, K
+  // E
+  std::vector<int> eidx;  // 4 per pair
+  std::vector<cplx> eval;
+  // sparse LU on the device
+  SparseLU lu;
+  DevBuf Lp, Lj, Lx, Up, Uj, Ux, Ud, lvlL, lvlLr, lvlU, lvlUr, pin, pout;
+  int nlevL = 0, nlevU = 0;
+  int64_t nnzW = 0;
+  DevBuf wy, wg, wz, wu, wt, wn;  // apply workspaces
+  double t_setup = 0;
+};
+
+// ------------------------------------------------------------------ helpers
+static int grid1(size_t tot) {
+  size_t g = (tot + 255) / 256;
+  return (int)(g > 8192 ? 8192 : (g ? g : 1));
 }
+
+template <class T>
+static int upload(DevBuf& b, const std::vector<T>& v, hipStream_t st) {
+  DP_TRY(b.reserve(std::max<size_t>(1, v.size()) * sizeof(T)));
+  if (!v.empty()) DP_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return DP_OK;
+}
+
+__device__ __forceinline__ double round_half_away(double x) { return x >= 0 ? floor(x + 0.5) : -floor(-x + 0.5); }
+
+// ------------------------------------------------------------------ flat blocks
+// Row B(d), d = 0..s-1 of the symmetric Toeplitz flat block (spacing ds,
+// parameter speed sp = L/(2 pi), global Kress table C with C[0] = R_0).
+//   soft: B = 1/2 - i eta S_flat,
+//     S_flat(d) = ds (i/4) H0(omega d ds) - C_d sp J0/(4 pi)           (d >= 1)
+//     S_flat(0) = -R_0 sp/(4 pi) + dt sp (i/4 - gamma/(2 pi) - log(omega sp/2)/(2 pi))
+//   hard: B = 1/2 + N_flat/(i eta), N_flat = f.p. (i omega/4) H1(omega r)/r:
+//     N_flat(d) = ds (i omega/4) H1(omega r)/r - C_d sp (omega/(4 pi)) J1(omega r)/r
+//                 + [d = 1] 1/(4 pi ds)                               (r = d ds)
+//     N_flat(0) = R_0 k1 + dt k2 - pi/(6 ds) - 1/(2 pi ds),
+//       k1 = -(omega^2/(8 pi)) sp,
+//       k2 = sp (i omega^2/8 - (omega^2/(4 pi)) (log(omega sp/2) + gamma - 1/2))
+//   (Laplace part 1/(2 pi r^2) by the finite-part trapezoid correction; the
+//   log-singular remainder by the Kress rule.)
+__global__ void flat_row(const double* __restrict__ C, cplx* row, int s, int n, double L, double omega,
+                         double eta, int kind) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= s) return;
+  const double ds = L / n, sp = L / (2.0 * kPi), dt = 2.0 * kPi / n;
+  cplx v;
+  if (kind == DP_SOFT) {
+    cplx S;
+    if (d == 0) {
+      S = {-C[0] * sp * kInv4Pi_p + dt * sp * (-kEulerGamma - log(0.5 * omega * sp)) * (2.0 * kInv4Pi_p),
+           0.25 * dt * sp};
+    } else {
+      const H01 h = hankel01(omega * d * ds);
+      S = {-0.25 * ds * h.h0.im - C[d] * sp * kInv4Pi_p * h.h0.re, 0.25 * ds * h.h0.re};
+    }
+    v = {eta * S.im, -eta * S.re};  // -i eta S
+  } else {
+    cplx N;
+    if (d == 0) {
+      const double k1 = -(omega * omega / 8.0 / kPi) * sp;
+      const double k2re = -sp * (omega * omega * kInv4Pi_p) * (log(0.5 * omega * sp) + kEulerGamma - 0.5);
+      const double k2im = sp * omega * omega / 8.0;
+      N = {C[0] * k1 + dt * k2re - kPi / (6.0 * ds) - 1.0 / (2.0 * kPi * ds), dt * k2im};
+    } else {
+      const double r = d * ds;
+      const H01 h = hankel01(omega * r);
+      // (i omega/4) H1 / r * ds
+      N = {-0.25 * omega * h.h1.im / r * ds - C[d] * sp * omega * kInv4Pi_p * h.h1.re / r,
+           0.25 * omega * h.h1.re / r * ds};
+      if (d == 1) N.re += 1.0 / (4.0 * kPi * ds);
+    }
+    v = {N.im / eta, -N.re / eta};  // N/(i eta) = -i N/eta
+  }
+  if (d == 0) v.re += 0.5;
+  row[d] = v;
+}
+
+// Dense s x s Toeplitz matrix from its first row, augmented with the identity
+// (row-major s x 2s) for Gauss-Jordan.
+__global__ void toeplitz_aug(const cplx* __restrict__ row, cplx* A, int s) {
+  const size_t tot = (size_t)s * 2 * s;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int r = idx / (2 * s), c = idx % (2 * s);
+    A[idx] = c < s ? row[abs(r - c)] : cplx{(c - s == r) ? 1.0 : 0.0, 0.0};
+  }
+}
+
+// ------------------------------------------------------------------ Gauss-Jordan
+// Step k on the augmented row-major s x 2s matrix: choose the pivot row (max
+// modulus in column k among rows >= k), swap it into row k, scale row k by the
+// inverse pivot, and save the multipliers A[i][k] of every row.
+__global__ __launch_bounds__(256) void gj_pivot(cplx* A, int s, int k, cplx* mult, int* status) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  const int w = 2 * s;
+  double best = -1.0;
+  int bidx = k;
+  for (int i = k + threadIdx.x; i < s; i += 256) {
+    const cplx a = A[(size_t)i * w + k];
+    const double m = a.re * a.re + a.im * a.im;
+    if (m > best) {
+      best = m;
+      bidx = i;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bidx;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      const double o = bv[threadIdx.x + st];
+      const int oi = bi[threadIdx.x + st];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int p = bi[0];
+  if (!(bv[0] > 0.0)) {
+    if (threadIdx.x == 0) status[0] = 1;
+    return;
+  }
+  if (p != k) {
+    for (int c = threadIdx.x; c < w; c += 256) {
+      const cplx t = A[(size_t)k * w + c];
+      A[(size_t)k * w + c] = A[(size_t)p * w + c];
+      A[(size_t)p * w + c] = t;
+    }
+  }
+  __syncthreads();
+  const cplx pv = A[(size_t)k * w + k];
+  const double den = pv.re * pv.re + pv.im * pv.im;
+  const cplx inv = {pv.re / den, -pv.im / den};
+  __syncthreads();
+  for (int c = threadIdx.x; c < w; c += 256) A[(size_t)k * w + c] = cmul(A[(size_t)k * w + c], inv);
+  for (int i = threadIdx.x; i < s; i += 256) mult[i] = (i == k) ? cplx{0.0, 0.0} : A[(size_t)i * w + k];
+}
+
+// Row i -= mult[i] * row k (all rows but k, columns k..2s-1).
+__global__ void gj_update(cplx* A, int s, int k, const cplx* __restrict__ mult, const int* __restrict__ status) {
+  if (status[0]) return;
+  const int w = 2 * s;
+  const int cols = w - k;
+  const size_t tot = (size_t)s * cols;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int i = idx / cols;
+    const int c = k + (int)(idx % cols);
+    if (i == k) continue;
+    const cplx m = mult[i];
+    const cplx a = A[(size_t)k * w + c];
+    cplx& t = A[(size_t)i * w + c];
+    t.re -= m.re * a.re - m.im * a.im;
+    t.im -= m.re * a.im + m.im * a.re;
+  }
+}
+
+__global__ void copy_right_half(const cplx* __restrict__ A, cplx* out, int s) {
+  const size_t tot = (size_t)s * s;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int r = idx / s, c = idx % s;
+    out[idx] = A[(size_t)r * 2 * s + s + c];
+  }
+}
+
+// inverse of a row-major s x s matrix (given in the left half of Aug)
+static int gj_inverse(hipStream_t st, DevBuf& aug, int s, cplx* out, DevBuf& scratch) {
+  DP_TRY(scratch.reserve(s * sizeof(cplx) + 64));
+  cplx* mult = scratch.as<cplx>();
+  int* status = reinterpret_cast<int*>(mult + s);
+  DP_HIP(hipMemsetAsync(status, 0, sizeof(int), st));
+  cplx* A = aug.as<cplx>();
+  for (int k = 0; k < s; ++k) {
+    gj_pivot<<<1, 256, 0, st>>>(A, s, k, mult, status);
+    gj_update<<<grid1((size_t)s * (2 * s - k)), 256, 0, st>>>(A, s, k, mult, status);
+  }
+  copy_right_half<<<grid1((size_t)s * s), 256, 0, st>>>(A, out, s);
+  DP_HIP(hipGetLastError());
+  int h = 0;
+  DP_HIP(hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, st));
+  DP_HIP(hipStreamSynchronize(st));
+  if (h) {
+    set_error("singular dense block in the preconditioner setup (size %d)", s);
+    return DP_ESINGULAR;
+  }
+  return DP_OK;
+}
+
+// ------------------------------------------------------------------ dense products
+// C (M x N) = A (M x Kd) * B (Kd x N), all row-major (setup products).
+__global__ void dense_gemm(const cplx* __restrict__ A, const cplx* __restrict__ B, cplx* C, int M, int N, int Kd) {
+  const size_t tot = (size_t)M * N;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int r = idx / N, c = idx % N;
+    cplx acc = {0.0, 0.0};
+    for (int k = 0; k < Kd; ++k) cfma(acc, A[(size_t)r * Kd + k], B[(size_t)k * N + c]);
+    C[idx] = acc;
+  }
+}
+
+// U (s x K) and U^t (K x s): U(a, j) = exp(2 pi i (j - J)(a - (s-1)/2)/s)
+__global__ void partial_fourier(cplx* U, cplx* Ut, int s, int J) {
+  const int K = 2 * J + 1;
+  const size_t tot = (size_t)s * K;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int a = idx / K, jj = idx % K;
+    const int j = jj - J;
+    // phase/pi = 2 j (a - (s-1)/2)/s = j (2a - s + 1)/s, reduced exactly mod 2
+    long long num = (long long)j * (2LL * a - s + 1);
+    long long den = s;
+    long long r = num % (2 * den);
+    double sn, cs;
+    sincospi((double)r / (double)den, &sn, &cs);
+    U[idx] = {cs, sn};
+    Ut[(size_t)jj * s + a] = {cs, sn};
+  }
+}
+
+// alpha_s(b) = (1/s) sum_a l_b(xi_a), xi_a = (a - (s-1)/2)/(s/2), Lagrange basis
+// on first-kind Chebyshev points x_b = cos((2b+1) pi/(2 m_c)).
+__global__ void lagrange_mean(double* alpha, int s, int mc) {
+  const int b = threadIdx.x;
+  if (b >= mc) return;
+  const double xb = cospi((2.0 * b + 1.0) / (2.0 * mc));
+  double acc = 0.0;
+  for (int a = 0; a < s; ++a) {
+    const double xa = (a - 0.5 * (s - 1)) / (0.5 * s);
+    double l = 1.0;
+    for (int c = 0; c < mc; ++c) {
+      if (c == b) continue;
+      const double xc = cospi((2.0 * c + 1.0) / (2.0 * mc));
+      l *= (xa - xc) / (xb - xc);
+    }
+    acc += l;
+  }
+  alpha[b] = acc / s;
+}
+
+// ------------------------------------------------------------------ geometry
+// Trigonometric interpolant of the node positions at fractional node index u:
+// x(u) = sum_j x_j D(u - j), D = (1/n) sin(pi (u-j)) cot(pi (u-j)/n) (modes
+// |k| < n/2 plus the Nyquist cosine), and its derivative in the parameter.
+// out[p] = {x, y, dx, dy} (derivative w.r.t. node index, direction only used).
+__global__ __launch_bounds__(256) void trig_interp(const SrcRec* __restrict__ src, const double* __restrict__ u,
+                                                   double* out, int n) {
+  __shared__ double red[4][256];
+  const double up = u[blockIdx.x];
+  double ax = 0, ay = 0, dx = 0, dy = 0;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double w = up - j;
+    double sw, cw, sh, ch;
+    sincospi(w, &sw, &cw);
+    sincospi(w / n, &sh, &ch);
+    double D, Dp;
+    if (fabs(sh) < 1e-14) {
+      D = 1.0;
+      Dp = 0.0;
+    } else {
+      // D = sin(pi w) cot(pi w/n)/n ; dD/dw = [pi cos(pi w) cot(pi w/n) - (pi/n) sin(pi w)/sin^2(pi w/n)]/n
+      D = sw * ch / sh / n;
+      Dp = (kPi * cw * ch / sh - (kPi / n) * sw / (sh * sh)) / n;
+    }
+    const SrcRec s = src[j];
+    ax = fma(s.x, D, ax);
+    ay = fma(s.y, D, ay);
+    dx = fma(s.x, Dp, dx);
+    dy = fma(s.y, Dp, dy);
+  }
+  red[0][threadIdx.x] = ax;
+  red[1][threadIdx.x] = ay;
+  red[2][threadIdx.x] = dx;
+  red[3][threadIdx.x] = dy;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+struct EArgs {
+  const double* geo;     // per segment: (1 + m_c) points x {x, y, dx, dy}
+  const int* seg;        // per segment: off, len, J, cls
+  const double* alpha;   // per class m_c values (concatenated)
+  cplx* e;               // per ordered pair (i, j != i), row-major in i
+  int* kk;               // 2 per pair: k^i, k^j
+  int m, mc, n;
+  double omega, eta, ds;
+  int kind;
+};
+
+// CFIE kernel without the identity part at (x, nx) <- (y, ny).
+__device__ __forceinline__ cplx cfie_kernel(int kind, double omega, double eta, double x0, double x1, double nx0,
+                                            double nx1, double y0, double y1, double ny0, double ny1) {
+  const double d0 = x0 - y0, d1 = x1 - y1;
+  const double r = sqrt(d0 * d0 + d1 * d1);
+  const double r0 = d0 / r, r1 = d1 / r;
+  const H01 h = hankel01(omega * r);
+  if (kind == DP_SOFT) {
+    // (i omega/4) H1 ny.rhat + (eta/4) H0
+    const double a = 0.25 * omega * (ny0 * r0 + ny1 * r1);
+    return {-a * h.h1.im + 0.25 * eta * h.h0.re, a * h.h1.re + 0.25 * eta * h.h0.im};
+  }
+  const double nxr = nx0 * r0 + nx1 * r1, nyr = ny0 * r0 + ny1 * r1, nn = nx0 * ny0 + nx1 * ny1;
+  // hyp = (i omega/4) [ (omega H0 - 2 H1/r) nxr nyr + H1 nn / r ]
+  const cplx inner = {(omega * h.h0.re - 2.0 * h.h1.re / r) * nxr * nyr + h.h1.re * nn / r,
+                      (omega * h.h0.im - 2.0 * h.h1.im / r) * nxr * nyr + h.h1.im * nn / r};
+  const cplx hyp = {-0.25 * omega * inner.im, 0.25 * omega * inner.re};
+  // (i omega/4) H1 nxr + hyp/(i eta)
+  const cplx a = {-0.25 * omega * nxr * h.h1.im, 0.25 * omega * nxr * h.h1.re};
+  return {a.re + hyp.im / eta, a.im - hyp.re / eta};
+}
+
+// One block per ordered pair (i, j), i != j: directions and e_ij (eq. (14)).
+__global__ __launch_bounds__(128) void e_entries(EArgs a) {
+  __shared__ cplx red[128];
+  __shared__ int kij[2];
+  const int pair = blockIdx.x;
+  const int i = pair / (a.m - 1);
+  int j = pair % (a.m - 1);
+  if (j >= i) ++j;
+  const int mc = a.mc;
+  const double* gi = a.geo + (size_t)i * (1 + mc) * 4;
+  const double* gj = a.geo + (size_t)j * (1 + mc) * 4;
+  const int si = a.seg[4 * i + 1], Ji = a.seg[4 * i + 2], ci = a.seg[4 * i + 3];
+  const int sj = a.seg[4 * j + 1], Jj = a.seg[4 * j + 2], cj = a.seg[4 * j + 3];
+  const double hi = 2.0 * kPi / (si * a.ds), hj = 2.0 * kPi / (sj * a.ds);
+  if (threadIdx.x == 0) {
+    double a0 = gi[0] - gj[0], a1 = gi[1] - gj[1];
+    const double an = sqrt(a0 * a0 + a1 * a1);
+    a0 /= an;
+    a1 /= an;
+    const double ti_n = sqrt(gi[2] * gi[2] + gi[3] * gi[3]);
+    const double tj_n = sqrt(gj[2] * gj[2] + gj[3] * gj[3]);
+    const double ati = (a0 * gi[2] + a1 * gi[3]) / ti_n;
+    const double atj = (a0 * gj[2] + a1 * gj[3]) / tj_n;
+    double ki = round_half_away(a.omega * ati / hi);
+    double kj = round_half_away(-a.omega * atj / hj);
+    ki = fmin(fmax(ki, -Ji), Ji);
+    kj = fmin(fmax(kj, -Jj), Jj);
+    kij[0] = (int)ki;
+    kij[1] = (int)kj;
+  }
+  __syncthreads();
+  const int ki = kij[0], kj = kij[1];
+  const double* ali = a.alpha + (size_t)ci * mc;
+  const double* alj = a.alpha + (size_t)cj * mc;
+  cplx acc = {0.0, 0.0};
+  for (int t = threadIdx.x; t < mc * mc; t += 128) {
+    const int b = t / mc, bp = t % mc;
+    const double* X = gi + 4 * (1 + b);
+    const double* Y = gj + 4 * (1 + bp);
+    const double tx = sqrt(X[2] * X[2] + X[3] * X[3]), ty = sqrt(Y[2] * Y[2] + Y[3] * Y[3]);
+    // outward normal = (t_y, -t_x) for counter-clockwise nodes
+    cplx M = cfie_kernel(a.kind, a.omega, a.eta, X[0], X[1], X[3] / tx, -X[2] / tx, Y[0], Y[1], Y[3] / ty,
+                         -Y[2] / ty);
+    M.re *= a.ds;
+    M.im *= a.ds;
+    // chebyshev offsets from the centres (arclength): delta = xi * s ds/2
+    const double di = cospi((2.0 * b + 1.0) / (2.0 * mc)) * (0.5 * si * a.ds);
+    const double dj = cospi((2.0 * bp + 1.0) / (2.0 * mc)) * (0.5 * sj * a.ds);
+    double sn, cs;
+    dp_sincos(-(ki * hi * di + kj * hj * dj), sn, cs);
+    const cplx Mt = cmul(M, cplx{cs, sn});
+    const double wgt = ali[b] * alj[bp];
+    acc.re = fma(wgt, Mt.re, acc.re);
+    acc.im = fma(wgt, Mt.im, acc.im);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 64; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      red[threadIdx.x].re += red[threadIdx.x + st].re;
+      red[threadIdx.x].im += red[threadIdx.x + st].im;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.e[pair] = red[0];
+    a.kk[2 * pair] = ki;
+    a.kk[2 * pair + 1] = kj;
+  }
+}
+
+// ------------------------------------------------------------------ apply kernels
+struct SegGemm {
+  const int* segs;     // per segment: off, len, offK, cls
+  const cplx* const* A;  // per class: matrix pointer (row-major), chosen by `which`
+  const int* dims;     // per class: s, K
+  const cplx* X;       // input, column-major, leading dim ldx
+  const cplx* Z;       // mode 1: out = Z - A X (leading dim ldy)
+  cplx* Y;
+  int ldx, ldy, nrhs;
+  int mrows;           // 0: rows = s, 1: rows = K
+  int kin;             // 0: inner dim = s (X rows at off), 1: inner = K (X rows at offK)
+  int yoff;            // 0: Y rows at off, 1: at offK
+  int mode;            // 0: Y = A X, 1: Y = Z - A X
+};
+
+// Batched per-segment complex GEMM: grid (segment, row tile of 64, column
+// tile of 16); the A tile and the X tile of each 16-deep slice go through LDS.
+__global__ __launch_bounds__(256) void seg_gemm(SegGemm g) {
+  __shared__ cplx As[64][17];
+  __shared__ cplx Xs[16][16];
+  const int sg = blockIdx.x;
+  const int off = g.segs[4 * sg], offK = g.segs[4 * sg + 2], cls = g.segs[4 * sg + 3];
+  const int s = g.dims[2 * cls], K = g.dims[2 * cls + 1];
+  const int M = g.mrows ? K : s;
+  const int Kd = g.kin ? K : s;
+  const int r0 = blockIdx.y * 64;
+  if (r0 >= M) return;
+  const int c0 = blockIdx.z * 16;
+  const cplx* A = g.A[cls];
+  const int xo = g.kin ? offK : off;
+  const int yo = g.yoff ? offK : off;
+  const int tr = threadIdx.x / 16;   // 0..15 -> rows tr, tr+16, tr+32, tr+48
+  const int tc = threadIdx.x % 16;
+  cplx acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  for (int k0 = 0; k0 < Kd; k0 += 16) {
+    for (int t = threadIdx.x; t < 64 * 16; t += 256) {
+      const int rr = t / 16, kk = t % 16;
+      const int r = r0 + rr, k = k0 + kk;
+      As[rr][kk] = (r < M && k < Kd) ? A[(size_t)r * Kd + k] : cplx{0.0, 0.0};
+    }
+    {
+      const int kk = threadIdx.x / 16, cc = threadIdx.x % 16;
+      const int k = k0 + kk, c = c0 + cc;
+      Xs[kk][cc] = (k < Kd && c < g.nrhs) ? g.X[(size_t)c * g.ldx + xo + k] : cplx{0.0, 0.0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const cplx xv = Xs[kk][tc];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cfma(acc[q], As[tr + 16 * q][kk], xv);
+    }
+    __syncthreads();
+  }
+  const int c = c0 + tc;
+  if (c >= g.nrhs) return;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + tr + 16 * q;
+    if (r >= M) continue;
+    const size_t o = (size_t)c * g.ldy + yo + r;
+    if (g.mode == 1) {
+      const cplx z = g.Z[o];
+      g.Y[o] = {z.re - acc[q].re, z.im - acc[q].im};
+    } else {
+      g.Y[o] = acc[q];
+    }
+  }
+}
+
+// zp[k] = z[perm[k]] (column-major, leading dim NW)
+__global__ void gather_rows(const cplx* __restrict__ z, cplx* zp, const int* __restrict__ perm, int NW, int nrhs) {
+  const size_t tot = (size_t)NW * nrhs;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int k = idx % NW, c = idx / NW;
+    zp[idx] = z[(size_t)c * NW + perm[k]];
+  }
+}
+
+__global__ void scatter_rows(const cplx* __restrict__ up, cplx* u, const int* __restrict__ perm, int NW, int nrhs) {
+  const size_t tot = (size_t)NW * nrhs;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int b = idx % NW, c = idx / NW;
+    u[(size_t)c * NW + perm[b]] = up[idx];
+  }
+}
+
+// Level-scheduled sparse triangular solve in place on x (NW x nrhs,
+// column-major).  One block handles a group of columns; rows of one level
+// are independent and are processed together, levels in order.
+// lower: x_i -= sum_j L_ij x_j (unit diagonal); upper: x_i = (x_i - sum U_ij x_j)/U_ii.
+__global__ __launch_bounds__(1024) void level_solve(cplx* x, const int* __restrict__ P, const int* __restrict__ Jc,
+                                                    const cplx* __restrict__ V, const cplx* __restrict__ diag,
+                                                    const int* __restrict__ lptr, const int* __restrict__ lrows,
+                                                    int nlev, int NW, int nrhs, int cpb) {
+  const int c0 = blockIdx.x * cpb;
+  const int nc = min(cpb, nrhs - c0);
+  for (int l = 0; l < nlev; ++l) {
+    const int b = lptr[l], e = lptr[l + 1];
+    const int items = (e - b) * nc;
+    for (int t = threadIdx.x; t < items; t += blockDim.x) {
+      const int ri = lrows[b + t / nc];
+      const int c = c0 + t % nc;
+      cplx* xc = x + (size_t)c * NW;
+      cplx acc = xc[ri];
+      for (int q = P[ri]; q < P[ri + 1]; ++q) {
+        const cplx a = V[q], xv = xc[Jc[q]];
+        acc.re -= a.re * xv.re - a.im * xv.im;
+        acc.im -= a.re * xv.im + a.im * xv.re;
+      }
+      if (diag) {
+        const cplx d = diag[ri];
+        const double den = d.re * d.re + d.im * d.im;
+        acc = {(acc.re * d.re + acc.im * d.im) / den, (acc.im * d.re - acc.re * d.im) / den};
+      }
+      xc[ri] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ host: setup
+static void segment_boundary(const dp_problem* p, const dp_precond_opts* o, std::vector<int>& off,
+                             std::vector<int>& len) {
+  const int n = (int)p->n;
+  const double L = p->L, ds = L / n, lam = 2.0 * kPi / p->omega;
+  int m0 = 1 << (int)std::lround(std::log2(std::sqrt(L / lam)));
+  m0 = std::max(1, std::min(m0, n));
+  while (n % m0) m0 /= 2;
+  std::vector<std::pair<int, int>> st;
+  const int s0 = n / m0;
+  for (int t = m0 - 1; t >= 0; --t) st.push_back({t * s0, s0});
+  while (!st.empty()) {
+    auto [o0, s] = st.back();
+    st.pop_back();
+    double cmax = 0;
+    for (int a = o0; a < o0 + s; ++a) cmax = std::max(cmax, std::fabs(p->hkap[a]));
+    const double length = s * ds;
+    if (cmax == 0 || length <= std::sqrt(L * lam / cmax) || length <= o->m_ell * lam || s <= o->min_pts || s % 2) {
+      off.push_back(o0);
+      len.push_back(s);
+      continue;
+    }
+    st.push_back({o0 + s / 2, s / 2});
+    st.push_back({o0, s / 2});
+  }
+}
+
+static void threshold_T(const std::vector<cplx>& T, int K, double t_keep, std::vector<cplx>& Tt) {
+  Tt = T;
+  if (t_keep <= 0) return;
+  const int k = (int)std::min<long long>((long long)K * K, std::llround(t_keep * K));
+  std::vector<double> mag(T.size());
+  for (size_t q = 0; q < T.size(); ++q) mag[q] = std::hypot(T[q].re, T[q].im);
+  std::vector<double> srt(mag);
+  std::nth_element(srt.begin(), srt.begin() + (k - 1), srt.end(), std::greater<double>());
+  const double tau = srt[k - 1];
+  for (int r = 0; r < K; ++r)
+    for (int c = 0; c < K; ++c) {
+      const size_t q = (size_t)r * K + c;
+      const bool keep = mag[q] >= tau * (1 - 1e-8) || c == K - 1 - r;
+      if (!keep) Tt[q] = {0.0, 0.0};
+    }
+}
+
+int precond_build(dp_problem* p, const dp_precond_opts* o) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = p->ctx->stream;
+  if (p->pc) {
+    precond_destroy(p->pc);
+    p->pc = nullptr;
+  }
+  Precond* P = new Precond();
+  auto fail = [&](int rc) {
+    precond_destroy(P);
+    return rc;
+  };
+  const int n = (int)p->n;
+  const double L = p->L, ds = L / n, omega = p->omega;
+  P->m_c = o->m_c;
+  segment_boundary(p, o, P->off, P->len);
+  P->m = (int)P->off.size();
+  const int m = P->m;
+  if (m < 2) {
+    set_error("dp_precond_build: fewer than two segments");
+    return fail(DP_EINVAL);
+  }
+  std::map<int, int> cls_of;
+  for (int s : P->len) cls_of[s] = 0;
+  for (auto& kv : cls_of) {
+    kv.second = (int)P->classes.size();
+    SizeClass c;
+    c.s = kv.first;
+    c.J = (int)std::ceil(c.s * omega * ds / (2.0 * kPi) - 1e-9);
+    c.K = 2 * c.J + 1;
+    P->classes.push_back(std::move(c));
+  }
+  P->offK.assign(m + 1, 0);
+  P->cls.resize(m);
+  P->J.resize(m);
+  for (int i = 0; i < m; ++i) {
+    P->cls[i] = cls_of[P->len[i]];
+    P->J[i] = P->classes[P->cls[i]].J;
+    P->offK[i + 1] = P->offK[i] + P->classes[P->cls[i]].K;
+  }
+  P->NW = P->offK[m];
+  const int mc = o->m_c;
+
+  // ---- size classes: B^{-1}, U, S, T, floor(T), alpha
+  DevBuf row, aug, scratch, X, S;
+  std::vector<double> alpha_all;
+  DevBuf d_alpha;
+  DP_TRY(d_alpha.reserve(P->classes.size() * mc * sizeof(double)));
+  for (size_t ci = 0; ci < P->classes.size(); ++ci) {
+    SizeClass& c = P->classes[ci];
+    const int s = c.s, K = c.K;
+    int rc;
+    if ((rc = row.reserve(s * sizeof(cplx))) || (rc = aug.reserve((size_t)s * 2 * s * sizeof(cplx))) ||
+        (rc = c.Binv.reserve((size_t)s * s * sizeof(cplx))) || (rc = c.U.reserve((size_t)s * K * sizeof(cplx))) ||
+        (rc = c.Ut.reserve((size_t)s * K * sizeof(cplx))) || (rc = c.Tt.reserve((size_t)K * K * sizeof(cplx))) ||
+        (rc = X.reserve((size_t)s * K * sizeof(cplx))) || (rc = S.reserve((size_t)K * 2 * K * sizeof(cplx))))
+      return fail(rc);
+    flat_row<<<(s + 255) / 256, 256, 0, st>>>(p->C.as<double>(), row.as<cplx>(), s, n, L, omega, p->eta, p->kind);
+    toeplitz_aug<<<grid1((size_t)s * 2 * s), 256, 0, st>>>(row.as<cplx>(), aug.as<cplx>(), s);
+    if ((rc = gj_inverse(st, aug, s, c.Binv.as<cplx>(), scratch))) return fail(rc);
+    partial_fourier<<<grid1((size_t)s * K), 256, 0, st>>>(c.U.as<cplx>(), c.Ut.as<cplx>(), s, c.J);
+    dense_gemm<<<grid1((size_t)s * K), 256, 0, st>>>(c.Binv.as<cplx>(), c.U.as<cplx>(), X.as<cplx>(), s, K, s);
+    // S = U^t X, written as the left half of an augmented K x 2K matrix
+    dense_gemm<<<grid1((size_t)K * K), 256, 0, st>>>(c.Ut.as<cplx>(), X.as<cplx>(), c.Tt.as<cplx>(), K, K, s);
+    {
+      // build [S | I]
+      std::vector<cplx> Sh((size_t)K * K);
+      DP_HIP(hipMemcpyAsync(Sh.data(), c.Tt.p, Sh.size() * sizeof(cplx), hipMemcpyDeviceToHost, st));
+      DP_HIP(hipStreamSynchronize(st));
+      std::vector<cplx> Ah((size_t)K * 2 * K, cplx{0.0, 0.0});
+      for (int r = 0; r < K; ++r) {
+        for (int q = 0; q < K; ++q) Ah[(size_t)r * 2 * K + q] = Sh[(size_t)r * K + q];
+        Ah[(size_t)r * 2 * K + K + r] = {1.0, 0.0};
+      }
+      DP_HIP(hipMemcpyAsync(S.p, Ah.data(), Ah.size() * sizeof(cplx), hipMemcpyHostToDevice, st));
+      DP_HIP(hipStreamSynchronize(st));
+    }
+    if ((rc = gj_inverse(st, S, K, c.Tt.as<cplx>(), scratch))) return fail(rc);
+    c.T.resize((size_t)K * K);
+    DP_HIP(hipMemcpyAsync(c.T.data(), c.Tt.p, c.T.size() * sizeof(cplx), hipMemcpyDeviceToHost, st));
+    DP_HIP(hipStreamSynchronize(st));
+    std::vector<cplx> Tt;
+    threshold_T(c.T, K, o->t_keep, Tt);
+    DP_HIP(hipMemcpyAsync(c.Tt.p, Tt.data(), Tt.size() * sizeof(cplx), hipMemcpyHostToDevice, st));
+    lagrange_mean<<<1, 64, 0, st>>>(d_alpha.as<double>() + ci * mc, s, mc);
+  }
+  DP_HIP(hipGetLastError());
+
+  // ---- segment geometry: centre + m_c Chebyshev points, by trigonometric interpolation
+  const int npts = m * (1 + mc);
+  std::vector<double> uh(npts);
+  for (int i = 0; i < m; ++i) {
+    const double uc = P->off[i] + 0.5 * (P->len[i] - 1);
+    uh[(size_t)i * (1 + mc)] = uc;
+    for (int b = 0; b < mc; ++b) {
+      const double xi = std::cos((2.0 * b + 1.0) * kPi / (2.0 * mc));
+      double u = uc + xi * 0.5 * P->len[i];
+      if (u < 0) u += n;
+      if (u >= n) u -= n;
+      uh[(size_t)i * (1 + mc) + 1 + b] = u;
+    }
+  }
+  DevBuf d_u, d_geo, d_seg, d_e, d_kk;
+  std::vector<int> seg4(4 * m);
+  for (int i = 0; i < m; ++i) {
+    seg4[4 * i] = P->off[i];
+    seg4[4 * i + 1] = P->len[i];
+    seg4[4 * i + 2] = P->J[i];
+    seg4[4 * i + 3] = P->cls[i];
+  }
+  const size_t npair = (size_t)m * (m - 1);
+  int rc;
+  if ((rc = upload(d_u, uh, st)) || (rc = d_geo.reserve((size_t)npts * 4 * sizeof(double))) ||
+      (rc = upload(d_seg, seg4, st)) || (rc = d_e.reserve(npair * sizeof(cplx))) ||
+      (rc = d_kk.reserve(npair * 2 * sizeof(int))))
+    return fail(rc);
+  trig_interp<<<npts, 256, 0, st>>>(p->src.as<SrcRec>(), d_u.as<double>(), d_geo.as<double>(), n);
+  EArgs ea;
+  ea.geo = d_geo.as<double>();
+  ea.seg = d_seg.as<int>();
+  ea.alpha = d_alpha.as<double>();
+  ea.e = d_e.as<cplx>();
+  ea.kk = d_kk.as<int>();
+  ea.m = m;
+  ea.mc = mc;
+  ea.n = n;
+  ea.omega = omega;
+  ea.eta = p->eta;
+  ea.ds = ds;
+  ea.kind = p->kind;
+  e_entries<<<(unsigned)npair, 128, 0, st>>>(ea);
+  DP_HIP(hipGetLastError());
+  P->eval.resize(npair);
+  std::vector<int> kk(npair * 2);
+  DP_HIP(hipMemcpyAsync(P->eval.data(), d_e.p, npair * sizeof(cplx), hipMemcpyDeviceToHost, st));
+  DP_HIP(hipMemcpyAsync(kk.data(), d_kk.p, npair * 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  DP_HIP(hipStreamSynchronize(st));
+  P->eidx.resize(npair * 4);
+  for (size_t q = 0; q < npair; ++q) {
+    const int i = (int)(q / (m - 1));
+    int j = (int)(q % (m - 1));
+    if (j >= i) ++j;
+    P->eidx[4 * q] = i;
+    P->eidx[4 * q + 1] = j;
+    P->eidx[4 * q + 2] = kk[2 * q];
+    P->eidx[4 * q + 3] = kk[2 * q + 1];
+  }
+
+  // ---- floor(W) = E + antidiag(T) in CSC, sparse LU on the host
+  const int NW = P->NW;
+  std::vector<std::vector<std::pair<int, zc>>> cols(NW);
+  for (int i = 0; i < m; ++i) {
+    const SizeClass& c = P->classes[P->cls[i]];
+    for (int r = 0; r < c.K; ++r) {
+      const cplx v = c.T[(size_t)r * c.K + (c.K - 1 - r)];
+      cols[P->offK[i] + c.K - 1 - r].push_back({P->offK[i] + r, zc(v.re, v.im)});
+    }
+  }
+  for (size_t q = 0; q < npair; ++q) {
+    const int i = P->eidx[4 * q], j = P->eidx[4 * q + 1];
+    const int row_ = P->offK[i] + P->eidx[4 * q + 2] + P->J[i];
+    const int col_ = P->offK[j] + P->eidx[4 * q + 3] + P->J[j];
+    cols[col_].push_back({row_, zc(P->eval[q].re, P->eval[q].im)});
+  }
+  std::vector<int> cp(NW + 1, 0), ri;
+  std::vector<zc> vx;
+  for (int c = 0; c < NW; ++c) {
+    auto& v = cols[c];
+    std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    // merge duplicates (an E entry landing on an antidiagonal position)
+    for (size_t q = 0; q < v.size(); ++q) {
+      if (!ri.empty() && (int)ri.size() > cp[c] && ri.back() == v[q].first) {
+        vx.back() += v[q].second;
+      } else {
+        ri.push_back(v[q].first);
+        vx.push_back(v[q].second);
+      }
+    }
+    cp[c + 1] = (int)ri.size();
+  }
+  P->nnzW = (int64_t)ri.size();
+  if ((rc = sparse_lu_factor(NW, cp, ri, vx, P->lu))) return fail(rc);
+  auto to_c = [](const std::vector<zc>& a) {
+    std::vector<cplx> r(a.size());
+    for (size_t q = 0; q < a.size(); ++q) r[q] = {a[q].real(), a[q].imag()};
+    return r;
+  };
+  const SparseLU& lu = P->lu;
+  if ((rc = upload(P->Lp, lu.Lp, st)) || (rc = upload(P->Lj, lu.Lj, st)) || (rc = upload(P->Lx, to_c(lu.Lx), st)) ||
+      (rc = upload(P->Up, lu.Up, st)) || (rc = upload(P->Uj, lu.Uj, st)) || (rc = upload(P->Ux, to_c(lu.Ux), st)) ||
+      (rc = upload(P->Ud, to_c(lu.Ud), st)) || (rc = upload(P->lvlL, lu.lvlL_ptr, st)) ||
+      (rc = upload(P->lvlLr, lu.lvlL_rows, st)) || (rc = upload(P->lvlU, lu.lvlU_ptr, st)) ||
+      (rc = upload(P->lvlUr, lu.lvlU_rows, st)) || (rc = upload(P->pin, lu.perm_in, st)) ||
+      (rc = upload(P->pout, lu.perm_out, st)))
+    return fail(rc);
+  P->nlevL = (int)lu.lvlL_ptr.size() - 1;
+  P->nlevU = (int)lu.lvlU_ptr.size() - 1;
+
+  // ---- apply tables
+  std::vector<int> segs(4 * m), dims(2 * P->classes.size());
+  std::vector<const cplx*> ptrs(4 * P->classes.size());
+  for (int i = 0; i < m; ++i) {
+    segs[4 * i] = P->off[i];
+    segs[4 * i + 1] = P->len[i];
+    segs[4 * i + 2] = P->offK[i];
+    segs[4 * i + 3] = P->cls[i];
+  }
+  const size_t nc = P->classes.size();
+  for (size_t c = 0; c < nc; ++c) {
+    dims[2 * c] = P->classes[c].s;
+    dims[2 * c + 1] = P->classes[c].K;
+    ptrs[0 * nc + c] = P->classes[c].Binv.as<cplx>();
+    ptrs[1 * nc + c] = P->classes[c].U.as<cplx>();
+    ptrs[2 * nc + c] = P->classes[c].Ut.as<cplx>();
+    ptrs[3 * nc + c] = P->classes[c].Tt.as<cplx>();
+  }
+  if ((rc = upload(P->d_segs, segs, st)) || (rc = upload(P->d_dims, dims, st)) ||
+      (rc = upload(P->d_ptrs, ptrs, st)))
+    return fail(rc);
+  DP_HIP(hipStreamSynchronize(st));
+  row.release();
+  aug.release();
+  scratch.release();
+  X.release();
+  S.release();
+  d_alpha.release();
+  d_u.release();
+  d_geo.release();
+  d_seg.release();
+  d_e.release();
+  d_kk.release();
+  P->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  p->pc = P;
+  return DP_OK;
+}
+
+// ------------------------------------------------------------------ host: apply
+static int run_seg_gemm(dp_problem* p, int which, int mrows, int kin, int yoff, int mode, const cplx* X, int ldx,
+                        const cplx* Z, cplx* Y, int ldy, int nrhs) {
+  Precond* P = p->pc;
+  const size_t nc = P->classes.size();
+  int maxM = 0;
+  for (auto& c : P->classes) maxM = std::max(maxM, mrows ? c.K : c.s);
+  SegGemm g;
+  g.segs = P->d_segs.as<int>();
+  g.A = P->d_ptrs.as<const cplx*>() + which * nc;
+  g.dims = P->d_dims.as<int>();
+  g.X = X;
+  g.Z = Z;
+  g.Y = Y;
+  g.ldx = ldx;
+  g.ldy = ldy;
+  g.nrhs = nrhs;
+  g.mrows = mrows;
+  g.kin = kin;
+  g.yoff = yoff;
+  g.mode = mode;
+  dim3 grid(P->m, (maxM + 63) / 64, (nrhs + 15) / 16);
+  seg_gemm<<<grid, 256, 0, p->ctx->stream>>>(g);
+  DP_HIP(hipGetLastError());
+  return DP_OK;
+}
+
+int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
+  Precond* P = p->pc;
+  hipStream_t st = p->ctx->stream;
+  const int n = (int)p->n, NW = P->NW;
+  DP_TRY(P->wy.reserve((size_t)n * nrhs * sizeof(cplx)));
+  DP_TRY(P->wn.reserve((size_t)n * nrhs * sizeof(cplx)));
+  DP_TRY(P->wg.reserve((size_t)NW * nrhs * sizeof(cplx)));
+  DP_TRY(P->wz.reserve((size_t)NW * nrhs * sizeof(cplx)));
+  DP_TRY(P->wu.reserve((size_t)NW * nrhs * sizeof(cplx)));
+  DP_TRY(P->wt.reserve((size_t)NW * nrhs * sizeof(cplx)));
+  cplx *y = P->wy.as<cplx>(), *g = P->wg.as<cplx>(), *z = P->wz.as<cplx>(), *u = P->wu.as<cplx>(),
+       *t = P->wt.as<cplx>(), *un = P->wn.as<cplx>();
+  enum { BINV = 0, UU = 1, UT = 2, TT = 3 };
+  // y = B^{-1} v
+  DP_TRY(run_seg_gemm(p, BINV, 0, 0, 0, 0, v, n, nullptr, y, n, nrhs));
+  // g = U^t y
+  DP_TRY(run_seg_gemm(p, UT, 1, 0, 1, 0, y, n, nullptr, g, NW, nrhs));
+  // z = floor(T) g
+  DP_TRY(run_seg_gemm(p, TT, 1, 1, 1, 0, g, NW, nullptr, z, NW, nrhs));
+  // u = floor(W)^{-1} z
+  gather_rows<<<grid1((size_t)NW * nrhs), 256, 0, st>>>(z, t, P->pin.as<int>(), NW, nrhs);
+  const int cpb = nrhs < 16 ? nrhs : 16;
+  const int nb = (nrhs + cpb - 1) / cpb;
+  level_solve<<<nb, 1024, 0, st>>>(t, P->Lp.as<int>(), P->Lj.as<int>(), P->Lx.as<cplx>(), nullptr,
+                                   P->lvlL.as<int>(), P->lvlLr.as<int>(), P->nlevL, NW, nrhs, cpb);
+  level_solve<<<nb, 1024, 0, st>>>(t, P->Up.as<int>(), P->Uj.as<int>(), P->Ux.as<cplx>(), P->Ud.as<cplx>(),
+                                   P->lvlU.as<int>(), P->lvlUr.as<int>(), P->nlevU, NW, nrhs, cpb);
+  scatter_rows<<<grid1((size_t)NW * nrhs), 256, 0, st>>>(t, u, P->pout.as<int>(), NW, nrhs);
+  // h = z - floor(T) u  (into g)
+  DP_TRY(run_seg_gemm(p, TT, 1, 1, 1, 1, u, NW, z, g, NW, nrhs));
+  // un = U h
+  DP_TRY(run_seg_gemm(p, UU, 0, 1, 0, 0, g, NW, nullptr, un, n, nrhs));
+  // q = y - B^{-1} un
+  DP_TRY(run_seg_gemm(p, BINV, 0, 0, 0, 1, un, n, y, q, n, nrhs));
+  DP_HIP(hipGetLastError());
+  return DP_OK;
+}
+
+void precond_destroy(Precond* P) {
+  if (!P) return;
+  for (auto& c : P->classes) {
+    c.Binv.release();
+    c.U.release();
+    c.Ut.release();
+    c.Tt.release();
+    c.alpha.release();
+  }
+  for (DevBuf* b : {&P->d_segs, &P->d_ptrs, &P->d_dims, &P->Lp, &P->Lj, &P->Lx, &P->Up, &P->Uj, &P->Ux, &P->Ud,
+                    &P->lvlL, &P->lvlLr, &P->lvlU, &P->lvlUr, &P->pin, &P->pout, &P->wy, &P->wg, &P->wz, &P->wu,
+                    &P->wt, &P->wn})
+    b->release();
+  delete P;
+}
+
+int precond_info(dp_problem* p, dp_precond_info* info) {
+  const Precond* P = p->pc;
+  info->m = P->m;
+  info->n_classes = (int64_t)P->classes.size();
+  info->NW = P->NW;
+  info->nnzE = (int64_t)P->m * (P->m - 1);
+  info->nnzW = P->nnzW;
+  info->nnzLU = (int64_t)P->lu.Lx.size() + (int64_t)P->lu.Ux.size() + P->NW;
+  info->levels = P->nlevL + P->nlevU;
+  info->t_setup = P->t_setup;
+  return DP_OK;
+}
+
+int precond_export(dp_problem* p, int64_t* seg_off, int64_t* seg_len, int64_t* e_idx, double* e_val) {
+  const Precond* P = p->pc;
+  for (int i = 0; i < P->m; ++i) {
+    if (seg_off) seg_off[i] = P->off[i];
+    if (seg_len) seg_len[i] = P->len[i];
+  }
+  const size_t npair = (size_t)P->m * (P->m - 1);
+  for (size_t q = 0; q < npair; ++q) {
+    if (e_idx)
+      for (int t = 0; t < 4; ++t) e_idx[4 * q + t] = P->eidx[4 * q + t];
+    if (e_val) {
+      e_val[2 * q] = P->eval[q].re;
+      e_val[2 * q + 1] = P->eval[q].im;
+    }
+  }
+  return DP_OK;
+}
+
+}  // namespace dp

@@ -1,0 +1,24 @@
+// Host sparse LU of floor(W) with level schedules for the device solves.
+#pragma once
+
+#include <complex>
+#include <vector>
+
+namespace dp {
+
+struct SparseLU {
+  int n = 0;
+  // W u = z  <=>  zp[k] = z[perm_in[k]];  L y = zp;  U u' = y;  u[perm_out[b]] = u'[b]
+  std::vector<int> perm_in, perm_out;
+  std::vector<int> Lp, Lj;  // CSR, strictly lower part of the unit lower factor
+  std::vector<std::complex<double>> Lx;
+  std::vector<int> Up, Uj;  // CSR, strictly upper part of U
+  std::vector<std::complex<double>> Ux, Ud;  // Ud: diagonal of U
+  std::vector<int> lvlL_ptr, lvlL_rows, lvlU_ptr, lvlU_rows;
+};
+
+// W given in CSC (colptr, rowind, values), n x n.
+int sparse_lu_factor(int n, const std::vector<int>& colptr, const std::vector<int>& rowind,
+                     const std::vector<std::complex<double>>& val, SparseLU& out);
+
+}  // namespace dp

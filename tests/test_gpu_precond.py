@@ -1,0 +1,84 @@
+"""GPU parity of the directional preconditioner (Sec. 2) against the dense
+oracle reference: integer structure bit-exact, e_ij and the apply in FP64."""
+import numpy as np
+import pytest
+
+import paper_1408_1578_amd as dp
+from oracle import nystrom as ny, precond as pc
+from oracle.gmres import gmres
+from synth import config_boundary, random_density, sample_boundary, omega_for_ppw
+from tests.gpu_util import empty, problem, relerr, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("disk", 1024, 0), ("disk", 1024, 1), ("star", 4096, 0), ("kite", 4096, 1), ("kite", 2048, 0)]
+
+
+def _setup(cfg, n, kind):
+    b, om, eta, _ = config_boundary(cfg, n)
+    P = pc.build(b, om, eta, kind)
+    p = problem(b, om, eta, kind)
+    dp.dp_precond_build(p)
+    return b, om, eta, P, p
+
+
+@pytest.mark.parametrize("cfg,n,kind", CASES)
+def test_structure_and_entries(cfg, n, kind):
+    b, om, eta, P, p = _setup(cfg, n, kind)
+    off, ln, eidx, ev = dp.dp_precond_export(p)
+    assert [tuple(x) for x in zip(off, ln)] == [tuple(s) for s in P.segs]
+    info = dp.dp_precond_get_info(p)
+    m = len(P.segs)
+    assert info["m"] == m and info["NW"] == P.NW and info["nnzE"] == m * (m - 1)
+    ref = {(i, j): (ki, kj, e) for i, j, ki, kj, e in P.E}
+    evals = np.array([ref[(int(i), int(j))][2] for i, j, _, _ in eidx])
+    for (i, j, ki, kj) in eidx:
+        assert (ki, kj) == ref[(int(i), int(j))][:2]          # rounded directions: bit-exact
+    assert np.max(np.abs(ev - evals)) < 1e-11 * np.max(np.abs(evals))
+    assert info["nnzW"] == np.count_nonzero(P.W)
+
+
+@pytest.mark.parametrize("cfg,n,kind", CASES)
+def test_apply_parity(cfg, n, kind):
+    b, om, eta, P, p = _setup(cfg, n, kind)
+    for nrhs in (1, 5, 20):
+        v = random_density(b.n, nrhs, seed=nrhs)
+        z = empty(b.n, nrhs)
+        dp.dp_precond_apply(p, to_dev(v), z)
+        assert relerr(to_host(z), pc.apply(P, v)) < 1e-10
+
+
+@pytest.mark.parametrize("cfg,n,kind", [("star", 4096, 0), ("kite", 4096, 1)])
+def test_preconditioned_solve(cfg, n, kind):
+    b, om, eta, P, p = _setup(cfg, n, kind)
+    A = ny.cfie_matrix(b, om, eta, kind)
+    F = ny.plane_wave_rhs(b, om, np.array([0.0, 1.0, 2.5]), kind)
+    Q = np.linalg.solve(A, F)
+    q = empty(b.n, 3)
+    info_p = dp.dp_solve(p, to_dev(F), q, tol=1e-8, use_precond=True)
+    assert info_p["converged"] and relerr(to_host(q), Q) < 1e-6
+    q2 = empty(b.n, 3)
+    info_n = dp.dp_solve(p, to_dev(F), q2, tol=1e-8, use_precond=False)
+    assert info_p["iters_max"] < info_n["iters_max"]
+    _, its_p, _ = gmres(A, F[:, 0], tol=1e-8, M=lambda v: pc.apply(P, v))
+    assert abs(int(info_p["iters"][0]) - its_p) <= 2
+
+
+def test_apply_before_build_is_an_error():
+    b, om, eta, kind = config_boundary("disk", 1024)
+    p = problem(b, om, eta, kind)
+    with pytest.raises(dp.DpError) as e:
+        dp.dp_precond_apply(p, empty(b.n, 1), empty(b.n, 1))
+    assert e.value.code == dp.DP_ESTATE
+
+
+def test_full_size_kite_hard_apply():
+    # the 32768-point sound-hard kite: apply parity against the dense reference
+    b, om, eta, kind = config_boundary("kite", 32768)
+    P = pc.build(b, om, eta, kind)
+    p = problem(b, om, eta, kind)
+    dp.dp_precond_build(p)
+    v = random_density(b.n, 2, seed=9)
+    z = empty(b.n, 2)
+    dp.dp_precond_apply(p, to_dev(v), z)
+    assert relerr(to_host(z), pc.apply(P, v)) < 1e-10
