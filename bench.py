@@ -1,0 +1,206 @@
+"""Benchmark: directional-preconditioned CFIE solves on one MI355X.
+
+Workload (one step): the sound-hard kite x = cos t + 0.65 cos 2t - 0.65,
+y = 1.5 sin t, n = 32768 arclength-equispaced nodes at 10 points per
+wavelength (omega = 2208.1), eta = omega, 64 incident plane waves at angles
+2 pi k/64, all solved to relative residual 1e-8 by right-preconditioned
+GMRES(80) in FP64.  A step = preconditioner setup + plane-wave data +
+the batched solve (the problem's geometry and Kress table are resident on the
+device before the timed region).  value = solved right-hand sides per second.
+
+Prints one JSON line (metric, value, roofline of the pair-sweep kernel from
+HIP events recorded by the library around each of its launches, and the CPU
+oracle's extrapolated rate on a bounded sample).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CFIE solves/s at n=32768 to 1e-8 residual (mixed vs FP64); p50/p99 latency"
+PEAK_FP64_VALU = 78.6  # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+
+# Algorithmic FP64 flops of one ordered pair in the sound-hard sweep (far-field
+# evaluation path; an FMA counts 2): geometry 5, 1/r 8, r and z 2, H0/H1 142,
+# weights 2, nu_i.rhat 4, S / D' / G assembly 27; plus 2 complex MACs (16 flops)
+# per right-hand side.
+FLOPS_PAIR_HARD = 190
+FLOPS_PAIR_PER_RHS_HARD = 16
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(b, om, eta, nrhs, budget_s=25.0):
+    """The oracle (dense Nystrom assembly + LU) timed on the host, on a sample.
+
+    Sample: (a) oracle S and D' rows for 96 target rows at the full n (pair
+    evaluations scale with n^2 -> x n/96); (b) the oracle's dense hard matrix at
+    n0 = 2048 on the same curve and its LU + 64 triangular solves (cubic parts
+    scale with (n/n0)^3).  The extrapolated time of one 64-RHS dense solve at n
+    gives solves/s = nrhs / T.
+    """
+    import oracle.nystrom as ny
+    from synth import sample_boundary, omega_for_ppw
+    import scipy.linalg as sla
+
+    n = b.n
+    t0 = time.perf_counter()
+    rows = np.arange(0, n, n // 96)[:96]
+    ny.layer_rows(b, om, rows)
+    t_rows = time.perf_counter() - t0
+    t_pairs = t_rows * n / len(rows)
+    n0 = 2048
+    b0 = sample_boundary(b.name, n0)
+    om0 = omega_for_ppw(n0, b0.L, 10.0)
+    t1 = time.perf_counter()
+    lay = ny.layer_rows(b0, om0)
+    t_pairs0 = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    A0 = ny.hard_matrix(b0, om0, om0)                  # includes the pair work again
+    t_asm0 = time.perf_counter() - t1
+    t_cubic_asm0 = max(t_asm0 - t_pairs0, 0.0)         # dense products of Maue's identity
+    F0 = ny.plane_wave_rhs(b0, om0, 2 * np.pi * np.arange(nrhs) / nrhs, 1)
+    t1 = time.perf_counter()
+    lu = sla.lu_factor(A0)
+    sla.lu_solve(lu, F0)
+    t_lu0 = time.perf_counter() - t1
+    scale3 = (n / n0) ** 3
+    T = t_pairs + (t_cubic_asm0 + t_lu0) * scale3
+    used = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": nrhs / T,
+        "unit": "solves/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"extrapolated: oracle pair work on {len(rows)} of {n} rows (x{n // len(rows)}), "
+                   f"dense Maue assembly + LU + {nrhs} solves at n={n0} (x(n/{n0})^3); "
+                   f"{used:.1f} s of CPU wall time, projected {T:.0f} s per {nrhs}-RHS solve"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precond", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU row split is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1408_1578_amd as dp
+    from synth import config_boundary, plane_wave_angles
+
+    b, om, eta, kind = config_boundary("kite", args.n)
+    nrhs = args.nrhs
+    ctx = dp.Context(0)
+    prob = dp.Problem.from_boundary(ctx, b, om, eta, kind)
+    angles = plane_wave_angles(nrhs)
+    f = torch.empty((nrhs, b.n), dtype=torch.complex128, device="cuda:0")
+    q = torch.empty_like(f)
+    use_pc = not args.no_precond
+
+    def step():
+        t0 = time.perf_counter()
+        if use_pc:
+            dp.dp_precond_build(prob)
+        dp.dp_rhs_plane_wave(prob, angles, f)
+        info = dp.dp_solve(prob, f, q, tol=1e-8, restart=80, use_precond=use_pc)
+        return info, time.perf_counter() - t0
+
+    for w in range(args.warmup):
+        info, dt = step()
+        log(f"warmup {w}: {dt:.3f} s iters={info['iters_max']} relres={info['relres_max']:.2e}")
+    torch.cuda.synchronize()
+    lat, infos = [], []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        info, dt = step()
+        lat.append(dt)
+        infos.append(info)
+        log(f"step {s}: {dt:.3f} s iters={info['iters_max']} relres={info['relres_max']:.2e} "
+            f"sweep {info['t_sweep'] / max(info['sweep_launches'], 1) * 1e3:.2f} ms x {info['sweep_launches']}")
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    ok = all(i["converged"] and i["relres_max"] <= 1e-8 for i in infos)
+
+    launches = sum(i["sweep_launches"] for i in infos)
+    t_sweep = sum(i["t_sweep"] for i in infos)
+    avg = t_sweep / max(launches, 1)
+    nrp = 1
+    while nrp < nrhs and nrp < 64:
+        nrp *= 2
+    pairs = b.n * (b.n - 1)
+    flops = pairs * (FLOPS_PAIR_HARD + FLOPS_PAIR_PER_RHS_HARD * nrp)
+    achieved = flops / avg / 1e12 if avg > 0 else 0.0
+    pinfo = dp.dp_precond_get_info(prob) if use_pc else {}
+    lat_ms = np.array(lat) * 1e3
+
+    out = {
+        "metric": METRIC,
+        "value": nrhs * args.steps / T,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"sound-hard kite, n={b.n}, 10 points/wavelength (omega={om:.1f}), eta=omega, "
+                        f"{nrhs} plane waves at 2*pi*k/{nrhs}, directional preconditioner + GMRES(80) "
+                        f"to 1e-8, FP64",
+            "n": b.n, "nrhs": nrhs, "omega": om, "tol": 1e-8, "restart": 80,
+            "precision": "fp64", "precond": use_pc,
+        },
+        "converged": ok,
+        "iterations": int(max(i["iters_max"] for i in infos)),
+        "relres_max": float(max(i["relres_max"] for i in infos)),
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "phase_s_per_step": {
+            "matvec": float(np.mean([i["t_matvec"] for i in infos])),
+            "precond_apply": float(np.mean([i["t_apply"] for i in infos])),
+            "krylov": float(np.mean([i["t_krylov"] for i in infos])),
+            "precond_setup": float(pinfo.get("t_setup", 0.0)),
+        },
+        "roofline": {
+            "kernel": "sweep_shared<hard, 16 rhs/wave, 4 waves>",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_VALU,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VALU,
+            "traffic": None,
+            "launch_ms": avg * 1e3,
+            "launches": launches,
+            "flops_per_launch": flops,
+        },
+    }
+    if pinfo:
+        out["precond"] = {k: pinfo[k] for k in ("m", "NW", "nnzW", "nnzLU", "levels")}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, bounded sample) ...")
+        out["cpu_baseline"] = cpu_baseline(b, om, eta, nrhs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

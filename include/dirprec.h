@@ -152,6 +152,8 @@ typedef struct {
   int64_t applies;     /* preconditioner applications */
   double relres_max;   /* largest true relative residual at exit */
   double t_total, t_matvec, t_apply, t_krylov;  /* seconds */
+  int64_t sweep_launches;  /* launches of the pair-sweep kernel during the solve */
+  double t_sweep;          /* their summed duration (HIP events on the context stream), s */
 } dp_solve_info;
 
 /* Solve A q = f for nrhs right-hand sides by restarted GMRES (x0 = 0, CGS2

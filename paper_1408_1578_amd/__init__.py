@@ -60,7 +60,8 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iters_max", ctypes.c_int64), ("matvecs", ctypes.c_int64),
                 ("applies", ctypes.c_int64), ("relres_max", ctypes.c_double),
                 ("t_total", ctypes.c_double), ("t_matvec", ctypes.c_double),
-                ("t_apply", ctypes.c_double), ("t_krylov", ctypes.c_double)]
+                ("t_apply", ctypes.c_double), ("t_krylov", ctypes.c_double),
+                ("sweep_launches", ctypes.c_int64), ("t_sweep", ctypes.c_double)]
 
 
 _lib = None

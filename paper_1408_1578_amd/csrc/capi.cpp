@@ -160,6 +160,7 @@ void dp_problem_destroy(dp_problem* p) {
   (void)hipSetDevice(p->ctx->device);
   (void)hipStreamSynchronize(p->ctx->stream);
   if (p->pc) precond_destroy(p->pc);
+  p->clock.destroy();
   p->src.release();
   p->C.release();
   p->twiddle.release();
@@ -188,6 +189,7 @@ int dp_matvec(dp_problem* p, int64_t nrhs, const double* q, double* y) {
   DP_SETDEV(p->ctx);
   DP_TRY(matvec(p, (int)nrhs, reinterpret_cast<const cplx*>(q), reinterpret_cast<cplx*>(y)));
   DP_HIP(hipStreamSynchronize(p->ctx->stream));
+  p->clock.collect();
   return DP_OK;
 }
 
@@ -202,6 +204,7 @@ int dp_layer_apply(dp_problem* p, int op, int64_t nrhs, const double* q, double*
     DP_TRY(sweep_apply(p, op, (int)nrhs, reinterpret_cast<const cplx*>(q), reinterpret_cast<cplx*>(y)));
   }
   DP_HIP(hipStreamSynchronize(p->ctx->stream));
+  p->clock.collect();
   return DP_OK;
 }
 

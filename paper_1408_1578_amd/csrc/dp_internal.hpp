@@ -58,6 +58,23 @@ struct SweepParams {
 
 struct Precond;
 
+// HIP-event timing of the pair-sweep kernel launches on one stream.
+struct SweepClock {
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  size_t used = 0;             // events recorded since the last collect
+  int64_t launches = 0;
+  double seconds = 0.0;
+  void start(hipStream_t s);
+  void stop(hipStream_t s);
+  void collect();  // after a stream synchronisation
+  void reset() {
+    collect();
+    launches = 0;
+    seconds = 0.0;
+  }
+  void destroy();
+};
+
 }  // namespace dp
 
 struct dp_ctx {
@@ -80,7 +97,7 @@ struct dp_problem {
   dp::DevBuf partial;   // sweep partial sums
   dp::DevBuf tmp1, tmp2, tmp3;
   dp::Precond* pc = nullptr;
-  double t_last_setup = 0;
+  dp::SweepClock clock;
 };
 
 namespace dp {

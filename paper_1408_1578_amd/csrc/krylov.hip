@@ -226,6 +226,7 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
   cplx* Wp = W.as<cplx>();
   cplx* Rp = R.as<cplx>();
 
+  p->clock.reset();
   Timer tm, ta;
   tm.init();
   ta.init();
@@ -297,6 +298,7 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
       DP_HIP(hipStreamSynchronize(st));
       tm.collect();
       ta.collect();
+      p->clock.collect();
       bool still = false;
       for (int c = 0; c < nrhs; ++c) {
         sbuf[c] = 0.0;
@@ -361,6 +363,7 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
     sub_from<<<g1(blk), 256, 0, st>>>(F, Rp, blk);
     DP_TRY(norms(p, Rp, nrhs, part, beta));
     tm.collect();
+    p->clock.collect();
     bool cont = false;
     for (int c = 0; c < nrhs; ++c) {
       if (done[c]) continue;
@@ -389,6 +392,8 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
     info->t_apply = ta.acc;
     info->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     info->t_krylov = info->t_total - tm.acc - ta.acc;
+    info->sweep_launches = p->clock.launches;
+    info->t_sweep = p->clock.seconds;
   }
   tm.destroy();
   ta.destroy();

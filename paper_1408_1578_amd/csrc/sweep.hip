@@ -336,6 +336,7 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   sp.omega = p->omega;
   sp.eta = p->eta;
   sp.dt = 2.0 * kPi / n;
+  p->clock.start(st);
   switch (op) {
     case OP_SOFT: launch_sweep<OP_SOFT>(sp, nrp, st); break;
     case OP_HARD: launch_sweep<OP_HARD>(sp, nrp, st); break;
@@ -343,6 +344,7 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
     case OP_D: launch_sweep<OP_D>(sp, nrp, st); break;
     default: launch_sweep<OP_DP>(sp, nrp, st); break;
   }
+  p->clock.stop(st);
   DP_HIP(hipGetLastError());
   EpiParams e;
   e.src = sp.src;
@@ -364,6 +366,39 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   sweep_epilogue<<<grid1d((size_t)n * nrhs), 256, 0, st>>>(e);
   DP_HIP(hipGetLastError());
   return DP_OK;
+}
+
+void SweepClock::start(hipStream_t s) {
+  if (used + 2 > ev.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+    ev.push_back(a);
+    ev.push_back(b);
+  }
+  (void)hipEventRecord(ev[used], s);
+}
+
+void SweepClock::stop(hipStream_t s) {
+  if (used + 2 > ev.size()) return;
+  (void)hipEventRecord(ev[used + 1], s);
+  used += 2;
+}
+
+void SweepClock::collect() {
+  for (size_t k = 0; k + 1 < used; k += 2) {
+    float ms = 0.f;
+    if (hipEventSynchronize(ev[k + 1]) == hipSuccess && hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) {
+      seconds += 1e-3 * ms;
+      ++launches;
+    }
+  }
+  used = 0;
+}
+
+void SweepClock::destroy() {
+  for (auto e : ev) (void)hipEventDestroy(e);
+  ev.clear();
+  used = 0;
 }
 
 int sweep_apply(dp_problem* p, int op, int nrhs, const cplx* q, cplx* y) {
