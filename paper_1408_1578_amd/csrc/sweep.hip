@@ -20,10 +20,12 @@
 //            row per lane; every wave evaluates its own kernel values and
 //            multiplies them into nrp columns.  Source data is wave-uniform
 //            (scalar loads).
-//   shared : nrp >= 8 columns.  64 target rows x WAVES waves per block; the
+//   shared : nrp = 8 columns.  64 target rows x WAVES waves per block; the
 //            waves split the kernel evaluations of a 32-source tile, share
 //            them through LDS, and each wave multiplies the whole tile into
 //            its own group of nrp/WAVES columns.
+//   mfma   : nrp >= 16 columns.  The column contraction runs on the FP64
+//            matrix cores (see sweep_mfma).
 // Sources are split into chunks (grid.y) so that large problems fill the
 // chip; per-chunk partial sums are reduced in a fixed order (deterministic).
 #include "dp_internal.hpp"
@@ -185,6 +187,106 @@ __global__ __launch_bounds__(64 * WAVES) void sweep_shared(SweepParams p) {
   }
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Many-column sweep on the matrix cores.  The contraction
+//   out_d[i][c] += sum_j K_d(i, j) dens_d[j][c]
+// is a dense complex GEMM whose left operand is generated on the fly: a
+// 16 x 4 tile of kernel values (16 targets x 4 sources, one pair per lane)
+// is exactly the A operand of v_mfma_f64_16x16x4 (A[i][k] in lane i + 16k),
+// and the densities of the same 4 sources for 16 columns are its B operand
+// (B[k][c] in lane c + 16k), staged in LDS for the 4 waves of a block.
+// Complex products take four real MFMAs (re.re, -im.im into the real
+// accumulator; re.im, im.re into the imaginary one); results land in
+// D[i][c] = register r of lane c + 16 (i mod 4), i = 4r + lane/16.
+// Block: 4 waves x 16 targets = 64 targets, all 16*NCB columns; the VALU work
+// of the kernel evaluation overlaps the MFMA work of the other wave(s).
+template <int OP, int NCB>
+__global__ __launch_bounds__(256) void sweep_mfma(SweepParams p) {
+  constexpr int ND = Nd<OP>::v;
+  constexpr int TJ = 16;
+  constexpr int NC = 16 * NCB;
+  __shared__ cplx Ds[TJ][ND][NC + 2];
+  const int n = p.n;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int i = blockIdx.x * 64 + w * 16 + li;
+  const int ii = i < n ? i : n - 1;
+  const SrcRec tr = p.src[ii];
+  const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
+  const int j0 = blockIdx.y * p.chunk_len;
+  const int j1 = min(n, j0 + p.chunk_len);
+  dbl4 acc[ND][NCB][2];
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      acc[d][cb][0] = dbl4{0.0, 0.0, 0.0, 0.0};
+      acc[d][cb][1] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+  for (int jt = j0; jt < j1; jt += TJ) {
+    for (int e = threadIdx.x; e < TJ * ND * NC; e += 256) {
+      const int jj = e / (ND * NC), rem = e % (ND * NC);
+      const int j = jt + jj;
+      Ds[jj][rem / NC][rem % NC] = (j < j1) ? p.dens[(size_t)j * ND * NC + rem] : cplx{0.0, 0.0};
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int ks = 0; ks < TJ / 4; ++ks) {
+      const int jj = ks * 4 + lk;
+      const int j = jt + jj;
+      cplx K[ND];
+      if (j < j1) {
+        int k = ii - j;
+        k += (k < 0) ? n : 0;
+        pair_kernel<OP>(t, p.src[j], p.C[k], ii == j, p.omega, p.eta, p.dt, K);
+      } else {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) K[d] = {0.0, 0.0};
+      }
+      cplx B[ND][NCB];
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) B[d][cb] = Ds[jj][d][cb * 16 + li];
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[d][cb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].re, B[d][cb].re, acc[d][cb][0], 0, 0, 0);
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[d][cb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].re, B[d][cb].im, acc[d][cb][1], 0, 0, 0);
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[d][cb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-K[d].im, B[d][cb].im, acc[d][cb][0], 0, 0, 0);
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[d][cb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].im, B[d][cb].re, acc[d][cb][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int rbase = blockIdx.x * 64 + w * 16;
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rbase + 4 * r + lk;
+        if (row < n)
+          p.partial[(((size_t)blockIdx.y * ND + d) * NC + cb * 16 + li) * n + row] =
+              cplx{acc[d][cb][0][r], acc[d][cb][1][r]};
+      }
+}
+
 // dens[j][d][c] = in_d[c*n + j] (zero for padded columns c >= nrhs)
 __global__ void pack_dens(const cplx* __restrict__ a, const cplx* __restrict__ b, cplx* __restrict__ dens,
                           int n, int nrhs, int nrp, int nd, int col0) {
@@ -287,9 +389,9 @@ static void launch_sweep(const SweepParams& sp, int nrp, hipStream_t st) {
     dim3 grid((n + 63) / 64, sp.nchunks);
     switch (nrp) {
       case 8: sweep_shared<OP, 2, 4><<<grid, 256, 0, st>>>(sp); break;
-      case 16: sweep_shared<OP, 4, 4><<<grid, 256, 0, st>>>(sp); break;
-      case 32: sweep_shared<OP, 8, 4><<<grid, 256, 0, st>>>(sp); break;
-      default: sweep_shared<OP, 16, 4><<<grid, 256, 0, st>>>(sp); break;
+      case 16: sweep_mfma<OP, 1><<<grid, 256, 0, st>>>(sp); break;
+      case 32: sweep_mfma<OP, 2><<<grid, 256, 0, st>>>(sp); break;
+      default: sweep_mfma<OP, 4><<<grid, 256, 0, st>>>(sp); break;
     }
   }
 }
