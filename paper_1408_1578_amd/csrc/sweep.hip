@@ -43,16 +43,12 @@ struct Nd {
   static constexpr int v = (OP == OP_HARD) ? 2 : 1;
 };
 
-// Kernel values of one ordered pair (i, j), i != j (self pairs return 0).
+// Kernel values of one ordered pair (i, j) from its Hankel values
+// (self pairs i == j return 0).
 template <int OP>
-__device__ __forceinline__ void pair_kernel(const Tgt& t, const SrcRec& s, double Ck, bool self,
-                                            double omega, double eta, double dt, cplx* K) {
-  const double dx = t.x - s.x, dy = t.y - s.y;
-  double r2 = fma(dx, dx, dy * dy);
-  r2 = self ? 1.0 : r2;
-  const double rinv = dp_rsqrt(r2);
-  const double r = r2 * rinv;
-  const H01 h = hankel01(omega * r);
+__device__ __forceinline__ void assemble_pair(const Tgt& t, const SrcRec& s, double dx, double dy, double rinv,
+                                              const H01& h, double Ck, bool self, double omega, double eta,
+                                              double dt, cplx* K) {
   const double w = dt * s.sp;   // trapezoid weight
   const double ck = Ck * s.sp;  // Kress correction weight
   if constexpr (OP == OP_SOFT) {
@@ -87,6 +83,35 @@ __device__ __forceinline__ void pair_kernel(const Tgt& t, const SrcRec& s, doubl
 #pragma unroll
     for (int d = 0; d < Nd<OP>::v; ++d) K[d] = {0.0, 0.0};
   }
+}
+
+// Kernel values of one ordered pair (i, j), i != j (self pairs return 0).
+template <int OP>
+__device__ __forceinline__ void pair_kernel(const Tgt& t, const SrcRec& s, double Ck, bool self,
+                                            double omega, double eta, double dt, cplx* K) {
+  const double dx = t.x - s.x, dy = t.y - s.y;
+  double r2 = fma(dx, dx, dy * dy);
+  r2 = self ? 1.0 : r2;
+  const double rinv = dp_rsqrt(r2);
+  const double r = r2 * rinv;
+  const H01 h = hankel01(omega * r);
+  assemble_pair<OP>(t, s, dx, dy, rinv, h, Ck, self, omega, eta, dt, K);
+}
+
+// Branch-free version for pairs with omega r >= DP_HANKEL_ZA (asymptotic
+// branch only).  `near` reports whether the pair needs the other branch; its
+// values are then replaced by pair_kernel.
+template <int OP>
+__device__ __forceinline__ void pair_kernel_far(const Tgt& t, const SrcRec& s, double Ck, bool self,
+                                                double omega, double eta, double dt, cplx* K, bool& near) {
+  const double dx = t.x - s.x, dy = t.y - s.y;
+  double r2 = fma(dx, dx, dy * dy);
+  r2 = self ? 1.0 : r2;
+  const double rinv = dp_rsqrt(r2);
+  const double z = omega * r2 * rinv;
+  near = z < DP_HANKEL_ZA && !self;
+  const H01 h = hankel01_far(fmax(z, DP_HANKEL_ZA));
+  assemble_pair<OP>(t, s, dx, dy, rinv, h, Ck, self, omega, eta, dt, K);
 }
 
 template <int OP, int NR>
@@ -195,94 +220,96 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // 16 x 4 tile of kernel values (16 targets x 4 sources, one pair per lane)
 // is exactly the A operand of v_mfma_f64_16x16x4 (A[i][k] in lane i + 16k),
 // and the densities of the same 4 sources for 16 columns are its B operand
-// (B[k][c] in lane c + 16k), staged in LDS for the 4 waves of a block.
+// (B[k][c] in lane c + 16k), read straight from the packed density array
+// (L2 / MALL resident, coalesced 16-column runs); with no barriers the two
+// waves sharing a SIMD drift out of phase.
 // Complex products take four real MFMAs (re.re, -im.im into the real
 // accumulator; re.im, im.re into the imaginary one); results land in
 // D[i][c] = register r of lane c + 16 (i mod 4), i = 4r + lane/16.
-// Block: 4 waves x 16 targets = 64 targets, all 16*NCB columns; the VALU work
-// of the kernel evaluation overlaps the MFMA work of the other wave(s).
-template <int OP, int NCB>
-__global__ __launch_bounds__(256) void sweep_mfma(SweepParams p) {
+// Block: 4 row groups x 16 targets = 64 targets; CH waves per row group split
+// the 16*NCBW*CH columns, so each wave keeps only its share of accumulators
+// and two waves fit per SIMD: the VALU work of one wave's kernel evaluation
+// overlaps the MFMA work of the other (each evaluates its own pairs).
+template <int OP, int NCBW, int CH>
+__global__ __launch_bounds__(256 * CH) void sweep_mfma(SweepParams p) {
   constexpr int ND = Nd<OP>::v;
-  constexpr int TJ = 16;
-  constexpr int NC = 16 * NCB;
-  __shared__ cplx Ds[TJ][ND][NC + 2];
+  constexpr int NC = 16 * NCBW * CH;   // columns of the block
   const int n = p.n;
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int wv = threadIdx.x >> 6;
+  const int rg = wv & 3;               // row group: 16 targets
+  const int c0 = (wv >> 2) * 16 * NCBW; // first column of this wave
   const int li = lane & 15, lk = lane >> 4;
-  const int i = blockIdx.x * 64 + w * 16 + li;
+  const int i = blockIdx.x * 64 + rg * 16 + li;
   const int ii = i < n ? i : n - 1;
   const SrcRec tr = p.src[ii];
   const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
   const int j0 = blockIdx.y * p.chunk_len;
   const int j1 = min(n, j0 + p.chunk_len);
-  dbl4 acc[ND][NCB][2];
+  const int nsteps = (j1 - j0 + 3) / 4;
+  dbl4 acc[ND][NCBW][2];
 #pragma unroll
   for (int d = 0; d < ND; ++d)
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
+    for (int cb = 0; cb < NCBW; ++cb) {
       acc[d][cb][0] = dbl4{0.0, 0.0, 0.0, 0.0};
       acc[d][cb][1] = dbl4{0.0, 0.0, 0.0, 0.0};
     }
-  for (int jt = j0; jt < j1; jt += TJ) {
-    for (int e = threadIdx.x; e < TJ * ND * NC; e += 256) {
-      const int jj = e / (ND * NC), rem = e % (ND * NC);
-      const int j = jt + jj;
-      Ds[jj][rem / NC][rem % NC] = (j < j1) ? p.dens[(size_t)j * ND * NC + rem] : cplx{0.0, 0.0};
+  for (int st = 0; st < nsteps; ++st) {
+    // kernel values of this lane's pair: target i, source j0 + 4 st + lk
+    const int j = j0 + 4 * st + lk;
+    const bool valid = j < j1;
+    const int jc = valid ? j : j1 - 1;
+    // B operand: densities of source jc for this wave's columns (L2/MALL resident)
+    cplx B[ND][NCBW];
+    const cplx* dj = p.dens + (size_t)jc * ND * NC + c0 + li;
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
+      for (int cb = 0; cb < NCBW; ++cb) B[d][cb] = dj[d * NC + cb * 16];
+    int k = ii - jc;
+    k += (k < 0) ? n : 0;
+    const SrcRec sr = p.src[jc];
+    const double Ck = p.C[k];
+    cplx K[ND];
+    bool near;
+    pair_kernel_far<OP>(t, sr, Ck, ii == jc, p.omega, p.eta, p.dt, K, near);
+    if (__builtin_amdgcn_ballot_w64(near)) {
+      if (near) pair_kernel<OP>(t, sr, Ck, false, p.omega, p.eta, p.dt, K);
     }
-    __syncthreads();
-#pragma unroll 1
-    for (int ks = 0; ks < TJ / 4; ++ks) {
-      const int jj = ks * 4 + lk;
-      const int j = jt + jj;
-      cplx K[ND];
-      if (j < j1) {
-        int k = ii - j;
-        k += (k < 0) ? n : 0;
-        pair_kernel<OP>(t, p.src[j], p.C[k], ii == j, p.omega, p.eta, p.dt, K);
-      } else {
 #pragma unroll
-        for (int d = 0; d < ND; ++d) K[d] = {0.0, 0.0};
-      }
-      cplx B[ND][NCB];
+    for (int d = 0; d < ND; ++d) K[d] = valid ? K[d] : cplx{0.0, 0.0};
 #pragma unroll
-      for (int d = 0; d < ND; ++d)
+    for (int d = 0; d < ND; ++d)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) B[d][cb] = Ds[jj][d][cb * 16 + li];
+      for (int cb = 0; cb < NCBW; ++cb)
+        acc[d][cb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].re, B[d][cb].re, acc[d][cb][0], 0, 0, 0);
 #pragma unroll
-      for (int d = 0; d < ND; ++d)
+    for (int d = 0; d < ND; ++d)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          acc[d][cb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].re, B[d][cb].re, acc[d][cb][0], 0, 0, 0);
+      for (int cb = 0; cb < NCBW; ++cb)
+        acc[d][cb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].re, B[d][cb].im, acc[d][cb][1], 0, 0, 0);
 #pragma unroll
-      for (int d = 0; d < ND; ++d)
+    for (int d = 0; d < ND; ++d)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          acc[d][cb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].re, B[d][cb].im, acc[d][cb][1], 0, 0, 0);
+      for (int cb = 0; cb < NCBW; ++cb)
+        acc[d][cb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-K[d].im, B[d][cb].im, acc[d][cb][0], 0, 0, 0);
 #pragma unroll
-      for (int d = 0; d < ND; ++d)
+    for (int d = 0; d < ND; ++d)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          acc[d][cb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-K[d].im, B[d][cb].im, acc[d][cb][0], 0, 0, 0);
-#pragma unroll
-      for (int d = 0; d < ND; ++d)
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          acc[d][cb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].im, B[d][cb].re, acc[d][cb][1], 0, 0, 0);
-    }
-    __syncthreads();
+      for (int cb = 0; cb < NCBW; ++cb)
+        acc[d][cb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].im, B[d][cb].re, acc[d][cb][1], 0, 0, 0);
   }
-  const int rbase = blockIdx.x * 64 + w * 16;
+  const int rbase = blockIdx.x * 64 + rg * 16;
 #pragma unroll
   for (int d = 0; d < ND; ++d)
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
+    for (int cb = 0; cb < NCBW; ++cb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = rbase + 4 * r + lk;
         if (row < n)
-          p.partial[(((size_t)blockIdx.y * ND + d) * NC + cb * 16 + li) * n + row] =
+          p.partial[(((size_t)blockIdx.y * ND + d) * NC + c0 + cb * 16 + li) * n + row] =
               cplx{acc[d][cb][0][r], acc[d][cb][1][r]};
       }
 }
@@ -389,9 +416,9 @@ static void launch_sweep(const SweepParams& sp, int nrp, hipStream_t st) {
     dim3 grid((n + 63) / 64, sp.nchunks);
     switch (nrp) {
       case 8: sweep_shared<OP, 2, 4><<<grid, 256, 0, st>>>(sp); break;
-      case 16: sweep_mfma<OP, 1><<<grid, 256, 0, st>>>(sp); break;
-      case 32: sweep_mfma<OP, 2><<<grid, 256, 0, st>>>(sp); break;
-      default: sweep_mfma<OP, 4><<<grid, 256, 0, st>>>(sp); break;
+      case 16: sweep_mfma<OP, 1, 1><<<grid, 256, 0, st>>>(sp); break;
+      case 32: sweep_mfma<OP, 1, 2><<<grid, 512, 0, st>>>(sp); break;
+      default: sweep_mfma<OP, 2, 2><<<grid, 512, 0, st>>>(sp); break;
     }
   }
 }
