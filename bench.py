@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precond", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -115,6 +117,15 @@ def main():
     f = torch.empty((nrhs, b.n), dtype=torch.complex128, device="cuda:0")
     q = torch.empty_like(f)
     use_pc = not args.no_precond
+    if args.copy_calibration:
+        a = torch.empty(args.copy_calibration * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
+        a.fill_(1.0)
+        bb = torch.empty_like(a)
+        torch.cuda.synchronize()
+        bb.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + written")
+        del a, bb
 
     def step():
         t0 = time.perf_counter()
