@@ -98,6 +98,17 @@ __device__ __forceinline__ void pair_kernel(const Tgt& t, const SrcRec& s, doubl
   assemble_pair<OP>(t, s, dx, dy, rinv, h, Ck, self, omega, eta, dt, K);
 }
 
+// Small-argument version (omega r < DP_HANKEL_ZA, the recurrence branch only).
+template <int OP>
+__device__ __forceinline__ void pair_kernel_near(const Tgt& t, const SrcRec& s, double Ck, double omega, double eta,
+                                                 double dt, cplx* K) {
+  const double dx = t.x - s.x, dy = t.y - s.y;
+  const double r2 = fma(dx, dx, dy * dy);
+  const double rinv = dp_rsqrt(r2);
+  const H01 h = hankel01_near(omega * r2 * rinv);
+  assemble_pair<OP>(t, s, dx, dy, rinv, h, Ck, false, omega, eta, dt, K);
+}
+
 // Branch-free version for pairs with omega r >= DP_HANKEL_ZA (asymptotic
 // branch only).  `near` reports whether the pair needs the other branch; its
 // values are then replaced by pair_kernel.
@@ -230,15 +241,17 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // the 16*NCBW*CH columns, so each wave keeps only its share of accumulators
 // and two waves fit per SIMD: the VALU work of one wave's kernel evaluation
 // overlaps the MFMA work of the other (each evaluates its own pairs).
-template <int OP, int NCBW, int CH>
-__global__ __launch_bounds__(256 * CH) void sweep_mfma(SweepParams p) {
+template <int OP, int NCBW>
+__global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
   constexpr int ND = Nd<OP>::v;
-  constexpr int NC = 16 * NCBW * CH;   // columns of the block
+  constexpr int NC = 32 * NCBW;        // columns of the block (two waves per row group)
+  __shared__ cplx Kx[2][4][2][ND][64];  // [buffer][row group][step parity][density][lane]
   const int n = p.n;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int rg = wv & 3;               // row group: 16 targets
-  const int c0 = (wv >> 2) * 16 * NCBW; // first column of this wave
+  const int rg = wv & 3;                // row group: 16 targets
+  const int ch = wv >> 2;               // column half; also the parity of the k-steps it evaluates
+  const int c0 = ch * 16 * NCBW;
   const int li = lane & 15, lk = lane >> 4;
   const int i = blockIdx.x * 64 + rg * 16 + li;
   const int ii = i < n ? i : n - 1;
@@ -247,26 +260,24 @@ __global__ __launch_bounds__(256 * CH) void sweep_mfma(SweepParams p) {
   const int j0 = blockIdx.y * p.chunk_len;
   const int j1 = min(n, j0 + p.chunk_len);
   const int nsteps = (j1 - j0 + 3) / 4;
-  dbl4 acc[ND][NCBW][2];
+  const int npairs = (nsteps + 1) / 2;
+  // 3-multiplication complex products: T1 += Kr Br, T2 += Ki Bi,
+  // T3 += (Kr + Ki)(Br + Bi); then Re = T1 - T2, Im = T3 - T1 - T2.
+  dbl4 T1[ND][NCBW], T2[ND][NCBW], T3[ND][NCBW];
 #pragma unroll
   for (int d = 0; d < ND; ++d)
 #pragma unroll
     for (int cb = 0; cb < NCBW; ++cb) {
-      acc[d][cb][0] = dbl4{0.0, 0.0, 0.0, 0.0};
-      acc[d][cb][1] = dbl4{0.0, 0.0, 0.0, 0.0};
+      T1[d][cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+      T2[d][cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+      T3[d][cb] = dbl4{0.0, 0.0, 0.0, 0.0};
     }
-  for (int st = 0; st < nsteps; ++st) {
-    // kernel values of this lane's pair: target i, source j0 + 4 st + lk
+  for (int sp = 0; sp < npairs; ++sp) {
+    // kernel values of this wave's k-step 2 sp + ch (target i, source j0 + 4 st + lk)
+    const int st = 2 * sp + ch;
     const int j = j0 + 4 * st + lk;
     const bool valid = j < j1;
     const int jc = valid ? j : j1 - 1;
-    // B operand: densities of source jc for this wave's columns (L2/MALL resident)
-    cplx B[ND][NCBW];
-    const cplx* dj = p.dens + (size_t)jc * ND * NC + c0 + li;
-#pragma unroll
-    for (int d = 0; d < ND; ++d)
-#pragma unroll
-      for (int cb = 0; cb < NCBW; ++cb) B[d][cb] = dj[d * NC + cb * 16];
     int k = ii - jc;
     k += (k < 0) ? n : 0;
     const SrcRec sr = p.src[jc];
@@ -275,30 +286,34 @@ __global__ __launch_bounds__(256 * CH) void sweep_mfma(SweepParams p) {
     bool near;
     pair_kernel_far<OP>(t, sr, Ck, ii == jc, p.omega, p.eta, p.dt, K, near);
     if (__builtin_amdgcn_ballot_w64(near)) {
-      if (near) pair_kernel<OP>(t, sr, Ck, false, p.omega, p.eta, p.dt, K);
+      if (near) pair_kernel_near<OP>(t, sr, Ck, p.omega, p.eta, p.dt, K);
     }
+    const int buf = sp & 1;
 #pragma unroll
-    for (int d = 0; d < ND; ++d) K[d] = valid ? K[d] : cplx{0.0, 0.0};
+    for (int d = 0; d < ND; ++d) {
+      K[d] = valid ? K[d] : cplx{0.0, 0.0};
+      Kx[buf][rg][ch][d][lane] = K[d];
+    }
+    __syncthreads();
 #pragma unroll
-    for (int d = 0; d < ND; ++d)
+    for (int h = 0; h < 2; ++h) {
+      const int sth = 2 * sp + h;
+      if (sth >= nsteps) break;
+      const int jh = min(j0 + 4 * sth + lk, j1 - 1);
+      const cplx* dj = p.dens + (size_t)jh * ND * NC + c0 + li;
 #pragma unroll
-      for (int cb = 0; cb < NCBW; ++cb)
-        acc[d][cb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].re, B[d][cb].re, acc[d][cb][0], 0, 0, 0);
+      for (int d = 0; d < ND; ++d) {
+        const cplx Kh = (h == ch) ? K[d] : Kx[buf][rg][h][d][lane];
+        const double ks = Kh.re + Kh.im;
 #pragma unroll
-    for (int d = 0; d < ND; ++d)
-#pragma unroll
-      for (int cb = 0; cb < NCBW; ++cb)
-        acc[d][cb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].re, B[d][cb].im, acc[d][cb][1], 0, 0, 0);
-#pragma unroll
-    for (int d = 0; d < ND; ++d)
-#pragma unroll
-      for (int cb = 0; cb < NCBW; ++cb)
-        acc[d][cb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-K[d].im, B[d][cb].im, acc[d][cb][0], 0, 0, 0);
-#pragma unroll
-    for (int d = 0; d < ND; ++d)
-#pragma unroll
-      for (int cb = 0; cb < NCBW; ++cb)
-        acc[d][cb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[d].im, B[d][cb].re, acc[d][cb][1], 0, 0, 0);
+        for (int cb = 0; cb < NCBW; ++cb) {
+          const cplx B = dj[d * NC + cb * 16];
+          T1[d][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Kh.re, B.re, T1[d][cb], 0, 0, 0);
+          T2[d][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Kh.im, B.im, T2[d][cb], 0, 0, 0);
+          T3[d][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ks, B.re + B.im, T3[d][cb], 0, 0, 0);
+        }
+      }
+    }
   }
   const int rbase = blockIdx.x * 64 + rg * 16;
 #pragma unroll
@@ -308,9 +323,11 @@ __global__ __launch_bounds__(256 * CH) void sweep_mfma(SweepParams p) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = rbase + 4 * r + lk;
-        if (row < n)
+        if (row < n) {
+          const double t1 = T1[d][cb][r], t2 = T2[d][cb][r], t3 = T3[d][cb][r];
           p.partial[(((size_t)blockIdx.y * ND + d) * NC + c0 + cb * 16 + li) * n + row] =
-              cplx{acc[d][cb][0][r], acc[d][cb][1][r]};
+              cplx{t1 - t2, t3 - t1 - t2};
+        }
       }
 }
 
@@ -416,9 +433,9 @@ static void launch_sweep(const SweepParams& sp, int nrp, hipStream_t st) {
     dim3 grid((n + 63) / 64, sp.nchunks);
     switch (nrp) {
       case 8: sweep_shared<OP, 2, 4><<<grid, 256, 0, st>>>(sp); break;
-      case 16: sweep_mfma<OP, 1, 1><<<grid, 256, 0, st>>>(sp); break;
-      case 32: sweep_mfma<OP, 1, 2><<<grid, 512, 0, st>>>(sp); break;
-      default: sweep_mfma<OP, 2, 2><<<grid, 512, 0, st>>>(sp); break;
+      case 16: sweep_shared<OP, 4, 4><<<grid, 256, 0, st>>>(sp); break;
+      case 32: sweep_mfma<OP, 1><<<grid, 512, 0, st>>>(sp); break;
+      default: sweep_mfma<OP, 2><<<grid, 512, 0, st>>>(sp); break;
     }
   }
 }
