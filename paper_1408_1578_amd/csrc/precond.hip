@@ -56,6 +56,9 @@ struct Precond {
   SparseLU lu;
   DevBuf Lp, Lj, Lx, Up, Uj, Ux, Ud, lvlL, lvlLr, lvlU, lvlUr, pin, pout;
   int nlevL = 0, nlevU = 0;
+  // level-ordered copies for the LDS-resident solve
+  DevBuf itL, itU, jL2, vL2, jU2, vU2, uinv;
+  bool lds_solve = false;
   int64_t nnzW = 0;
   DevBuf wy, wg, wz, wu, wt, wn;  // apply workspaces
   double t_setup = 0;
@@ -564,6 +567,65 @@ __global__ __launch_bounds__(1024) void level_solve(cplx* x, const int* __restri
   }
 }
 
+// Whole floor(W)^{-1} z for one column per block with the column held in LDS:
+// gather zp[k] = z[perm_in[k]], forward solve with L (unit diagonal),
+// backward solve with U, scatter u[perm_out[b]] = u'[b].  Rows of one
+// dependency level are independent; each row is an item (row, first entry,
+// entry count) in level order, with its entries stored contiguously, so the
+// only accesses that depend on the previous level are LDS reads.
+__global__ __launch_bounds__(256) void tri_solve_lds(const cplx* __restrict__ z, cplx* __restrict__ u, int NW,
+                                                     const int* __restrict__ pin, const int* __restrict__ pout,
+                                                     const int4* __restrict__ itL, const int* __restrict__ lvL,
+                                                     int nlevL, const int* __restrict__ jL,
+                                                     const cplx* __restrict__ vL, const int4* __restrict__ itU,
+                                                     const int* __restrict__ lvU, int nlevU,
+                                                     const int* __restrict__ jU, const cplx* __restrict__ vU,
+                                                     const cplx* __restrict__ uinv) {
+  extern __shared__ cplx xs[];
+  const size_t c = blockIdx.x;
+  for (int k = threadIdx.x; k < NW; k += blockDim.x) xs[k] = z[c * NW + pin[k]];
+  __syncthreads();
+  // each row is handled by RL consecutive lanes (strided over its entries,
+  // then a shuffle reduction): long rows do not serialise a level
+  constexpr int RL = 8;
+  const int g = threadIdx.x / RL, lr = threadIdx.x % RL;
+  const int G = blockDim.x / RL;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int4* it_ = pass ? itU : itL;
+    const int* lv = pass ? lvU : lvL;
+    const int* jj = pass ? jU : jL;
+    const cplx* vv = pass ? vU : vL;
+    const int nlev = pass ? nlevU : nlevL;
+    for (int l = 0; l < nlev; ++l) {
+      const int b = lv[l], e = lv[l + 1];
+      for (int t0 = b; t0 < e; t0 += G) {
+        const int t = t0 + g;
+        const bool act = t < e;
+        const int4 it = act ? it_[t] : int4{0, 0, 0, 0};
+        cplx acc = {0.0, 0.0};
+        for (int q = it.y + lr; q < it.y + it.z; q += RL) {
+          const cplx a = vv[q], xv = xs[jj[q]];
+          acc.re += a.re * xv.re - a.im * xv.im;
+          acc.im += a.re * xv.im + a.im * xv.re;
+        }
+#pragma unroll
+        for (int off = RL / 2; off > 0; off >>= 1) {
+          acc.re += __shfl_xor(acc.re, off, RL);
+          acc.im += __shfl_xor(acc.im, off, RL);
+        }
+        if (act && lr == 0) {
+          const cplx x0 = xs[it.x];
+          cplx r = {x0.re - acc.re, x0.im - acc.im};
+          if (pass) r = cmul(r, uinv[it.x]);
+          xs[it.x] = r;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int k = threadIdx.x; k < NW; k += blockDim.x) u[c * NW + pout[k]] = xs[k];
+}
+
 // ------------------------------------------------------------------ host: setup
 static void segment_boundary(const dp_problem* p, const dp_precond_opts* o, std::vector<int>& off,
                              std::vector<int>& len) {
@@ -805,6 +867,39 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     return fail(rc);
   P->nlevL = (int)lu.lvlL_ptr.size() - 1;
   P->nlevU = (int)lu.lvlU_ptr.size() - 1;
+  {
+    // level-ordered items (row, first entry, count) and entries
+    auto order = [&](const std::vector<int>& rows, const std::vector<int>& Pp, const std::vector<int>& Jj,
+                     const std::vector<zc>& Vv, std::vector<int4>& items, std::vector<int>& j2,
+                     std::vector<cplx>& v2) {
+      for (int r : rows) {
+        items.push_back(int4{r, (int)j2.size(), Pp[r + 1] - Pp[r], 0});
+        for (int q = Pp[r]; q < Pp[r + 1]; ++q) {
+          j2.push_back(Jj[q]);
+          v2.push_back({Vv[q].real(), Vv[q].imag()});
+        }
+      }
+    };
+    std::vector<int4> itl, itu;
+    std::vector<int> jl, ju;
+    std::vector<cplx> vl, vu, ui(NW);
+    order(lu.lvlL_rows, lu.Lp, lu.Lj, lu.Lx, itl, jl, vl);
+    order(lu.lvlU_rows, lu.Up, lu.Uj, lu.Ux, itu, ju, vu);
+    for (int r = 0; r < NW; ++r) {
+      const zc inv = 1.0 / lu.Ud[r];
+      ui[r] = {inv.real(), inv.imag()};
+    }
+    if ((rc = upload(P->itL, itl, st)) || (rc = upload(P->itU, itu, st)) || (rc = upload(P->jL2, jl, st)) ||
+        (rc = upload(P->vL2, vl, st)) || (rc = upload(P->jU2, ju, st)) || (rc = upload(P->vU2, vu, st)) ||
+        (rc = upload(P->uinv, ui, st)))
+      return fail(rc);
+    int maxlds = 0;
+    DP_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->ctx->device));
+    P->lds_solve = (size_t)NW * sizeof(cplx) <= (size_t)maxlds;
+    if (P->lds_solve)
+      DP_HIP(hipFuncSetAttribute((const void*)tri_solve_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(NW * sizeof(cplx))));
+  }
 
   // ---- apply tables
   std::vector<int> segs(4 * m), dims(2 * P->classes.size());
@@ -891,14 +986,21 @@ int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
   // z = floor(T) g
   DP_TRY(run_seg_gemm(p, TT, 1, 1, 1, 0, g, NW, nullptr, z, NW, nrhs));
   // u = floor(W)^{-1} z
-  gather_rows<<<grid1((size_t)NW * nrhs), 256, 0, st>>>(z, t, P->pin.as<int>(), NW, nrhs);
-  const int cpb = nrhs < 16 ? nrhs : 16;
-  const int nb = (nrhs + cpb - 1) / cpb;
-  level_solve<<<nb, 1024, 0, st>>>(t, P->Lp.as<int>(), P->Lj.as<int>(), P->Lx.as<cplx>(), nullptr,
-                                   P->lvlL.as<int>(), P->lvlLr.as<int>(), P->nlevL, NW, nrhs, cpb);
-  level_solve<<<nb, 1024, 0, st>>>(t, P->Up.as<int>(), P->Uj.as<int>(), P->Ux.as<cplx>(), P->Ud.as<cplx>(),
-                                   P->lvlU.as<int>(), P->lvlUr.as<int>(), P->nlevU, NW, nrhs, cpb);
-  scatter_rows<<<grid1((size_t)NW * nrhs), 256, 0, st>>>(t, u, P->pout.as<int>(), NW, nrhs);
+  if (P->lds_solve) {
+    tri_solve_lds<<<nrhs, 256, (size_t)NW * sizeof(cplx), st>>>(
+        z, u, NW, P->pin.as<int>(), P->pout.as<int>(), P->itL.as<int4>(), P->lvlL.as<int>(), P->nlevL,
+        P->jL2.as<int>(), P->vL2.as<cplx>(), P->itU.as<int4>(), P->lvlU.as<int>(), P->nlevU, P->jU2.as<int>(),
+        P->vU2.as<cplx>(), P->uinv.as<cplx>());
+  } else {
+    gather_rows<<<grid1((size_t)NW * nrhs), 256, 0, st>>>(z, t, P->pin.as<int>(), NW, nrhs);
+    const int cpb = nrhs < 16 ? nrhs : 16;
+    const int nb = (nrhs + cpb - 1) / cpb;
+    level_solve<<<nb, 1024, 0, st>>>(t, P->Lp.as<int>(), P->Lj.as<int>(), P->Lx.as<cplx>(), nullptr,
+                                     P->lvlL.as<int>(), P->lvlLr.as<int>(), P->nlevL, NW, nrhs, cpb);
+    level_solve<<<nb, 1024, 0, st>>>(t, P->Up.as<int>(), P->Uj.as<int>(), P->Ux.as<cplx>(), P->Ud.as<cplx>(),
+                                     P->lvlU.as<int>(), P->lvlUr.as<int>(), P->nlevU, NW, nrhs, cpb);
+    scatter_rows<<<grid1((size_t)NW * nrhs), 256, 0, st>>>(t, u, P->pout.as<int>(), NW, nrhs);
+  }
   // h = z - floor(T) u  (into g)
   DP_TRY(run_seg_gemm(p, TT, 1, 1, 1, 1, u, NW, z, g, NW, nrhs));
   // un = U h
@@ -920,7 +1022,7 @@ void precond_destroy(Precond* P) {
   }
   for (DevBuf* b : {&P->d_segs, &P->d_ptrs, &P->d_dims, &P->Lp, &P->Lj, &P->Lx, &P->Up, &P->Uj, &P->Ux, &P->Ud,
                     &P->lvlL, &P->lvlLr, &P->lvlU, &P->lvlUr, &P->pin, &P->pout, &P->wy, &P->wg, &P->wz, &P->wu,
-                    &P->wt, &P->wn})
+                    &P->wt, &P->wn, &P->itL, &P->itU, &P->jL2, &P->vL2, &P->jU2, &P->vU2, &P->uinv})
     b->release();
   delete P;
 }
