@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 METRIC = "CFIE solves/s at n=32768 to 1e-8 residual (mixed vs FP64); p50/p99 latency"
 # FP64 peak, TFLOP/s: dense MFMA and vector FMA are both 256 CU x 4 SIMD x 32 flop/clk x 2.4 GHz
 PEAK_FP64_VALU = 78.6
+# dense FP32 matrix-core peak, TFLOP/s (the mixed-precision correction sweeps)
+PEAK_FP32_MFMA = 157.3
 
 # Algorithmic FP64 flops of one ordered pair in the sound-hard sweep (far-field
 # evaluation path; an FMA counts 2): geometry 5, 1/r 8, r and z 2, H0/H1 142,
@@ -99,6 +101,9 @@ def main():
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precond", action="store_true")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="fp64: GMRES on the FP64 operator; mixed: iterative refinement with "
+                         "FP32-operator corrections and FP64 residuals (same 1e-8 FP64 residual)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -119,6 +124,8 @@ def main():
     f = torch.empty((nrhs, b.n), dtype=torch.complex128, device="cuda:0")
     q = torch.empty_like(f)
     use_pc = not args.no_precond
+    mixed = args.precision == "mixed"
+    prec = dp.DP_PREC_MIXED if mixed else dp.DP_PREC_FP64
     if args.copy_calibration:
         a = torch.empty(args.copy_calibration * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
         a.fill_(1.0)
@@ -134,7 +141,7 @@ def main():
         if use_pc:
             dp.dp_precond_build(prob)
         dp.dp_rhs_plane_wave(prob, angles, f)
-        info = dp.dp_solve(prob, f, q, tol=1e-8, restart=80, use_precond=use_pc)
+        info = dp.dp_solve(prob, f, q, tol=1e-8, restart=80, use_precond=use_pc, precision=prec)
         return info, time.perf_counter() - t0
 
     for w in range(args.warmup):
@@ -148,20 +155,27 @@ def main():
         lat.append(dt)
         infos.append(info)
         log(f"step {s}: {dt:.3f} s iters={info['iters_max']} relres={info['relres_max']:.2e} "
-            f"sweep {info['t_sweep'] / max(info['sweep_launches'], 1) * 1e3:.2f} ms x {info['sweep_launches']}")
+            f"sweep {info['t_sweep'] / max(info['sweep_launches'], 1) * 1e3:.2f} ms x {info['sweep_launches']}"
+            f" fp32 {info['t_sweep_fp32'] / max(info['sweep_launches_fp32'], 1) * 1e3:.2f} ms x "
+            f"{info['sweep_launches_fp32']} refinements={info['refinements']}")
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     ok = all(i["converged"] and i["relres_max"] <= 1e-8 for i in infos)
 
-    launches = sum(i["sweep_launches"] for i in infos)
-    t_sweep = sum(i["t_sweep"] for i in infos)
-    avg = t_sweep / max(launches, 1)
     nrp = 1
     while nrp < nrhs and nrp < 64:
         nrp *= 2
     pairs = b.n * (b.n - 1)
     flops = pairs * (FLOPS_PAIR_HARD + FLOPS_PAIR_PER_RHS_HARD * nrp)
-    achieved = flops / avg / 1e12 if avg > 0 else 0.0
+
+    def sweep_rate(key_l, key_t):
+        launches = sum(i[key_l] for i in infos)
+        t = sum(i[key_t] for i in infos)
+        avg = t / max(launches, 1)
+        return launches, avg, (flops / avg / 1e12 if avg > 0 else 0.0)
+
+    launches, avg, achieved = sweep_rate("sweep_launches", "t_sweep")
+    launches32, avg32, achieved32 = sweep_rate("sweep_launches_fp32", "t_sweep_fp32")
     pinfo = dp.dp_precond_get_info(prob) if use_pc else {}
     lat_ms = np.array(lat) * 1e3
 
@@ -176,18 +190,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {
             "workload": f"sound-hard kite, n={b.n}, 10 points/wavelength (omega={om:.1f}), eta=omega, "
                         f"{nrhs} plane waves at 2*pi*k/{nrhs}, directional preconditioner + GMRES(80) "
-                        f"to 1e-8, FP64",
+                        f"to 1e-8 (FP64 residual), " + ("mixed FP32/FP64 refinement" if mixed else "FP64"),
             "n": b.n, "nrhs": nrhs, "omega": om, "tol": 1e-8, "restart": 80,
-            "precision": "fp64", "precond": use_pc,
+            "precision": args.precision, "precond": use_pc,
         },
         "converged": ok,
         "iterations": int(max(i["iters_max"] for i in infos)),
         "relres_max": float(max(i["relres_max"] for i in infos)),
+        "refinements": int(max(i["refinements"] for i in infos)),
+        "matvecs_fp32": int(max(i["matvecs_fp32"] for i in infos)),
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "phase_s_per_step": {
             "matvec": float(np.mean([i["t_matvec"] for i in infos])),
@@ -195,7 +211,21 @@ def main():
             "krylov": float(np.mean([i["t_krylov"] for i in infos])),
             "precond_setup": float(pinfo.get("t_setup", 0.0)),
         },
-        "roofline": {
+        "roofline": ({
+            "kernel": "sweep_mfma32<hard, 64 columns> (FP32 kernel values and matrix-core products, "
+                      "FP64 phase reduction; 8 waves, kernel values shared by wave pairs)",
+            "bound": "mfma",
+            "achieved": achieved32,
+            "peak": PEAK_FP32_MFMA,
+            "unit": "TFLOP/s",
+            "frac": achieved32 / PEAK_FP32_MFMA,
+            "traffic": None,
+            "launch_ms": avg32 * 1e3,
+            "launches": launches32,
+            "flops_per_launch": flops,
+            "fp64_residual_sweeps": {"launch_ms": avg * 1e3, "launches": launches,
+                                     "achieved": achieved, "frac_fp64_peak": achieved / PEAK_FP64_VALU},
+        } if mixed else {
             "kernel": "sweep_mfma<hard, 2 column blocks/wave> (8 waves: kernel values shared by wave pairs, 3-multiply complex MFMA)",
             "bound": "mfma",
             "achieved": achieved,
@@ -206,7 +236,7 @@ def main():
             "launch_ms": avg * 1e3,
             "launches": launches,
             "flops_per_launch": flops,
-        },
+        }),
     }
     if pinfo:
         out["precond"] = {k: pinfo[k] for k in ("m", "NW", "nnzW", "nnzLU", "levels")}

@@ -94,6 +94,12 @@ int dp_rhs_plane_wave(dp_problem* p, int64_t nrhs, const double* angles, double*
  * complex, must not overlap.  nrhs >= 1. */
 int dp_matvec(dp_problem* p, int64_t nrhs, const double* q, double* y);
 
+/* y = A_32 q: the single-precision operator used by the correction solves of
+ * DP_PREC_MIXED (FP32 kernel values and matrix-core products, FP64 geometry,
+ * phase reduction, small-argument Hankel values, diagonal terms and output).
+ * Same arguments as dp_matvec; relative error ~1e-6. */
+int dp_matvec_mixed(dp_problem* p, int64_t nrhs, const double* q, double* y);
+
 /* y = OP q for one operator (DP_OP_S, DP_OP_D, DP_OP_DP, DP_OP_DS); device
  * n x nrhs complex arrays.  Exposed for parity tests of the single layers. */
 int dp_layer_apply(dp_problem* p, int op, int64_t nrhs, const double* q, double* y);
@@ -139,11 +145,20 @@ int dp_precond_export(dp_problem* p, int64_t* seg_off, int64_t* seg_len, int64_t
                       double* e_val);
 
 /* ------------------------------------------------------------------ solve */
+enum { DP_PREC_FP64 = 0, DP_PREC_MIXED = 1 };
+
 typedef struct {
   double tol;       /* relative residual ||f - A q|| / ||f|| per column; default 1e-8 */
   int restart;      /* GMRES restart length; default 80 (Sec. 3) */
   int max_iters;    /* total Arnoldi steps per column; default 2000 */
   int use_precond;  /* 1: right-precondition with the built preconditioner */
+  int precision;    /* DP_PREC_FP64, or DP_PREC_MIXED: iterative refinement whose
+                       corrections come from GMRES with the single-precision
+                       operator (FP32 kernel values and matrix-core products;
+                       FP64 geometry, phase reduction, small-argument Hankel
+                       values, diagonal terms, Krylov vectors and Givens
+                       rotations) and whose residuals f - A q are FP64 */
+  double inner_tol; /* mixed: relative tolerance of each correction solve; default 1e-5 */
 } dp_solve_opts;
 
 typedef struct {
@@ -154,14 +169,20 @@ typedef struct {
   double t_total, t_matvec, t_apply, t_krylov;  /* seconds */
   int64_t sweep_launches;  /* launches of the pair-sweep kernel during the solve */
   double t_sweep;          /* their summed duration (HIP events on the context stream), s */
+  int64_t refinements;     /* mixed: outer refinement steps (FP64 residuals) */
+  int64_t matvecs_fp32;    /* mixed: operator applications in single precision */
+  int64_t sweep_launches_fp32;  /* mixed: launches of the single-precision sweep */
+  double t_sweep_fp32;          /* their summed duration, s */
 } dp_solve_info;
 
 /* Solve A q = f for nrhs right-hand sides by restarted GMRES (x0 = 0, CGS2
  * Arnoldi, Givens rotations), right-preconditioned when requested; the
  * preconditioned vectors are stored (flexible form) so q = Z y needs no extra
- * apply.  f, q: device n x nrhs complex.  opts/info may be NULL.  iters,
- * relres: optional host arrays of nrhs entries (per-column iteration counts
- * and true relative residuals).  Returns DP_OK or DP_ENOCONV. */
+ * apply.  With DP_PREC_MIXED the solve is q_{k+1} = q_k + GMRES_32(f - A q_k)
+ * until the FP64 residual meets tol.  f, q: device n x nrhs complex.
+ * opts/info may be NULL.  iters, relres: optional host arrays of nrhs entries
+ * (per-column iteration counts and true FP64 relative residuals).  Returns
+ * DP_OK or DP_ENOCONV. */
 int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_solve_opts* opts,
              dp_solve_info* info, int64_t* iters, double* relres);
 

@@ -28,7 +28,7 @@ DP_OP_S, DP_OP_D, DP_OP_DP, DP_OP_DS = 2, 3, 4, 5
 # every symbol declared in include/dirprec.h
 EXPORTED = [
     "dp_ctx_create", "dp_ctx_destroy", "dp_last_error", "dp_problem_create",
-    "dp_problem_destroy", "dp_rhs_plane_wave", "dp_matvec", "dp_layer_apply",
+    "dp_problem_destroy", "dp_rhs_plane_wave", "dp_matvec", "dp_matvec_mixed", "dp_layer_apply",
     "dp_precond_build", "dp_precond_apply", "dp_precond_get_info", "dp_precond_export",
     "dp_solve", "dp_hankel_dev", "dp_hankel_host",
 ]
@@ -51,9 +51,13 @@ class PrecondInfo(ctypes.Structure):
                 ("levels", ctypes.c_int64), ("t_setup", ctypes.c_double)]
 
 
+DP_PREC_FP64, DP_PREC_MIXED = 0, 1
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int),
-                ("max_iters", ctypes.c_int), ("use_precond", ctypes.c_int)]
+                ("max_iters", ctypes.c_int), ("use_precond", ctypes.c_int),
+                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -61,7 +65,9 @@ class SolveInfo(ctypes.Structure):
                 ("applies", ctypes.c_int64), ("relres_max", ctypes.c_double),
                 ("t_total", ctypes.c_double), ("t_matvec", ctypes.c_double),
                 ("t_apply", ctypes.c_double), ("t_krylov", ctypes.c_double),
-                ("sweep_launches", ctypes.c_int64), ("t_sweep", ctypes.c_double)]
+                ("sweep_launches", ctypes.c_int64), ("t_sweep", ctypes.c_double),
+                ("refinements", ctypes.c_int64), ("matvecs_fp32", ctypes.c_int64),
+                ("sweep_launches_fp32", ctypes.c_int64), ("t_sweep_fp32", ctypes.c_double)]
 
 
 _lib = None
@@ -94,6 +100,7 @@ def lib():
         "dp_problem_destroy": (None, [vp]),
         "dp_rhs_plane_wave": (ci, [vp, i64, vp, vp]),
         "dp_matvec": (ci, [vp, i64, vp, vp]),
+        "dp_matvec_mixed": (ci, [vp, i64, vp, vp]),
         "dp_layer_apply": (ci, [vp, ci, i64, vp, vp]),
         "dp_precond_build": (ci, [vp, ctypes.POINTER(PrecondOpts)]),
         "dp_precond_apply": (ci, [vp, i64, vp, vp]),
@@ -225,6 +232,13 @@ def dp_matvec(p, q, y):
     _check("dp_matvec", lib().dp_matvec(p.h, nr, _ptr(q), _ptr(y)))
 
 
+def dp_matvec_mixed(p, q, y):
+    nr = _cols(q, p.n)
+    if _cols(y, p.n) != nr:
+        raise ValueError("shape mismatch")
+    _check("dp_matvec_mixed", lib().dp_matvec_mixed(p.h, nr, _ptr(q), _ptr(y)))
+
+
 def dp_layer_apply(p, op, q, y):
     nr = _cols(q, p.n)
     if _cols(y, p.n) != nr:
@@ -263,11 +277,12 @@ def dp_precond_export(p):
     return off, ln, ei.reshape(-1, 4), ev.view(np.complex128)
 
 
-def dp_solve(p, f, q, tol=1e-8, restart=80, max_iters=2000, use_precond=False):
+def dp_solve(p, f, q, tol=1e-8, restart=80, max_iters=2000, use_precond=False, precision=DP_PREC_FP64,
+             inner_tol=1e-5):
     nr = _cols(f, p.n)
     if _cols(q, p.n) != nr:
         raise ValueError("shape mismatch")
-    o = SolveOpts(tol, restart, max_iters, 1 if use_precond else 0)
+    o = SolveOpts(tol, restart, max_iters, 1 if use_precond else 0, int(precision), inner_tol)
     info = SolveInfo()
     its = np.zeros(nr, np.int64)
     rel = np.zeros(nr, np.float64)

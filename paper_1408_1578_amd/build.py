@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdirprec.so")
-SOURCES = ["capi.cpp", "tables.hip", "sweep.hip", "fft.hip", "krylov.hip", "precond.hip", "sparse_lu.cpp"]
+SOURCES = ["capi.cpp", "tables.hip", "sweep.hip", "near.hip", "fft.hip", "krylov.hip", "precond.hip", "sparse_lu.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -147,6 +147,7 @@ int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nr
     rc = DP_EDEVICE;
   }
   if (rc == DP_OK) rc = build_tables(p);
+  if (rc == DP_OK) rc = near_build(p);
   if (rc != DP_OK) {
     dp_problem_destroy(p);
     return rc;
@@ -161,11 +162,15 @@ void dp_problem_destroy(dp_problem* p) {
   (void)hipStreamSynchronize(p->ctx->stream);
   if (p->pc) precond_destroy(p->pc);
   p->clock.destroy();
+  p->clock32.destroy();
   p->src.release();
   p->C.release();
   p->twiddle.release();
   p->dens.release();
   p->partial.release();
+  p->near_ptr.release();
+  p->near_col.release();
+  p->near_out.release();
   p->tmp1.release();
   p->tmp2.release();
   p->tmp3.release();
@@ -190,6 +195,16 @@ int dp_matvec(dp_problem* p, int64_t nrhs, const double* q, double* y) {
   DP_TRY(matvec(p, (int)nrhs, reinterpret_cast<const cplx*>(q), reinterpret_cast<cplx*>(y)));
   DP_HIP(hipStreamSynchronize(p->ctx->stream));
   p->clock.collect();
+  return DP_OK;
+}
+
+int dp_matvec_mixed(dp_problem* p, int64_t nrhs, const double* q, double* y) {
+  DP_CHECK(p && q && y && nrhs >= 1 && q != y, "dp_matvec_mixed: bad argument");
+  DP_SETDEV(p->ctx);
+  DP_TRY(matvec(p, (int)nrhs, reinterpret_cast<const cplx*>(q), reinterpret_cast<cplx*>(y), 1));
+  DP_HIP(hipStreamSynchronize(p->ctx->stream));
+  p->clock.collect();
+  p->clock32.collect();
   return DP_OK;
 }
 
@@ -252,9 +267,11 @@ int dp_precond_export(dp_problem* p, int64_t* seg_off, int64_t* seg_len, int64_t
 int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_solve_opts* opts,
              dp_solve_info* info, int64_t* iters, double* relres) {
   DP_CHECK(p && f && q && nrhs >= 1 && f != q, "dp_solve: bad argument");
-  dp_solve_opts o = {1e-8, 80, 2000, 0};
+  dp_solve_opts o = {1e-8, 80, 2000, 0, DP_PREC_FP64, 1e-5};
   if (opts) o = *opts;
+  if (o.inner_tol <= 0) o.inner_tol = 1e-5;
   DP_CHECK(o.tol > 0 && o.restart >= 1 && o.restart <= 1000 && o.max_iters >= 1, "dp_solve: bad options");
+  DP_CHECK(o.precision == DP_PREC_FP64 || o.precision == DP_PREC_MIXED, "dp_solve: precision %d", o.precision);
   if (o.use_precond && !p->pc) {
     set_error("dp_solve: use_precond set but no preconditioner was built");
     return DP_ESTATE;

@@ -52,8 +52,11 @@ struct SweepParams {
   const double* C;         // n: Kress correction C_k (index (i - j) mod n)
   const cplx* dens;        // [j][nd][nrp] source densities (transposed layout)
   cplx* partial;           // [chunk][nd][nrp][n] partial sums
+  const cplxf* dens32;     // FP32 copies for the mixed-precision matrix-core sweep
+  cplxf* partial32;
   int n, nrp, nd, chunk_len, nchunks;
   double omega, eta, dt;   // dt = 2 pi / n
+  double r2near;           // pairs with r^2 < r2near are left to the near-field pass
 };
 
 struct Precond;
@@ -95,17 +98,31 @@ struct dp_problem {
   dp::DevBuf twiddle;   // cplx[n]   (e^{-2 pi i l/n})
   dp::DevBuf dens;      // sweep operands
   dp::DevBuf partial;   // sweep partial sums
+  // near-field pairs (i != j, r^2 < r2near = (DP_HANKEL_ZA/omega)^2), CSR by
+  // target row, columns ascending; their kernel values use the small-argument
+  // Hankel branch and are applied by a separate pass
+  double r2near = 0;
+  int64_t near_nnz = 0;
+  dp::DevBuf near_ptr;  // int[n + 1]
+  dp::DevBuf near_col;  // int[near_nnz]
+  dp::DevBuf near_out;  // near-field sums [nd][nrp][n]
   dp::DevBuf tmp1, tmp2, tmp3;
   dp::Precond* pc = nullptr;
-  dp::SweepClock clock;
+  dp::SweepClock clock;    // FP64 sweep launches
+  dp::SweepClock clock32;  // single-precision sweep launches
 };
 
 namespace dp {
 // tables.hip
 int build_tables(dp_problem* p);
 // sweep.hip
-int sweep_apply(dp_problem* p, int op, int nrhs, const cplx* q, cplx* y);
-int matvec(dp_problem* p, int nrhs, const cplx* q, cplx* y);
+// prec: 0 = FP64 sweep, 1 = mixed (FP32 kernel values and products with FP64
+// geometry, phase reduction, small-argument Hankel values and diagonal terms)
+int sweep_apply(dp_problem* p, int op, int nrhs, const cplx* q, cplx* y, int prec = 0);
+int near_build(dp_problem* p);
+// near.hip: near-field sums of one sweep group into p->near_out (no-op without near pairs)
+int near_apply_group(dp_problem* p, int op, int nrp, const void* dens, bool dens32);
+int matvec(dp_problem* p, int nrhs, const cplx* q, cplx* y, int prec = 0);
 // fft.hip
 int spectral_derivative(dp_problem* p, int nrhs, const cplx* in, cplx* out);
 // rhs

@@ -187,4 +187,72 @@ DP_HD H01 hankel01_near(double z) {
 
 DP_HD H01 hankel01(double z) { return z >= DP_HANKEL_ZA ? hankel01_far(z) : hankel01_near(z); }
 
+// ----------------------------------------------------- single precision
+struct cplxf {
+  float re, im;
+};
+
+struct H01f {
+  cplxf h0, h1;
+};
+
+DP_HD float dp_rsqrtf(float z) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rsqf(z);
+#else
+  return 1.0f / sqrtf(z);
+#endif
+}
+
+// Asymptotic branch for z >= DP_HANKEL_ZA with FP32 arithmetic: the phase z
+// is reduced modulo pi/2 in FP64 (|z| up to 1e6 keeps ~1e-16 absolute phase
+// error), everything after the reduction is FP32.  Terms k <= 6 of the
+// expansion (truncation < 3e-10 at z = 25); sin/cos of the reduced argument
+// by their Taylor series to r^9 / r^10.  Relative accuracy ~3e-7.
+DP_HD H01f hankel01_far32(double z) {
+  const double kq = rint(z * kTwoOverPi);
+  double rr = fma(-kq, kPio2Hi, z);
+  rr = fma(-kq, kPio2Lo, rr);
+  const float r = (float)rr, r2 = r * r;
+  float ps = (float)inv_fact(9);
+  ps = fmaf(ps, r2, -(float)inv_fact(7));
+  ps = fmaf(ps, r2, (float)inv_fact(5));
+  ps = fmaf(ps, r2, -(float)inv_fact(3));
+  const float sr = fmaf(ps * r2, r, r);
+  float pc = -(float)inv_fact(10);
+  pc = fmaf(pc, r2, (float)inv_fact(8));
+  pc = fmaf(pc, r2, -(float)inv_fact(6));
+  pc = fmaf(pc, r2, (float)inv_fact(4));
+  pc = fmaf(pc, r2, -(float)inv_fact(2));
+  const float cr = fmaf(pc, r2, 1.0f);
+  const long long q = (long long)kq & 3;
+  const float s1 = (q & 1) ? cr : sr;
+  const float c1 = (q & 1) ? sr : cr;
+  const float s = (q & 2) ? -s1 : s1;
+  const float c = ((q + 1) & 2) ? -c1 : c1;
+  const float zf = (float)z;
+  const float y = dp_rsqrtf(zf);
+  const float t = y * y;
+  const float u = -t * t;
+  float p0 = (float)hankel_a(6, 0), p1 = (float)hankel_a(6, 1);
+  p0 = fmaf(p0, u, (float)hankel_a(4, 0));
+  p1 = fmaf(p1, u, (float)hankel_a(4, 1));
+  p0 = fmaf(p0, u, (float)hankel_a(2, 0));
+  p1 = fmaf(p1, u, (float)hankel_a(2, 1));
+  p0 = fmaf(p0, u, 1.0f);
+  p1 = fmaf(p1, u, 1.0f);
+  float q0 = (float)hankel_a(5, 0), q1 = (float)hankel_a(5, 1);
+  q0 = fmaf(q0, u, (float)hankel_a(3, 0));
+  q1 = fmaf(q1, u, (float)hankel_a(3, 1));
+  q0 = fmaf(q0, u, (float)hankel_a(1, 0)) * t;
+  q1 = fmaf(q1, u, (float)hankel_a(1, 1)) * t;
+  const float m = (float)(kSqrt2OverPi * kInvSqrt2) * y;
+  const cplxf e0 = {(c + s) * m, (s - c) * m};
+  const cplxf e1 = {(s - c) * m, -(s + c) * m};
+  H01f h;
+  h.h0 = {e0.re * p0 - e0.im * q0, e0.re * q0 + e0.im * p0};
+  h.h1 = {e1.re * p1 - e1.im * q1, e1.re * q1 + e1.im * p1};
+  return h;
+}
+
 }  // namespace dp

@@ -196,8 +196,15 @@ static int norms(dp_problem* p, const cplx* W, int nrhs, DevBuf& part, std::vect
   return DP_OK;
 }
 
-int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* o, dp_solve_info* info,
-          int64_t* iters_out, double* relres_out) {
+// Restarted (flexible) GMRES with operator precision `prec` (0 FP64, 1 mixed)
+// from x0 = 0; the residual checks at restarts use the same operator.  With
+// `trust_estimate` (the correction solves of the refinement) a column whose
+// Arnoldi residual estimate meets tol is final without a true-residual check:
+// the single-precision operator's own rounding can hold its true residual just
+// above a tight inner tolerance, and the FP64 residual of the outer step is the
+// real test.
+static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* o, int prec,
+                      bool trust_estimate, dp_solve_info* info, int64_t* iters_out, double* relres_out) {
   const auto t0 = std::chrono::steady_clock::now();
   const int n = (int)p->n;
   const double tol = o->tol;
@@ -226,7 +233,6 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
   cplx* Wp = W.as<cplx>();
   cplx* Rp = R.as<cplx>();
 
-  p->clock.reset();
   Timer tm, ta;
   tm.init();
   ta.init();
@@ -247,7 +253,7 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
   std::vector<zc> H((size_t)(m + 1) * m * nrhs), cs((size_t)m * nrhs), sn((size_t)m * nrhs),
       g((size_t)(m + 1) * nrhs);
   std::vector<int> kc(nrhs);
-  std::vector<char> active(nrhs);
+  std::vector<char> active(nrhs), conv_est(nrhs);
   std::vector<cplx> hbuf(2 * hsz);
   std::vector<double> nbuf(nrhs), sbuf(nrhs);
   std::vector<cplx> yh((size_t)m * nrhs);
@@ -258,6 +264,7 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
     bool any = false;
     for (int c = 0; c < nrhs; ++c) {
       active[c] = !done[c] && its[c] < o->max_iters;
+      conv_est[c] = 0;
       any |= active[c];
       sbuf[c] = active[c] ? 1.0 / beta[c] : 0.0;
       kc[c] = 0;
@@ -277,7 +284,7 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
         ++applies;
       }
       tm.start(st);
-      DP_TRY(matvec(p, nrhs, zk, Wp));
+      DP_TRY(matvec(p, nrhs, zk, Wp, prec));
       tm.stop(st);
       ++matvecs;
       const int kp1 = k + 1;
@@ -299,6 +306,7 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
       tm.collect();
       ta.collect();
       p->clock.collect();
+      p->clock32.collect();
       bool still = false;
       for (int c = 0; c < nrhs; ++c) {
         sbuf[c] = 0.0;
@@ -331,6 +339,7 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
         rel[c] = est;
         if (est <= tol || hn == 0.0 || its[c] >= o->max_iters) {
           active[c] = 0;
+          conv_est[c] = est <= tol || hn == 0.0;
         } else {
           sbuf[c] = 1.0 / hn;
           still = true;
@@ -355,15 +364,24 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
     }
     DP_HIP(hipMemcpyAsync(ydev, yh.data(), (size_t)kdone * nrhs * sizeof(cplx), hipMemcpyHostToDevice, st));
     combine<<<g1(blk), 256, 0, st>>>(Zp, blk, X, ydev, n, nrhs, kdone);
+    if (trust_estimate) {
+      bool more = false;
+      for (int c = 0; c < nrhs; ++c) {
+        if (conv_est[c]) done[c] = 1;
+        more |= !done[c] && its[c] < o->max_iters;
+      }
+      if (!more) break;
+    }
     // true residual
     tm.start(st);
-    DP_TRY(matvec(p, nrhs, X, Rp));
+    DP_TRY(matvec(p, nrhs, X, Rp, prec));
     tm.stop(st);
     ++matvecs;
     sub_from<<<g1(blk), 256, 0, st>>>(F, Rp, blk);
     DP_TRY(norms(p, Rp, nrhs, part, beta));
     tm.collect();
     p->clock.collect();
+    p->clock32.collect();
     bool cont = false;
     for (int c = 0; c < nrhs; ++c) {
       if (done[c]) continue;
@@ -394,6 +412,10 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
     info->t_krylov = info->t_total - tm.acc - ta.acc;
     info->sweep_launches = p->clock.launches;
     info->t_sweep = p->clock.seconds;
+    info->refinements = 0;
+    info->matvecs_fp32 = prec ? matvecs : 0;
+    info->sweep_launches_fp32 = p->clock32.launches;
+    info->t_sweep_fp32 = p->clock32.seconds;
   }
   tm.destroy();
   ta.destroy();
@@ -403,6 +425,139 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
   R.release();
   part.release();
   small.release();
+  return rc;
+}
+
+// out[c] = F[c] - R[c] for columns with keep[c] != 0, else 0
+__global__ void residual_cols(const cplx* __restrict__ F, cplx* __restrict__ R, const double* __restrict__ keep,
+                              int n, int nrhs) {
+  const size_t tot = (size_t)n * nrhs;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const cplx a = F[idx], b = R[idx];
+    R[idx] = keep[idx / n] != 0.0 ? cplx{a.re - b.re, a.im - b.im} : cplx{0.0, 0.0};
+  }
+}
+
+// X += D
+__global__ void add_into(cplx* __restrict__ X, const cplx* __restrict__ D, size_t tot) {
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const cplx a = X[idx], b = D[idx];
+    X[idx] = {a.re + b.re, a.im + b.im};
+  }
+}
+
+int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* o, dp_solve_info* info,
+          int64_t* iters_out, double* relres_out) {
+  p->clock.reset();
+  p->clock32.reset();
+  if (o->precision == DP_PREC_FP64) return gmres_core(p, nrhs, F, X, o, 0, false, info, iters_out, relres_out);
+  // Mixed precision: q_{k+1} = q_k + GMRES_32(f - A q_k), residuals in FP64.
+  const auto t0 = std::chrono::steady_clock::now();
+  const int n = (int)p->n;
+  hipStream_t st = p->ctx->stream;
+  const size_t blk = (size_t)n * nrhs;
+  DevBuf R, D, part, keep;
+  DP_TRY(R.reserve(blk * sizeof(cplx)));
+  DP_TRY(D.reserve(blk * sizeof(cplx)));
+  DP_TRY(keep.reserve(nrhs * sizeof(double)));
+  std::vector<double> fn, rn;
+  DP_TRY(norms(p, F, nrhs, part, fn));
+  DP_HIP(hipMemsetAsync(X, 0, blk * sizeof(cplx), st));
+  DP_HIP(hipMemcpyAsync(R.p, F, blk * sizeof(cplx), hipMemcpyDeviceToDevice, st));
+  std::vector<int64_t> its(nrhs, 0), its_in(nrhs);
+  std::vector<double> rel(nrhs, 1.0), rel_in(nrhs), kv(nrhs);
+  for (int c = 0; c < nrhs; ++c) rel[c] = fn[c] > 0 ? 1.0 : 0.0;
+  dp_solve_opts oi = *o;
+  oi.tol = o->inner_tol;
+  int64_t mv = 0, mv32 = 0, ap = 0, outer = 0;
+  double t_mv = 0, t_ap = 0;
+  Timer tm;
+  tm.init();
+  int rc = DP_OK;
+  const int max_outer = 12;
+  while (true) {
+    bool any = false;
+    int64_t left = o->max_iters;
+    for (int c = 0; c < nrhs; ++c)
+      if (rel[c] > o->tol) {
+        any = true;
+        left = std::min<int64_t>(left, o->max_iters - its[c]);
+      }
+    if (!any) break;
+    if (outer >= max_outer || left <= 0) {
+      rc = DP_ENOCONV;
+      break;
+    }
+    oi.max_iters = (int)std::max<int64_t>(1, left);
+    dp_solve_info ii;
+    int r = gmres_core(p, nrhs, R.as<cplx>(), D.as<cplx>(), &oi, 1, true, &ii, its_in.data(), rel_in.data());
+    if (r < 0) return r;
+    for (int c = 0; c < nrhs; ++c) its[c] += its_in[c];
+    mv += ii.matvecs;
+    mv32 += ii.matvecs;
+    ap += ii.applies;
+    t_mv += ii.t_matvec;
+    t_ap += ii.t_apply;
+    ++outer;
+    const size_t g = (blk + 255) / 256;
+    add_into<<<(int)(g > 8192 ? 8192 : g), 256, 0, st>>>(X, D.as<cplx>(), blk);
+    // R = f - A X in FP64 (converged columns get zero right-hand sides)
+    tm.start(st);
+    DP_TRY(matvec(p, nrhs, X, R.as<cplx>(), 0));
+    tm.stop(st);
+    ++mv;
+    for (int c = 0; c < nrhs; ++c) kv[c] = 1.0;
+    DP_HIP(hipMemcpyAsync(keep.p, kv.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    residual_cols<<<(int)(g > 8192 ? 8192 : g), 256, 0, st>>>(F, R.as<cplx>(), keep.as<double>(), n, nrhs);
+    DP_TRY(norms(p, R.as<cplx>(), nrhs, part, rn));
+    tm.collect();
+    p->clock.collect();
+    p->clock32.collect();
+    bool zero_any = false;
+    for (int c = 0; c < nrhs; ++c) {
+      rel[c] = fn[c] > 0 ? rn[c] / fn[c] : 0.0;
+      kv[c] = rel[c] > o->tol ? 1.0 : 0.0;
+      zero_any |= kv[c] == 0.0;
+    }
+    if (zero_any) {
+      DP_HIP(hipMemcpyAsync(keep.p, kv.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+      // zero the residual columns that already meet tol (their corrections vanish)
+      scale_cols<<<(int)(g > 8192 ? 8192 : g), 256, 0, st>>>(R.as<cplx>(), R.as<cplx>(), keep.as<double>(), n,
+                                                             nrhs);
+    }
+  }
+  DP_HIP(hipStreamSynchronize(st));
+  double rmax = 0;
+  int64_t imax = 0;
+  for (int c = 0; c < nrhs; ++c) {
+    rmax = std::max(rmax, rel[c]);
+    imax = std::max(imax, its[c]);
+    if (iters_out) iters_out[c] = its[c];
+    if (relres_out) relres_out[c] = rel[c];
+  }
+  if (info) {
+    info->iters_max = imax;
+    info->matvecs = mv;
+    info->applies = ap;
+    info->relres_max = rmax;
+    info->t_matvec = t_mv + tm.acc;
+    info->t_apply = t_ap;
+    info->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->t_krylov = info->t_total - info->t_matvec - t_ap;
+    info->sweep_launches = p->clock.launches;
+    info->t_sweep = p->clock.seconds;
+    info->refinements = outer;
+    info->matvecs_fp32 = mv32;
+    info->sweep_launches_fp32 = p->clock32.launches;
+    info->t_sweep_fp32 = p->clock32.seconds;
+  }
+  tm.destroy();
+  R.release();
+  D.release();
+  part.release();
+  keep.release();
   return rc;
 }
 

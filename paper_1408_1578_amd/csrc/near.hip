@@ -1,0 +1,208 @@
+// Near-field pairs of the Nystrom matrix.
+//
+// The Hankel kernels are evaluated by two branches (dp_math.hpp): the
+// asymptotic expansion for omega r >= DP_HANKEL_ZA and a Bessel recurrence
+// below it.  The sweeps evaluate only the first (branch-free, so the
+// matrix-core loop carries no divergent path and no extra live registers)
+// and return 0 for pairs with r^2 < r2near = (DP_HANKEL_ZA/omega)^2.  Those
+// pairs, about 2 DP_HANKEL_ZA/(omega h) per row for node spacing h (about 80
+// at 10 points per wavelength), are listed here once per problem (CSR by
+// target row, sources ascending) and applied by near_apply in FP64, which
+// writes its sums to a buffer that the sweep epilogue adds.  Both sides decide
+// "near" with pair_r2, so every off-diagonal pair is applied exactly once.
+#include "sweep_pair.hpp"
+
+#include <vector>
+
+namespace dp {
+
+namespace {
+
+constexpr int kNearThreads = 256;
+
+// Per-row count (pass 0) or fill (pass 1) of the near-field sources: thread t
+// scans the contiguous source range [t per, (t + 1) per), so a block-wide
+// exclusive scan of the per-thread counts gives each thread its output slot
+// and the row comes out in ascending source order.
+template <int PASS>
+__global__ __launch_bounds__(kNearThreads) void near_scan(const SrcRec* __restrict__ src, int n, double r2near,
+                                                          int* __restrict__ cnt, const int* __restrict__ ptr,
+                                                          int* __restrict__ col) {
+  __shared__ int sc[kNearThreads];
+  const int i = blockIdx.x;
+  const int t = threadIdx.x;
+  const int per = (n + kNearThreads - 1) / kNearThreads;
+  const int ja = min(n, t * per), jb = min(n, ja + per);
+  const SrcRec ti = src[i];
+  int c = 0;
+  for (int j = ja; j < jb; ++j) {
+    const SrcRec s = src[j];
+    c += (j != i && pair_r2(ti.x, ti.y, s.x, s.y) < r2near) ? 1 : 0;
+  }
+  sc[t] = c;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the block
+  for (int off = 1; off < kNearThreads; off <<= 1) {
+    const int v = t >= off ? sc[t - off] : 0;
+    __syncthreads();
+    sc[t] += v;
+    __syncthreads();
+  }
+  if (PASS == 0) {
+    if (t == kNearThreads - 1) cnt[i] = sc[t];
+    return;
+  }
+  int o = ptr[i] + sc[t] - c;
+  for (int j = ja; j < jb; ++j) {
+    const SrcRec s = src[j];
+    if (j != i && pair_r2(ti.x, ti.y, s.x, s.y) < r2near) col[o++] = j;
+  }
+}
+
+struct NearParams {
+  const SrcRec* src;
+  const double* C;
+  const int* ptr;
+  const int* col;
+  const void* dens;  // packed densities [j][nd][nrp] (cplx or cplxf)
+  cplx* out;         // [nd][nrp][n]
+  int n, nrp;
+  double omega, eta, dt;
+};
+
+// One wave per target row (4 rows per block).  Lane l evaluates the kernel
+// values of the row's near entry base + l; then lane (g, c), c < nrp,
+// g < 64/nrp, accumulates entries l = g (mod 64/nrp) of column c, taking the
+// values by cross-lane shuffles, and a butterfly over g sums the groups.
+// Row blocks are spread so that each XCD (blocks b = x mod 8) works on a
+// contiguous range of rows and finds the shared source densities in its L2.
+template <int OP, class DT>
+__global__ __launch_bounds__(256) void near_apply(NearParams p) {
+  constexpr int ND = Nd<OP>::v;
+  const int lane = threadIdx.x & 63;
+  const int nb = gridDim.x;
+  const int x = blockIdx.x & 7, q = nb >> 3, r = nb & 7;
+  const int bb = x * q + min(x, r) + (blockIdx.x >> 3);
+  const int i = bb * 4 + (threadIdx.x >> 6);
+  if (i >= p.n) return;  // no block barriers below
+  const int nrp = p.nrp;
+  const int G = 64 / nrp;
+  const int c = lane % nrp, g = lane / nrp;
+  const SrcRec tr = p.src[i];
+  const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
+  const DT* dens = static_cast<const DT*>(p.dens);
+  cplx acc[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) acc[d] = {0.0, 0.0};
+  const int e0 = p.ptr[i], e1 = p.ptr[i + 1];
+  for (int base = e0; base < e1; base += 64) {
+    const int cnt = min(64, e1 - base);
+    int j = i;
+    cplx K[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) K[d] = {0.0, 0.0};
+    if (lane < cnt) {
+      j = p.col[base + lane];
+      int k = i - j;
+      k += (k < 0) ? p.n : 0;
+      pair_kernel_near<OP>(t, p.src[j], p.C[k], p.omega, p.eta, p.dt, K);
+    }
+    for (int l0 = 0; l0 < cnt; l0 += G) {
+      const int l = l0 + g;  // < 64
+      const int jl = __shfl(j, l);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        const cplx Kl = {__shfl(K[d].re, l), __shfl(K[d].im, l)};
+        if (l < cnt) {
+          const DT v = dens[((size_t)jl * ND + d) * nrp + c];
+          cfma(acc[d], Kl, cplx{(double)v.re, (double)v.im});
+        }
+      }
+    }
+  }
+  for (int off = nrp; off < 64; off <<= 1)
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      acc[d].re += __shfl_xor(acc[d].re, off);
+      acc[d].im += __shfl_xor(acc[d].im, off);
+    }
+  if (g == 0)
+#pragma unroll
+    for (int d = 0; d < ND; ++d) p.out[((size_t)d * nrp + c) * p.n + i] = acc[d];
+}
+
+template <class DT>
+void launch_near(int op, const NearParams& np, hipStream_t st) {
+  const int grid = (np.n + 3) / 4;
+  switch (op) {
+    case OP_SOFT: near_apply<OP_SOFT, DT><<<grid, 256, 0, st>>>(np); break;
+    case OP_HARD: near_apply<OP_HARD, DT><<<grid, 256, 0, st>>>(np); break;
+    case OP_S: near_apply<OP_S, DT><<<grid, 256, 0, st>>>(np); break;
+    case OP_D: near_apply<OP_D, DT><<<grid, 256, 0, st>>>(np); break;
+    default: near_apply<OP_DP, DT><<<grid, 256, 0, st>>>(np); break;
+  }
+}
+
+}  // namespace
+
+int near_build(dp_problem* p) {
+  hipStream_t st = p->ctx->stream;
+  const int n = (int)p->n;
+  const double zr = DP_HANKEL_ZA / p->omega;
+  p->r2near = zr * zr;
+  DevBuf cnt;
+  DP_TRY(cnt.reserve((size_t)n * sizeof(int)));
+  near_scan<0><<<n, kNearThreads, 0, st>>>(p->src.as<SrcRec>(), n, p->r2near, cnt.as<int>(), nullptr, nullptr);
+  DP_HIP(hipGetLastError());
+  std::vector<int> hc(n);
+  DP_HIP(hipMemcpyAsync(hc.data(), cnt.p, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
+  DP_HIP(hipStreamSynchronize(st));
+  std::vector<int> hp(n + 1);
+  int64_t tot = 0;
+  for (int i = 0; i < n; ++i) {
+    hp[i] = (int)tot;
+    tot += hc[i];
+    if (tot > 0x7fffffff) {
+      cnt.release();
+      set_error("near field too large: more than 2^31 pairs have omega r < 25 (frequency too low for n)");
+      return DP_EINVAL;
+    }
+  }
+  hp[n] = (int)tot;
+  p->near_nnz = tot;
+  DP_TRY(p->near_ptr.reserve((size_t)(n + 1) * sizeof(int)));
+  DP_TRY(p->near_col.reserve((size_t)(tot > 0 ? tot : 1) * sizeof(int)));
+  DP_HIP(hipMemcpyAsync(p->near_ptr.p, hp.data(), (size_t)(n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  if (tot > 0) {
+    near_scan<1><<<n, kNearThreads, 0, st>>>(p->src.as<SrcRec>(), n, p->r2near, nullptr, p->near_ptr.as<int>(),
+                                            p->near_col.as<int>());
+    DP_HIP(hipGetLastError());
+  }
+  DP_HIP(hipStreamSynchronize(st));
+  cnt.release();
+  return DP_OK;
+}
+
+int near_apply_group(dp_problem* p, int op, int nrp, const void* dens, bool dens32) {
+  if (p->near_nnz == 0) return DP_OK;
+  const int nd = op == OP_HARD ? 2 : 1;
+  DP_TRY(p->near_out.reserve((size_t)nd * nrp * p->n * sizeof(cplx)));
+  NearParams np;
+  np.src = p->src.as<SrcRec>();
+  np.C = p->C.as<double>();
+  np.ptr = p->near_ptr.as<int>();
+  np.col = p->near_col.as<int>();
+  np.dens = dens;
+  np.out = p->near_out.as<cplx>();
+  np.n = (int)p->n;
+  np.nrp = nrp;
+  np.omega = p->omega;
+  np.eta = p->eta;
+  np.dt = 2.0 * kPi / p->n;
+  if (dens32) launch_near<cplxf>(op, np, p->ctx->stream);
+  else launch_near<cplx>(op, np, p->ctx->stream);
+  DP_HIP(hipGetLastError());
+  return DP_OK;
+}
+
+}  // namespace dp

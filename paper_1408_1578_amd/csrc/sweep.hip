@@ -28,102 +28,9 @@
 //            matrix cores (see sweep_mfma).
 // Sources are split into chunks (grid.y) so that large problems fill the
 // chip; per-chunk partial sums are reduced in a fixed order (deterministic).
-#include "dp_internal.hpp"
+#include "sweep_pair.hpp"
 
 namespace dp {
-
-constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
-
-struct Tgt {
-  double x, y, nx, ny;
-};
-
-template <int OP>
-struct Nd {
-  static constexpr int v = (OP == OP_HARD) ? 2 : 1;
-};
-
-// Kernel values of one ordered pair (i, j) from its Hankel values
-// (self pairs i == j return 0).
-template <int OP>
-__device__ __forceinline__ void assemble_pair(const Tgt& t, const SrcRec& s, double dx, double dy, double rinv,
-                                              const H01& h, double Ck, bool self, double omega, double eta,
-                                              double dt, cplx* K) {
-  const double w = dt * s.sp;   // trapezoid weight
-  const double ck = Ck * s.sp;  // Kress correction weight
-  if constexpr (OP == OP_SOFT) {
-    const double nd = (s.nx * dx + s.ny * dy) * rinv;
-    // K = (i omega/4) H1 nd + (eta/4) H0,  K1 = -(omega/(4pi)) J1 nd + i eta J0/(4pi)
-    const double a = 0.25 * omega * nd, b = 0.25 * eta;
-    K[0].re = w * fma(-a, h.h1.im, b * h.h0.re) - ck * (omega * kInv4Pi) * nd * h.h1.re;
-    K[0].im = w * fma(a, h.h1.re, b * h.h0.im) + ck * (eta * kInv4Pi) * h.h0.re;
-  } else if constexpr (OP == OP_S) {
-    K[0].re = -0.25 * w * h.h0.im - ck * kInv4Pi * h.h0.re;
-    K[0].im = 0.25 * w * h.h0.re;
-  } else if constexpr (OP == OP_D) {
-    const double nd = (s.nx * dx + s.ny * dy) * rinv;
-    K[0].re = -0.25 * omega * nd * w * h.h1.im - ck * omega * kInv4Pi * nd * h.h1.re;
-    K[0].im = 0.25 * omega * nd * w * h.h1.re;
-  } else if constexpr (OP == OP_DP) {
-    const double ni = (t.nx * dx + t.ny * dy) * rinv;
-    K[0].re = 0.25 * omega * ni * w * h.h1.im + ck * omega * kInv4Pi * ni * h.h1.re;
-    K[0].im = -0.25 * omega * ni * w * h.h1.re;
-  } else {  // OP_HARD
-    const double ni = (t.nx * dx + t.ny * dy) * rinv;
-    const double Sre = -0.25 * w * h.h0.im - ck * kInv4Pi * h.h0.re;
-    const double Sim = 0.25 * w * h.h0.re;
-    const double Dre = 0.25 * omega * ni * w * h.h1.im + ck * omega * kInv4Pi * ni * h.h1.re;
-    const double Dim = -0.25 * omega * ni * w * h.h1.re;
-    const double g = (omega * omega / eta) * (t.nx * s.nx + t.ny * s.ny);
-    K[0] = {Sre, Sim};
-    // G = -i g S - D'
-    K[1] = {g * Sim - Dre, -g * Sre - Dim};
-  }
-  if (self) {
-#pragma unroll
-    for (int d = 0; d < Nd<OP>::v; ++d) K[d] = {0.0, 0.0};
-  }
-}
-
-// Kernel values of one ordered pair (i, j), i != j (self pairs return 0).
-template <int OP>
-__device__ __forceinline__ void pair_kernel(const Tgt& t, const SrcRec& s, double Ck, bool self,
-                                            double omega, double eta, double dt, cplx* K) {
-  const double dx = t.x - s.x, dy = t.y - s.y;
-  double r2 = fma(dx, dx, dy * dy);
-  r2 = self ? 1.0 : r2;
-  const double rinv = dp_rsqrt(r2);
-  const double r = r2 * rinv;
-  const H01 h = hankel01(omega * r);
-  assemble_pair<OP>(t, s, dx, dy, rinv, h, Ck, self, omega, eta, dt, K);
-}
-
-// Small-argument version (omega r < DP_HANKEL_ZA, the recurrence branch only).
-template <int OP>
-__device__ __forceinline__ void pair_kernel_near(const Tgt& t, const SrcRec& s, double Ck, double omega, double eta,
-                                                 double dt, cplx* K) {
-  const double dx = t.x - s.x, dy = t.y - s.y;
-  const double r2 = fma(dx, dx, dy * dy);
-  const double rinv = dp_rsqrt(r2);
-  const H01 h = hankel01_near(omega * r2 * rinv);
-  assemble_pair<OP>(t, s, dx, dy, rinv, h, Ck, false, omega, eta, dt, K);
-}
-
-// Branch-free version for pairs with omega r >= DP_HANKEL_ZA (asymptotic
-// branch only).  `near` reports whether the pair needs the other branch; its
-// values are then replaced by pair_kernel.
-template <int OP>
-__device__ __forceinline__ void pair_kernel_far(const Tgt& t, const SrcRec& s, double Ck, bool self,
-                                                double omega, double eta, double dt, cplx* K, bool& near) {
-  const double dx = t.x - s.x, dy = t.y - s.y;
-  double r2 = fma(dx, dx, dy * dy);
-  r2 = self ? 1.0 : r2;
-  const double rinv = dp_rsqrt(r2);
-  const double z = omega * r2 * rinv;
-  near = z < DP_HANKEL_ZA && !self;
-  const H01 h = hankel01_far(fmax(z, DP_HANKEL_ZA));
-  assemble_pair<OP>(t, s, dx, dy, rinv, h, Ck, self, omega, eta, dt, K);
-}
 
 template <int OP, int NR>
 __global__ __launch_bounds__(256) void sweep_private(SweepParams p) {
@@ -146,7 +53,7 @@ __global__ __launch_bounds__(256) void sweep_private(SweepParams p) {
     const SrcRec s = p.src[j];
     const double Ck = p.C[k];
     cplx K[ND];
-    pair_kernel<OP>(t, s, Ck, ii == j, p.omega, p.eta, p.dt, K);
+    pair_kernel_far<OP>(t, s, Ck, ii == j, p.omega, p.eta, p.dt, p.r2near, K);
     const cplx* dj = p.dens + (size_t)j * ND * NR;
 #pragma unroll
     for (int d = 0; d < ND; ++d)
@@ -193,7 +100,7 @@ __global__ __launch_bounds__(64 * WAVES) void sweep_shared(SweepParams p) {
       if (j < j1) {
         int k = ii - j;
         k += (k < 0) ? n : 0;
-        pair_kernel<OP>(t, p.src[j], p.C[k], ii == j, p.omega, p.eta, p.dt, K);
+        pair_kernel_far<OP>(t, p.src[j], p.C[k], ii == j, p.omega, p.eta, p.dt, p.r2near, K);
       } else {
 #pragma unroll
         for (int d = 0; d < ND; ++d) K[d] = {0.0, 0.0};
@@ -224,33 +131,82 @@ __global__ __launch_bounds__(64 * WAVES) void sweep_shared(SweepParams p) {
 }
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Precision traits of the matrix-core sweep.  FP64: v_mfma_f64_16x16x4,
+// result D[i][c] in register r of lane c + 16 (i mod 4), i = 4r + lane/16.
+// FP32: v_mfma_f32_16x16x4 (FP32 products and accumulation within a source
+// chunk), result D[i][c] in register r of lane c + 16 (i / 4),
+// i = 4 (lane/16) + r.  Either way A[i][k] sits in lane i + 16k and
+// B[k][c] in lane c + 16k.
+struct Mfma64 {
+  using C = cplx;
+  using V4 = dbl4;
+  static __device__ __forceinline__ V4 mma(double a, double b, V4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int lk) { return 4 * r + lk; }
+  static __device__ __forceinline__ const C* dens(const SweepParams& p) { return p.dens; }
+  static __device__ __forceinline__ C* partial(const SweepParams& p) { return p.partial; }
+  template <int OP>
+  static __device__ __forceinline__ void far(const Tgt& t, const SrcRec& s, double Ck, bool self,
+                                             const SweepParams& p, C* K) {
+    pair_kernel_far<OP>(t, s, Ck, self, p.omega, p.eta, p.dt, p.r2near, K);
+  }
+};
+
+struct Mfma32 {
+  using C = cplxf;
+  using V4 = flt4;
+  static __device__ __forceinline__ V4 mma(float a, float b, V4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int lk) { return 4 * lk + r; }
+  static __device__ __forceinline__ const C* dens(const SweepParams& p) { return p.dens32; }
+  static __device__ __forceinline__ C* partial(const SweepParams& p) { return p.partial32; }
+  template <int OP>
+  static __device__ __forceinline__ void far(const Tgt& t, const SrcRec& s, double Ck, bool self,
+                                             const SweepParams& p, C* K) {
+    pair_kernel_far32<OP>(t, s, Ck, self, p.omega, p.eta, p.dt, p.r2near, K);
+  }
+};
 
 // Many-column sweep on the matrix cores.  The contraction
 //   out_d[i][c] += sum_j K_d(i, j) dens_d[j][c]
 // is a dense complex GEMM whose left operand is generated on the fly: a
 // 16 x 4 tile of kernel values (16 targets x 4 sources, one pair per lane)
-// is exactly the A operand of v_mfma_f64_16x16x4 (A[i][k] in lane i + 16k),
-// and the densities of the same 4 sources for 16 columns are its B operand
-// (B[k][c] in lane c + 16k), read straight from the packed density array
-// (L2 / MALL resident, coalesced 16-column runs); with no barriers the two
-// waves sharing a SIMD drift out of phase.
-// Complex products take four real MFMAs (re.re, -im.im into the real
-// accumulator; re.im, im.re into the imaginary one); results land in
-// D[i][c] = register r of lane c + 16 (i mod 4), i = 4r + lane/16.
-// Block: 4 row groups x 16 targets = 64 targets; CH waves per row group split
-// the 16*NCBW*CH columns, so each wave keeps only its share of accumulators
-// and two waves fit per SIMD: the VALU work of one wave's kernel evaluation
-// overlaps the MFMA work of the other (each evaluates its own pairs).
-template <int OP, int NCBW>
+// is the A operand of a 16x16x4 MFMA, and the densities of the same 4
+// sources for 16 columns are its B operand.
+// Block: 8 waves = 4 row groups (16 targets each) x 2 column halves.  The
+// two waves of a row group evaluate alternate 4-source steps and swap their
+// kernel values through a double-buffered LDS slot (one barrier per pair of
+// steps), so every kernel value is computed once per block; each wave then
+// multiplies both steps into its own half of the columns.
+// The densities of a pair of steps (8 sources x ND x NC columns, one
+// contiguous run of the packed array) are staged once per block in a
+// double-buffered LDS tile: the block's threads request the next pair's tile
+// before the kernel evaluation and store it after the barrier, so the load
+// latency hides behind the evaluation and the four row groups share one copy.
+// The source record and C_k of a wave's next step are prefetched the same way.
+// Complex products take three real MFMAs: T1 += Kr Br, T2 += Ki Bi,
+// T3 += (Kr + Ki)(Br + Bi); Re = T1 - T2, Im = T3 - T1 - T2.
+template <int OP, int NCBW, class M>
 __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
+  using C = typename M::C;
+  using V4 = typename M::V4;
+  using R = decltype(C{}.re);
   constexpr int ND = Nd<OP>::v;
-  constexpr int NC = 32 * NCBW;        // columns of the block (two waves per row group)
-  __shared__ cplx Kx[2][4][2][ND][64];  // [buffer][row group][step parity][density][lane]
+  constexpr int NC = 32 * NCBW;            // columns of the block = nrp (two waves per row group)
+  constexpr int TILE = 8 * ND * NC;        // density tile of a pair of steps
+  constexpr int PER = (TILE + 511) / 512;  // tile elements per thread
+  __shared__ C Kx[2][4][2][ND][64];        // [buffer][row group][step parity][density][lane]
+  __shared__ C Bt[2][TILE];                // [buffer][(source * ND + density) * NC + column]
   const int n = p.n;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int rg = wv & 3;                // row group: 16 targets
-  const int ch = wv >> 2;               // column half; also the parity of the k-steps it evaluates
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int rg = wv & 3;                   // row group: 16 targets
+  const int ch = wv >> 2;                  // column half; also the parity of the k-steps it evaluates
   const int c0 = ch * 16 * NCBW;
   const int li = lane & 15, lk = lane >> 4;
   const int i = blockIdx.x * 64 + rg * 16 + li;
@@ -261,60 +217,93 @@ __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
   const int j1 = min(n, j0 + p.chunk_len);
   const int nsteps = (j1 - j0 + 3) / 4;
   const int npairs = (nsteps + 1) / 2;
-  // 3-multiplication complex products: T1 += Kr Br, T2 += Ki Bi,
-  // T3 += (Kr + Ki)(Br + Bi); then Re = T1 - T2, Im = T3 - T1 - T2.
-  dbl4 T1[ND][NCBW], T2[ND][NCBW], T3[ND][NCBW];
+  const C* dens = M::dens(p);
+  // tile rows past the chunk are clamped to its last source (finite values
+  // that meet zero kernel values)
+  auto load_tile = [&](int sp, C* reg) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 512 * q;
+      if (e < TILE) {
+        const int jr = e / (ND * NC);
+        const int j = min(j0 + 8 * sp + jr, j1 - 1);
+        reg[q] = dens[(size_t)j * ND * NC + (e - jr * ND * NC)];
+      }
+    }
+  };
+  auto store_tile = [&](int buf, const C* reg) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 512 * q;
+      if (e < TILE) Bt[buf][e] = reg[q];
+    }
+  };
+  V4 T1[ND][NCBW], T2[ND][NCBW], T3[ND][NCBW];
 #pragma unroll
   for (int d = 0; d < ND; ++d)
 #pragma unroll
     for (int cb = 0; cb < NCBW; ++cb) {
-      T1[d][cb] = dbl4{0.0, 0.0, 0.0, 0.0};
-      T2[d][cb] = dbl4{0.0, 0.0, 0.0, 0.0};
-      T3[d][cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+      T1[d][cb] = V4{0, 0, 0, 0};
+      T2[d][cb] = V4{0, 0, 0, 0};
+      T3[d][cb] = V4{0, 0, 0, 0};
     }
-  for (int sp = 0; sp < npairs; ++sp) {
-    // kernel values of this wave's k-step 2 sp + ch (target i, source j0 + 4 st + lk)
-    const int st = 2 * sp + ch;
-    const int j = j0 + 4 * st + lk;
-    const bool valid = j < j1;
-    const int jc = valid ? j : j1 - 1;
-    int k = ii - jc;
+  // source of this wave's k-step st: j = j0 + 4 st + lk (clamped into the chunk)
+  auto src_of = [&](int st, int& jc, int& k) {
+    jc = min(j0 + 4 * st + lk, j1 - 1);
+    k = ii - jc;
     k += (k < 0) ? n : 0;
-    const SrcRec sr = p.src[jc];
-    const double Ck = p.C[k];
-    cplx K[ND];
-    bool near;
-    pair_kernel_far<OP>(t, sr, Ck, ii == jc, p.omega, p.eta, p.dt, K, near);
-    if (__builtin_amdgcn_ballot_w64(near)) {
-      if (near) pair_kernel_near<OP>(t, sr, Ck, p.omega, p.eta, p.dt, K);
-    }
+  };
+  C breg[PER];
+  load_tile(0, breg);
+  store_tile(0, breg);  // read after the first barrier
+  int jc, k;
+  src_of(ch, jc, k);
+  SrcRec sr = p.src[jc];
+  double Ck = p.C[k];
+  for (int sp = 0; sp < npairs; ++sp) {
+    const int st = 2 * sp + ch;
+    const bool valid = j0 + 4 * st + lk < j1;
+    const bool self = ii == jc;
+    const bool more = sp + 1 < npairs;
+    if (more) load_tile(sp + 1, breg);
+    int jn, kn;
+    src_of(st + 2, jn, kn);  // clamped: the last iteration reloads a valid record
+    const SrcRec srn = p.src[jn];
+    const double Ckn = p.C[kn];
+
+    C K[ND];
+    M::template far<OP>(t, sr, Ck, self, p, K);
     const int buf = sp & 1;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-      K[d] = valid ? K[d] : cplx{0.0, 0.0};
+      K[d] = valid ? K[d] : C{0, 0};
       Kx[buf][rg][ch][d][lane] = K[d];
     }
     __syncthreads();
+    // every wave has left the previous pair's products: its tile buffer is free
+    if (more) store_tile(buf ^ 1, breg);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int sth = 2 * sp + h;
-      if (sth >= nsteps) break;
-      const int jh = min(j0 + 4 * sth + lk, j1 - 1);
-      const cplx* dj = p.dens + (size_t)jh * ND * NC + c0 + li;
+      if (2 * sp + h >= nsteps) break;
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
-        const cplx Kh = (h == ch) ? K[d] : Kx[buf][rg][h][d][lane];
-        const double ks = Kh.re + Kh.im;
+        const C Kh = (h == ch) ? K[d] : Kx[buf][rg][h][d][lane];
+        const R ks = Kh.re + Kh.im;
+        const C* bt = &Bt[buf][((4 * h + lk) * ND + d) * NC + c0 + li];
 #pragma unroll
         for (int cb = 0; cb < NCBW; ++cb) {
-          const cplx B = dj[d * NC + cb * 16];
-          T1[d][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Kh.re, B.re, T1[d][cb], 0, 0, 0);
-          T2[d][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Kh.im, B.im, T2[d][cb], 0, 0, 0);
-          T3[d][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ks, B.re + B.im, T3[d][cb], 0, 0, 0);
+          const C Bv = bt[cb * 16];
+          T1[d][cb] = M::mma(Kh.re, Bv.re, T1[d][cb]);
+          T2[d][cb] = M::mma(Kh.im, Bv.im, T2[d][cb]);
+          T3[d][cb] = M::mma(ks, Bv.re + Bv.im, T3[d][cb]);
         }
       }
     }
+    sr = srn;
+    Ck = Ckn;
+    jc = jn;
   }
+  C* part = M::partial(p);
   const int rbase = blockIdx.x * 64 + rg * 16;
 #pragma unroll
   for (int d = 0; d < ND; ++d)
@@ -322,13 +311,68 @@ __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
     for (int cb = 0; cb < NCBW; ++cb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = rbase + 4 * r + lk;
+        const int row = rbase + M::row(r, lk);
         if (row < n) {
-          const double t1 = T1[d][cb][r], t2 = T2[d][cb][r], t3 = T3[d][cb][r];
-          p.partial[(((size_t)blockIdx.y * ND + d) * NC + c0 + cb * 16 + li) * n + row] =
-              cplx{t1 - t2, t3 - t1 - t2};
+          const R t1 = T1[d][cb][r], t2 = T2[d][cb][r], t3 = T3[d][cb][r];
+          part[(((size_t)blockIdx.y * ND + d) * NC + c0 + cb * 16 + li) * n + row] = C{t1 - t2, t3 - t1 - t2};
         }
       }
+}
+
+// ------------------------------------------------------------ mixed precision
+// Private shape with FP32 kernel values; the few products per pair are
+// accumulated in FP64 (FP64 and FP32 VALU issue at the same rate here).
+template <int OP, int NR>
+__global__ __launch_bounds__(256) void sweep_private32(SweepParams p) {
+  constexpr int ND = Nd<OP>::v;
+  const int n = p.n;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const SrcRec tr = p.src[ii];
+  const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
+  const int j0 = blockIdx.y * p.chunk_len;
+  const int j1 = min(n, j0 + p.chunk_len);
+  cplx acc[ND][NR];
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[d][c] = {0.0, 0.0};
+  int k = ii - j0;
+  k += (k < 0) ? n : 0;
+  for (int j = j0; j < j1; ++j) {
+    const SrcRec s = p.src[j];
+    const double Ck = p.C[k];
+    cplxf K[ND];
+    pair_kernel_far32<OP>(t, s, Ck, ii == j, p.omega, p.eta, p.dt, p.r2near, K);
+    const cplx* dj = p.dens + (size_t)j * ND * NR;
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) cfma(acc[d][c], cplx{(double)K[d].re, (double)K[d].im}, dj[d * NR + c]);
+    k = (k == 0) ? n - 1 : k - 1;
+  }
+  if (i < n) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+        p.partial[(((size_t)blockIdx.y * ND + d) * NR + c) * n + i] = acc[d][c];
+  }
+}
+
+// dens[j][d][c] = in_d[c*n + j] (zero for padded columns c >= nrhs), FP32
+__global__ void pack_dens32(const cplx* __restrict__ a, const cplx* __restrict__ b, cplxf* __restrict__ dens,
+                            int n, int nrhs, int nrp, int nd, int col0) {
+  const size_t tot = (size_t)n * nrp * nd;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int c = idx % nrp;
+    const int d = (idx / nrp) % nd;
+    const size_t j = idx / ((size_t)nrp * nd);
+    const cplx* src = d == 0 ? a : b;
+    const cplx v = (c < nrhs) ? src[(size_t)(col0 + c) * n + j] : cplx{0.0, 0.0};
+    dens[idx] = {(float)v.re, (float)v.im};
+  }
 }
 
 // dens[j][d][c] = in_d[c*n + j] (zero for padded columns c >= nrhs)
@@ -342,64 +386,6 @@ __global__ void pack_dens(const cplx* __restrict__ a, const cplx* __restrict__ b
     const size_t j = idx / ((size_t)nrp * nd);
     const cplx* src = d == 0 ? a : b;
     dens[idx] = (c < nrhs) ? src[(size_t)(col0 + c) * n + j] : cplx{0.0, 0.0};
-  }
-}
-
-struct EpiParams {
-  const SrcRec* src;
-  const cplx* partial;
-  const cplx* q;       // density (n x nrhs), for diagonal and identity terms
-  const cplx* q2;      // second density (hard: sigma1) or null
-  cplx* out0;          // result (soft/layer) or u (hard)
-  cplx* out1;          // v (hard)
-  int n, nrhs, nrp, nchunks, op, col0;
-  double omega, eta, dt, R0;
-};
-
-// Sum chunk partials, add the diagonal (Kress limits) and identity terms.
-__global__ void sweep_epilogue(EpiParams e) {
-  const size_t tot = (size_t)e.n * e.nrhs;
-  const int nd = e.op == OP_HARD ? 2 : 1;
-  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int i = idx % e.n;
-    const int c = idx / e.n;
-    const SrcRec s = e.src[i];
-    const double sp = s.sp;
-    // S_ii = R0 (-sp/(4 pi)) + dt sp (i/4 - gamma/(2 pi) - log(omega sp/2)/(2 pi))
-    const cplx Sii = {e.R0 * (-sp * kInv4Pi) +
-                          e.dt * sp * (-kEulerGamma - log(0.5 * e.omega * sp)) * (2.0 * kInv4Pi),
-                      0.25 * e.dt * sp};
-    const double Dii = -e.dt * s.kappa * sp * kInv4Pi;  // D_ii = D'_ii
-    cplx sum[2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int ch = 0; ch < e.nchunks; ++ch)
-      for (int d = 0; d < nd; ++d) {
-        const cplx v = e.partial[(((size_t)ch * nd + d) * e.nrp + c) * e.n + i];
-        sum[d].re += v.re;
-        sum[d].im += v.im;
-      }
-    const cplx qi = e.q[(size_t)(e.col0 + c) * e.n + i];
-    const size_t o = (size_t)(e.col0 + c) * e.n + i;
-    if (e.op == OP_SOFT) {
-      // (1/2 + D_ii - i eta S_ii) q_i
-      const cplx a = {0.5 + Dii + e.eta * Sii.im, -e.eta * Sii.re};
-      cfma(sum[0], a, qi);
-      e.out0[o] = sum[0];
-    } else if (e.op == OP_S) {
-      cfma(sum[0], Sii, qi);
-      e.out0[o] = sum[0];
-    } else if (e.op == OP_D || e.op == OP_DP) {
-      cfma(sum[0], cplx{Dii, 0.0}, qi);
-      e.out0[o] = sum[0];
-    } else {
-      const cplx s1 = e.q2[(size_t)(e.col0 + c) * e.n + i];
-      cfma(sum[0], Sii, s1);
-      // G_ii = -i (omega^2/eta) S_ii - D'_ii
-      const double g = e.omega * e.omega / e.eta;
-      cfma(sum[1], cplx{g * Sii.im - Dii, -g * Sii.re}, qi);
-      e.out0[o] = sum[0];
-      e.out1[o] = sum[1];
-    }
   }
 }
 
@@ -434,9 +420,26 @@ static void launch_sweep(const SweepParams& sp, int nrp, hipStream_t st) {
     switch (nrp) {
       case 8: sweep_shared<OP, 2, 4><<<grid, 256, 0, st>>>(sp); break;
       case 16: sweep_shared<OP, 4, 4><<<grid, 256, 0, st>>>(sp); break;
-      case 32: sweep_mfma<OP, 1><<<grid, 512, 0, st>>>(sp); break;
-      default: sweep_mfma<OP, 2><<<grid, 512, 0, st>>>(sp); break;
+      case 32: sweep_mfma<OP, 1, Mfma64><<<grid, 512, 0, st>>>(sp); break;
+      default: sweep_mfma<OP, 2, Mfma64><<<grid, 512, 0, st>>>(sp); break;
     }
+  }
+}
+
+template <int OP>
+static void launch_sweep32(const SweepParams& sp, int nrp, hipStream_t st) {
+  const int n = sp.n;
+  if (nrp <= 4) {
+    dim3 grid((n + 255) / 256, sp.nchunks);
+    switch (nrp) {
+      case 1: sweep_private32<OP, 1><<<grid, 256, 0, st>>>(sp); break;
+      case 2: sweep_private32<OP, 2><<<grid, 256, 0, st>>>(sp); break;
+      default: sweep_private32<OP, 4><<<grid, 256, 0, st>>>(sp); break;
+    }
+  } else {
+    dim3 grid((n + 63) / 64, sp.nchunks);
+    if (nrp == 32) sweep_mfma<OP, 1, Mfma32><<<grid, 512, 0, st>>>(sp);
+    else sweep_mfma<OP, 2, Mfma32><<<grid, 512, 0, st>>>(sp);
   }
 }
 
@@ -449,11 +452,13 @@ static int pad_cols(int nrhs) {
 // Core sweep over one group of <= 64 columns.  a (and b for hard) are the
 // densities; results go to out0 (and out1).
 static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a, const cplx* b,
-                       cplx* out0, cplx* out1) {
+                       cplx* out0, cplx* out1, int prec) {
   hipStream_t st = p->ctx->stream;
   const int n = (int)p->n;
   const int nd = op == OP_HARD ? 2 : 1;
-  const int nrp = pad_cols(nrhs);
+  int nrp = pad_cols(nrhs);
+  if (prec && nrp > 4 && nrp < 32) nrp = 32;  // matrix-core shape for every multi-column mixed sweep
+  const bool part32 = prec && nrp > 4;
   const int rows_per_block = nrp <= 4 ? 256 : 64;
   const int bx = (n + rows_per_block - 1) / rows_per_block;
   int nchunks = (2048 + bx - 1) / bx;
@@ -467,13 +472,18 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   DP_TRY(p->partial.reserve((size_t)nchunks * nd * nrp * n * sizeof(cplx)));
   {
     size_t tot = (size_t)n * nrp * nd;
-    pack_dens<<<grid1d(tot), 256, 0, st>>>(a, b, p->dens.as<cplx>(), n, nrhs, nrp, nd, col0);
+    if (part32)
+      pack_dens32<<<grid1d(tot), 256, 0, st>>>(a, b, reinterpret_cast<cplxf*>(p->dens.p), n, nrhs, nrp, nd, col0);
+    else
+      pack_dens<<<grid1d(tot), 256, 0, st>>>(a, b, p->dens.as<cplx>(), n, nrhs, nrp, nd, col0);
   }
   SweepParams sp;
   sp.src = p->src.as<SrcRec>();
   sp.C = p->C.as<double>();
   sp.dens = p->dens.as<cplx>();
   sp.partial = p->partial.as<cplx>();
+  sp.dens32 = reinterpret_cast<const cplxf*>(p->dens.p);
+  sp.partial32 = reinterpret_cast<cplxf*>(p->partial.p);
   sp.n = n;
   sp.nrp = nrp;
   sp.nd = nd;
@@ -482,19 +492,33 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   sp.omega = p->omega;
   sp.eta = p->eta;
   sp.dt = 2.0 * kPi / n;
-  p->clock.start(st);
-  switch (op) {
-    case OP_SOFT: launch_sweep<OP_SOFT>(sp, nrp, st); break;
-    case OP_HARD: launch_sweep<OP_HARD>(sp, nrp, st); break;
-    case OP_S: launch_sweep<OP_S>(sp, nrp, st); break;
-    case OP_D: launch_sweep<OP_D>(sp, nrp, st); break;
-    default: launch_sweep<OP_DP>(sp, nrp, st); break;
+  sp.r2near = p->r2near;
+  SweepClock& clk = prec ? p->clock32 : p->clock;
+  clk.start(st);
+  if (prec) {
+    switch (op) {
+      case OP_SOFT: launch_sweep32<OP_SOFT>(sp, nrp, st); break;
+      case OP_HARD: launch_sweep32<OP_HARD>(sp, nrp, st); break;
+      case OP_S: launch_sweep32<OP_S>(sp, nrp, st); break;
+      case OP_D: launch_sweep32<OP_D>(sp, nrp, st); break;
+      default: launch_sweep32<OP_DP>(sp, nrp, st); break;
+    }
+  } else {
+    switch (op) {
+      case OP_SOFT: launch_sweep<OP_SOFT>(sp, nrp, st); break;
+      case OP_HARD: launch_sweep<OP_HARD>(sp, nrp, st); break;
+      case OP_S: launch_sweep<OP_S>(sp, nrp, st); break;
+      case OP_D: launch_sweep<OP_D>(sp, nrp, st); break;
+      default: launch_sweep<OP_DP>(sp, nrp, st); break;
+    }
   }
-  p->clock.stop(st);
+  clk.stop(st);
   DP_HIP(hipGetLastError());
+  DP_TRY(near_apply_group(p, op, nrp, p->dens.p, part32));
   EpiParams e;
   e.src = sp.src;
   e.partial = sp.partial;
+  e.nearp = p->near_nnz > 0 ? p->near_out.as<cplx>() : nullptr;
   e.q = op == OP_HARD ? b : a;
   e.q2 = op == OP_HARD ? a : nullptr;
   e.out0 = out0;
@@ -509,7 +533,8 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   e.eta = p->eta;
   e.dt = sp.dt;
   e.R0 = p->R0;
-  sweep_epilogue<<<grid1d((size_t)n * nrhs), 256, 0, st>>>(e);
+  if (part32) sweep_epilogue<cplxf><<<grid1d((size_t)n * nrhs), 256, 0, st>>>(e);
+  else sweep_epilogue<cplx><<<grid1d((size_t)n * nrhs), 256, 0, st>>>(e);
   DP_HIP(hipGetLastError());
   return DP_OK;
 }
@@ -547,16 +572,16 @@ void SweepClock::destroy() {
   used = 0;
 }
 
-int sweep_apply(dp_problem* p, int op, int nrhs, const cplx* q, cplx* y) {
+int sweep_apply(dp_problem* p, int op, int nrhs, const cplx* q, cplx* y, int prec) {
   for (int c0 = 0; c0 < nrhs; c0 += 64) {
     const int nc = nrhs - c0 < 64 ? nrhs - c0 : 64;
-    DP_TRY(sweep_group(p, op, nc, c0, q, nullptr, y, nullptr));
+    DP_TRY(sweep_group(p, op, nc, c0, q, nullptr, y, nullptr, prec));
   }
   return DP_OK;
 }
 
-int matvec(dp_problem* p, int nrhs, const cplx* q, cplx* y) {
-  if (p->kind == DP_SOFT) return sweep_apply(p, OP_SOFT, nrhs, q, y);
+int matvec(dp_problem* p, int nrhs, const cplx* q, cplx* y, int prec) {
+  if (p->kind == DP_SOFT) return sweep_apply(p, OP_SOFT, nrhs, q, y, prec);
   const size_t tot = (size_t)p->n * nrhs;
   DP_TRY(p->tmp1.reserve(tot * sizeof(cplx)));
   DP_TRY(p->tmp2.reserve(tot * sizeof(cplx)));
@@ -567,7 +592,7 @@ int matvec(dp_problem* p, int nrhs, const cplx* q, cplx* y) {
   DP_TRY(spectral_derivative(p, nrhs, q, sig));
   for (int c0 = 0; c0 < nrhs; c0 += 64) {
     const int nc = nrhs - c0 < 64 ? nrhs - c0 : 64;
-    DP_TRY(sweep_group(p, OP_HARD, nc, c0, sig, q, u, v));
+    DP_TRY(sweep_group(p, OP_HARD, nc, c0, sig, q, u, v, prec));
   }
   DP_TRY(spectral_derivative(p, nrhs, u, sig));
   hard_combine<<<grid1d(tot), 256, 0, p->ctx->stream>>>(q, v, sig, y, tot, p->eta);

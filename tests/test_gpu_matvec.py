@@ -68,6 +68,36 @@ def test_hard_kite_matvec(nrhs):
     assert relerr(to_host(y), A @ q) < TOL
 
 
+# Pairs with omega r < 25 take the small-argument Hankel branch in a separate
+# near-field pass.  omega = 3 on the unit disk puts every pair there (a dense,
+# unbanded near list); omega = 30 puts about a quarter of them there; the
+# kite at 40 points per wavelength has long near bands in every row.
+@pytest.mark.parametrize("kind,omega,nrhs", [(0, 3.0, 1), (1, 3.0, 70), (0, 30.0, 64), (1, 30.0, 5)])
+def test_near_field_heavy_disk(kind, omega, nrhs):
+    b = sample_boundary("disk", 512)
+    A = ny.cfie_matrix(b, omega, omega, kind)
+    q = random_density(b.n, nrhs, seed=13)
+    p = problem(b, omega, omega, kind)
+    y = empty(b.n, nrhs)
+    dp.dp_matvec(p, to_dev(q), y)
+    assert relerr(to_host(y), A @ q) < TOL
+
+
+@pytest.mark.parametrize("nrhs", [2, 32])
+def test_near_field_dense_bands_kite(nrhs):
+    b = sample_boundary("kite", 2048)
+    om = omega_for_ppw(2048, b.L, 40.0)
+    A = ny.hard_matrix(b, om, om)
+    q = random_density(b.n, nrhs, seed=17)
+    p = problem(b, om, om, 1)
+    y = empty(b.n, nrhs)
+    dp.dp_matvec(p, to_dev(q), y)
+    assert relerr(to_host(y), A @ q) < TOL
+    y32 = empty(b.n, nrhs)
+    dp.dp_matvec_mixed(p, to_dev(q), y32)
+    assert relerr(to_host(y32), A @ q) < 1e-5
+
+
 @pytest.mark.parametrize("op,name", [(dp.DP_OP_S, "S"), (dp.DP_OP_D, "D"), (dp.DP_OP_DP, "Dp")])
 def test_layers(op, name):
     b = sample_boundary("randstar2", 1000)
