@@ -7,8 +7,8 @@
 //   * z >= DP_HANKEL_ZA: Hankel's asymptotic expansion (DLMF 10.17.5),
 //       H_nu(z) ~ sqrt(2/(pi z)) e^{i(z - nu pi/2 - pi/4)} sum_k i^k a_k(nu) z^-k,
 //       a_k(nu) = prod_{m=1..k} (4 nu^2 - (2m-1)^2) / (k! 8^k),
-//     truncated after DP_HANKEL_NTERMS terms (truncation error < 1e-17 at
-//     z = DP_HANKEL_ZA);
+//     whose even and odd parts P_nu, Q_nu are polynomials in u = 1/z^2,
+//     economized on [0, 1/DP_HANKEL_ZA^2] (hankel_poly.hpp, error < 1e-17);
 //   * z < DP_HANKEL_ZA: J_0, J_1 by Miller's backward recurrence
 //     J_{k-1} = (2k/z) J_k - J_{k+1} normalised by J_0 + 2 sum J_{2k} = 1
 //     (DLMF 10.74(iv), 10.12.4), Y_0 by Neumann's series (DLMF 10.23.?:
@@ -17,11 +17,14 @@
 //       Y_1 = (2/pi)[-J_0/z + (ln(z/2)+gamma) J_1 - J_1
 //              + sum_{m>=1} (-1)^{m+1} (2m+1)/(m(m+1)) J_{2m+1}].
 // sin/cos: x = k pi/2 + r, |r| <= pi/4, with pi/2 split in two doubles and
-// fused multiply-adds, then the Taylor series of sin and cos in r.
+// fused multiply-adds, then the Taylor series of sin and cos in r economized
+// on the reduced range (hankel_poly.hpp).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include "hankel_poly.hpp"
 
 #define DP_HD __host__ __device__ __forceinline__
 
@@ -51,25 +54,20 @@ DP_HD void cfma(cplx& acc, cplx a, cplx b) {
 }
 
 // --------------------------------------------------------------- sin / cos
-// 1/(2k+1)! and 1/(2k)! built from their definition at compile time.
-constexpr double inv_fact(int k) {
-  double f = 1.0;
-  for (int i = 2; i <= k; ++i) f *= i;
-  return 1.0 / f;
+// Horner evaluation of sum_k c[k] x^k.
+template <class T, int N>
+DP_HD T horner(const T (&c)[N], T x) {
+  T p = c[N - 1];
+#pragma unroll
+  for (int k = N - 2; k >= 0; --k) p = fma(p, x, c[k]);
+  return p;
 }
 
+// sin r = r + r v S(v), cos r = 1 + v C(v), v = r^2, |r| <= pi/4.
 DP_HD void sincos_reduced(double r, double& s, double& c) {
-  const double r2 = r * r;
-  // sin r = r + r^3 sum_{k=1..8} (-1)^k r^{2k-2}/(2k+1)!   (|r| <= pi/4)
-  double ps = inv_fact(17);
-#pragma unroll
-  for (int k = 7; k >= 1; --k) ps = fma(ps, r2, ((k & 1) ? -1.0 : 1.0) * inv_fact(2 * k + 1));
-  s = fma(ps * r2, r, r);
-  // cos r = 1 + r^2 sum_{k=1..9} (-1)^k r^{2k-2}/(2k)!
-  double pc = -inv_fact(18);
-#pragma unroll
-  for (int k = 8; k >= 1; --k) pc = fma(pc, r2, ((k & 1) ? -1.0 : 1.0) * inv_fact(2 * k));
-  c = fma(pc, r2, 1.0);
+  const double v = r * r;
+  s = fma(r * v, horner(kSinS, v), r);
+  c = fma(v, horner(kCosC, v), 1.0);
 }
 
 // sin and cos of x for |x| < 2^40.
@@ -96,41 +94,20 @@ DP_HD double dp_rsqrt(double z) {
 }
 
 // --------------------------------------------------------------- Hankel
-constexpr double DP_HANKEL_ZA = 25.0;
-constexpr int DP_HANKEL_NTERMS = 19;  // k = 0..18
-
-// a_k(nu) of the Hankel expansion, from its product definition.
-constexpr double hankel_a(int k, int nu) {
-  double p = 1.0;
-  for (int m = 1; m <= k; ++m) p *= (4.0 * nu * nu - (2.0 * m - 1) * (2.0 * m - 1)) / (8.0 * m);
-  return p;
-}
+constexpr double DP_HANKEL_ZA = kHankelZA;  // branch point; the far polynomials are fitted above it
 
 struct H01 {
   cplx h0, h1;
 };
 
-// Asymptotic branch, z >= DP_HANKEL_ZA.  P + iQ = sum_k i^k a_k t^k, t = 1/z.
+// Asymptotic branch, z >= DP_HANKEL_ZA: H_nu = sqrt(2/(pi z)) e^{i(z - nu pi/2 - pi/4)}
+// (P_nu + i Q_nu), P_nu and Q_nu/t polynomials in u = t^2, t = 1/z.
 DP_HD H01 hankel01_far(double z) {
   const double y = dp_rsqrt(z);
   const double t = y * y;
-  const double t2 = t * t;
-  // P_nu = sum_j a_{2j} (-t^2)^j, Q_nu = t sum_j a_{2j+1} (-t^2)^j  (Horner in -t^2)
-  const double u = -t2;
-  double p0 = hankel_a(18, 0), p1 = hankel_a(18, 1);
-#pragma unroll
-  for (int k = 16; k >= 0; k -= 2) {
-    p0 = fma(p0, u, hankel_a(k, 0));
-    p1 = fma(p1, u, hankel_a(k, 1));
-  }
-  double q0 = hankel_a(17, 0), q1 = hankel_a(17, 1);
-#pragma unroll
-  for (int k = 15; k >= 1; k -= 2) {
-    q0 = fma(q0, u, hankel_a(k, 0));
-    q1 = fma(q1, u, hankel_a(k, 1));
-  }
-  q0 *= t;
-  q1 *= t;
+  const double u = t * t;
+  const double p0 = horner(kHankP0, u), p1 = horner(kHankP1, u);
+  const double q0 = horner(kHankQ0, u) * t, q1 = horner(kHankQ1, u) * t;
   double s, c;
   dp_sincos(z, s, c);
   const double m = kSqrt2OverPi * y * kInvSqrt2;
@@ -206,26 +183,16 @@ DP_HD float dp_rsqrtf(float z) {
 
 // Asymptotic branch for z >= DP_HANKEL_ZA with FP32 arithmetic: the phase z
 // is reduced modulo pi/2 in FP64 (|z| up to 1e6 keeps ~1e-16 absolute phase
-// error), everything after the reduction is FP32.  Terms k <= 6 of the
-// expansion (truncation < 3e-10 at z = 25); sin/cos of the reduced argument
-// by their Taylor series to r^9 / r^10.  Relative accuracy ~3e-7.
+// error), everything after the reduction is FP32 with the FP32-economized
+// polynomials (approximation error < 4e-9).  Relative accuracy ~3e-7.
 DP_HD H01f hankel01_far32(double z) {
   const double kq = rint(z * kTwoOverPi);
   double rr = fma(-kq, kPio2Hi, z);
   rr = fma(-kq, kPio2Lo, rr);
-  const float r = (float)rr, r2 = r * r;
-  float ps = (float)inv_fact(9);
-  ps = fmaf(ps, r2, -(float)inv_fact(7));
-  ps = fmaf(ps, r2, (float)inv_fact(5));
-  ps = fmaf(ps, r2, -(float)inv_fact(3));
-  const float sr = fmaf(ps * r2, r, r);
-  float pc = -(float)inv_fact(10);
-  pc = fmaf(pc, r2, (float)inv_fact(8));
-  pc = fmaf(pc, r2, -(float)inv_fact(6));
-  pc = fmaf(pc, r2, (float)inv_fact(4));
-  pc = fmaf(pc, r2, -(float)inv_fact(2));
-  const float cr = fmaf(pc, r2, 1.0f);
-  const long long q = (long long)kq & 3;
+  const float r = (float)rr, v = r * r;
+  const float sr = fmaf(r * v, horner(kSinS32, v), r);
+  const float cr = fmaf(v, horner(kCosC32, v), 1.0f);
+  const int q = (int)kq & 3;  // kq < 2^31 for z < 3e9
   const float s1 = (q & 1) ? cr : sr;
   const float c1 = (q & 1) ? sr : cr;
   const float s = (q & 2) ? -s1 : s1;
@@ -233,19 +200,9 @@ DP_HD H01f hankel01_far32(double z) {
   const float zf = (float)z;
   const float y = dp_rsqrtf(zf);
   const float t = y * y;
-  const float u = -t * t;
-  float p0 = (float)hankel_a(6, 0), p1 = (float)hankel_a(6, 1);
-  p0 = fmaf(p0, u, (float)hankel_a(4, 0));
-  p1 = fmaf(p1, u, (float)hankel_a(4, 1));
-  p0 = fmaf(p0, u, (float)hankel_a(2, 0));
-  p1 = fmaf(p1, u, (float)hankel_a(2, 1));
-  p0 = fmaf(p0, u, 1.0f);
-  p1 = fmaf(p1, u, 1.0f);
-  float q0 = (float)hankel_a(5, 0), q1 = (float)hankel_a(5, 1);
-  q0 = fmaf(q0, u, (float)hankel_a(3, 0));
-  q1 = fmaf(q1, u, (float)hankel_a(3, 1));
-  q0 = fmaf(q0, u, (float)hankel_a(1, 0)) * t;
-  q1 = fmaf(q1, u, (float)hankel_a(1, 1)) * t;
+  const float u = t * t;
+  const float p0 = horner(kHankP032, u), p1 = horner(kHankP132, u);
+  const float q0 = horner(kHankQ032, u) * t, q1 = horner(kHankQ132, u) * t;
   const float m = (float)(kSqrt2OverPi * kInvSqrt2) * y;
   const cplxf e0 = {(c + s) * m, (s - c) * m};
   const cplxf e1 = {(s - c) * m, -(s + c) * m};
