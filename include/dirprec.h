@@ -158,7 +158,9 @@ typedef struct {
                        FP64 geometry, phase reduction, small-argument Hankel
                        values, diagonal terms, Krylov vectors and Givens
                        rotations) and whose residuals f - A q are FP64 */
-  double inner_tol; /* mixed: relative tolerance of each correction solve; default 1e-5 */
+  double inner_tol; /* mixed: relative tolerance of the correction solves, at least the one
+                       that takes every column from its current FP64 residual r to
+                       tol/10 (0.1 tol/r for the worst column); default 1e-5 */
 } dp_solve_opts;
 
 typedef struct {

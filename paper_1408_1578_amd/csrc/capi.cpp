@@ -137,7 +137,10 @@ int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nr
     p->hsp[i] = w[i] * (double)n / (2.0 * kPi);
     p->hkap[i] = kappa[i];
     L += w[i];
-    rec[i] = {p->hx[i], p->hy[i], p->hnx[i], p->hny[i], p->hsp[i], p->hkap[i], 0.0, 0.0};
+    rec[i] = {p->hx[i],        p->hy[i],        p->hnx[i],
+              p->hny[i],       p->hsp[i],       p->hkap[i],
+              (float)p->hnx[i], (float)p->hny[i], (float)(2.0 * kPi / (double)n * p->hsp[i]),
+              (float)p->hsp[i]};
   }
   p->L = L;
   int rc = p->src.reserve(n * sizeof(SrcRec));

@@ -41,9 +41,14 @@ struct DevBuf {
 };
 
 // One source record: geometry of node j, 64 bytes so one scalar load fetches it.
+// One boundary node (64 bytes): position, outward normal, speed |x'(t)| and
+// curvature in FP64, and FP32 copies of the normal, the trapezoid weight
+// (2 pi/n) |x'(t)| and the speed for the single-precision sweep.
 struct SrcRec {
-  double x, y, nx, ny, sp, kappa, pad0, pad1;
+  double x, y, nx, ny, sp, kappa;
+  float nxf, nyf, wf, spf;
 };
+static_assert(sizeof(SrcRec) == 64, "SrcRec is one 64-byte record");
 
 enum SweepOp { OP_SOFT = 0, OP_HARD = 1, OP_S = 2, OP_D = 3, OP_DP = 4 };
 

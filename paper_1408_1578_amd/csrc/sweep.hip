@@ -167,7 +167,7 @@ struct Mfma32 {
   template <int OP>
   static __device__ __forceinline__ void far(const Tgt& t, const SrcRec& s, double Ck, bool self,
                                              const SweepParams& p, C* K) {
-    pair_kernel_far32<OP>(t, s, Ck, self, p.omega, p.eta, p.dt, p.r2near, K);
+    pair_kernel_far32<OP>(t, s, Ck, self, p.omega, p.eta, p.r2near, K);
   }
 };
 
@@ -184,7 +184,8 @@ struct Mfma32 {
 // multiplies both steps into its own half of the columns.
 // The densities of a pair of steps (8 sources x ND x NC columns, one
 // contiguous run of the packed array) are staged once per block in a
-// double-buffered LDS tile: the block's threads request the next pair's tile
+// double-buffered LDS tile, with the sums re + im that the 3-multiplication
+// products need: the block's threads request the next pair's tile
 // before the kernel evaluation and store it after the barrier, so the load
 // latency hides behind the evaluation and the four row groups share one copy.
 // The source record and C_k of a wave's next step are prefetched the same way.
@@ -201,6 +202,7 @@ __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
   constexpr int PER = (TILE + 511) / 512;  // tile elements per thread
   __shared__ C Kx[2][4][2][ND][64];        // [buffer][row group][step parity][density][lane]
   __shared__ C Bt[2][TILE];                // [buffer][(source * ND + density) * NC + column]
+  __shared__ R Bs[2][TILE];                // re + im of the same entries (3-multiplication products)
   const int n = p.n;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -218,24 +220,28 @@ __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
   const int nsteps = (j1 - j0 + 3) / 4;
   const int npairs = (nsteps + 1) / 2;
   const C* dens = M::dens(p);
-  // tile rows past the chunk are clamped to its last source (finite values
-  // that meet zero kernel values)
+  // Tile rows past the chunk are clamped to its last source (finite values
+  // that meet zero kernel values).  Every thread issues exactly PER loads
+  // (indices clamped into the tile, extra elements discarded at the store)
+  // so the number of loads in flight is the same on every path and the
+  // compiler's wait counts stay partial.
   auto load_tile = [&](int sp, C* reg) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = tid + 512 * q;
-      if (e < TILE) {
-        const int jr = e / (ND * NC);
-        const int j = min(j0 + 8 * sp + jr, j1 - 1);
-        reg[q] = dens[(size_t)j * ND * NC + (e - jr * ND * NC)];
-      }
+      const int e = min(tid + 512 * q, TILE - 1);
+      const int jr = e / (ND * NC);
+      const int j = min(j0 + 8 * sp + jr, j1 - 1);
+      reg[q] = dens[(size_t)j * ND * NC + (e - jr * ND * NC)];
     }
   };
   auto store_tile = [&](int buf, const C* reg) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = tid + 512 * q;
-      if (e < TILE) Bt[buf][e] = reg[q];
+      if (e < TILE) {
+        Bt[buf][e] = reg[q];
+        Bs[buf][e] = reg[q].re + reg[q].im;
+      }
     }
   };
   V4 T1[ND][NCBW], T2[ND][NCBW], T3[ND][NCBW];
@@ -265,7 +271,7 @@ __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
     const bool valid = j0 + 4 * st + lk < j1;
     const bool self = ii == jc;
     const bool more = sp + 1 < npairs;
-    if (more) load_tile(sp + 1, breg);
+    load_tile(sp + 1, breg);  // past the last pair: clamped rows, never stored
     int jn, kn;
     src_of(st + 2, jn, kn);  // clamped: the last iteration reloads a valid record
     const SrcRec srn = p.src[jn];
@@ -289,13 +295,13 @@ __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
       for (int d = 0; d < ND; ++d) {
         const C Kh = (h == ch) ? K[d] : Kx[buf][rg][h][d][lane];
         const R ks = Kh.re + Kh.im;
-        const C* bt = &Bt[buf][((4 * h + lk) * ND + d) * NC + c0 + li];
+        const int o = ((4 * h + lk) * ND + d) * NC + c0 + li;
 #pragma unroll
         for (int cb = 0; cb < NCBW; ++cb) {
-          const C Bv = bt[cb * 16];
+          const C Bv = Bt[buf][o + cb * 16];
           T1[d][cb] = M::mma(Kh.re, Bv.re, T1[d][cb]);
           T2[d][cb] = M::mma(Kh.im, Bv.im, T2[d][cb]);
-          T3[d][cb] = M::mma(ks, Bv.re + Bv.im, T3[d][cb]);
+          T3[d][cb] = M::mma(ks, Bs[buf][o + cb * 16], T3[d][cb]);
         }
       }
     }
@@ -343,7 +349,7 @@ __global__ __launch_bounds__(256) void sweep_private32(SweepParams p) {
     const SrcRec s = p.src[j];
     const double Ck = p.C[k];
     cplxf K[ND];
-    pair_kernel_far32<OP>(t, s, Ck, ii == j, p.omega, p.eta, p.dt, p.r2near, K);
+    pair_kernel_far32<OP>(t, s, Ck, ii == j, p.omega, p.eta, p.r2near, K);
     const cplx* dj = p.dens + (size_t)j * ND * NR;
 #pragma unroll
     for (int d = 0; d < ND; ++d)
