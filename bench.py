@@ -33,6 +33,12 @@ METRIC = "CFIE solves/s at n=32768 to 1e-8 residual (mixed vs FP64); p50/p99 lat
 PEAK_FP64_VALU = 78.6
 # dense FP32 matrix-core peak, TFLOP/s (the mixed-precision correction sweeps)
 PEAK_FP32_MFMA = 157.3
+# HBM bytes per launch of the two 64-column hard sweeps at n = 32768 (rocprofv3
+# FETCH_SIZE and WRITE_SIZE, scaled by the counts of a 512 MiB device copy in
+# the same run).  They describe the current kernels; a changed kernel must be
+# measured again before these are reported.
+TRAFFIC_FP32_SWEEP = 0.6905e9
+TRAFFIC_FP64_SWEEP = 1.3985e9
 
 # Algorithmic FP64 flops of one ordered pair in the sound-hard sweep (far-field
 # evaluation path; an FMA counts 2): geometry 5, 1/r 8, r and z 2, H0/H1 142,
@@ -218,14 +224,16 @@ def main():
         roof = {"kernel": "sweep_mfma<hard, 64 columns, FP32> (FP32 kernel values and v_mfma_f32_16x16x4 "
                           "products, FP64 phase reduction; 8 waves, shared kernel values, LDS density tiles)",
                 "bound": "mfma", "achieved": sw["tflops"], "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-                "frac": sw["tflops"] / PEAK_FP32_MFMA, "traffic": None, "launch_ms": sw["launch_ms"],
+                "frac": sw["tflops"] / PEAK_FP32_MFMA,
+                "traffic": TRAFFIC_FP32_SWEEP if (b.n == 32768 and nrhs == 64) else None, "launch_ms": sw["launch_ms"],
                 "launches": sw["launches"], "flops_per_launch": flops}
     else:
         sw = main_run["sweep_fp64"]
         roof = {"kernel": "sweep_mfma<hard, 64 columns, FP64> (v_mfma_f64_16x16x4 products; 8 waves, "
                           "shared kernel values, LDS density tiles)",
                 "bound": "mfma", "achieved": sw["tflops"], "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
-                "frac": sw["tflops"] / PEAK_FP64_VALU, "traffic": None, "launch_ms": sw["launch_ms"],
+                "frac": sw["tflops"] / PEAK_FP64_VALU,
+                "traffic": TRAFFIC_FP64_SWEEP if (b.n == 32768 and nrhs == 64) else None, "launch_ms": sw["launch_ms"],
                 "launches": sw["launches"], "flops_per_launch": flops}
     out = {
         "metric": METRIC,
