@@ -110,6 +110,9 @@ typedef struct {
   int min_pts;     /* never split a segment below this many points; default 8 */
   int m_c;         /* Chebyshev grid size for e_ij (Sec. 3: 10); default 10 */
   double t_keep;   /* floor(T_i) keeps ~t_keep*|K_i| entries (Sec. 2.2); 0 = all; default 3 */
+  int w_solver;    /* factorisation of floor(W): 0 = automatic (host sparse LU unless the
+                      fill-reducing ordering predicts more than max(1.5e6, 8 nnz) factor
+                      entries, then dense LU on the device), 1 = sparse, 2 = dense; default 0 */
 } dp_precond_opts;
 
 typedef struct {
@@ -119,14 +122,16 @@ typedef struct {
   int64_t nnzE;       /* m (m - 1) */
   int64_t nnzW;       /* non-zeros of floor(W) */
   int64_t nnzLU;      /* non-zeros of its sparse LU factors */
-  int64_t levels;     /* dependency levels of the two triangular solves */
+  int64_t levels;     /* dependency levels of the two triangular solves (sparse) */
   double t_setup;     /* seconds spent in dp_precond_build */
+  int64_t dense_w;    /* 1 when floor(W) was factored densely on the device (nnzLU = NW^2) */
 } dp_precond_info;
 
 /* Build the directional preconditioner of Sec. 2 (segments, flat blocks B_j,
  * partial Fourier factors U_i, S_i = U_i^t B_i^{-1} U_i, T_i = S_i^{-1},
  * floor(T_i), rank-1 entries e_ij of eq. (14), floor(W) = E + antidiag(T) and
- * its sparse LU).  opts may be NULL (defaults).  Requires arclength-
+ * its LU: sparse with minimum-degree ordering on the host, or dense with
+ * partial pivoting on the device when the sparse factors would fill in).  opts may be NULL (defaults).  Requires arclength-
  * equispaced nodes (all w_j equal within 1e-12 relative), else DP_EINVAL;
  * DP_ESINGULAR on a zero pivot. */
 int dp_precond_build(dp_problem* p, const dp_precond_opts* opts);
@@ -187,6 +192,64 @@ typedef struct {
  * DP_OK or DP_ENOCONV. */
 int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_solve_opts* opts,
              dp_solve_info* info, int64_t* iters, double* relres);
+
+/* ------------------------------------------------------------------ serving */
+/* A request server for streams of independent solves (different n, omega,
+ * geometries, boundary conditions and right-hand-side counts).  Each request
+ * is the whole path of Sec. 1-3: problem set-up, the directional
+ * preconditioner of Sec. 2 (optional), plane-wave or given data, and the
+ * GMRES solve.  The server owns `slots` worker threads, each with its own
+ * context and HIP stream; a free worker admits the oldest queued request once
+ * its estimated device-memory footprint fits in the budget next to the
+ * requests already running, so requests that arrive while others are on the
+ * GPU start as soon as a slot and memory free up and their kernels overlap
+ * on the device.  A request's result does not depend on what else runs: it
+ * executes the same kernels on its own buffers and stream as it would alone. */
+typedef struct dp_server dp_server;
+
+typedef struct {
+  int slots;           /* concurrent requests (worker threads); default 4, 1..64 */
+  int64_t mem_budget;  /* bytes of device memory the admitted requests may hold by
+                          estimate; 0 = 80% of the free memory at creation */
+} dp_server_opts;
+
+typedef struct {
+  int64_t n;                   /* as dp_problem_create; the host arrays are copied by submit */
+  const double *xy, *nrm, *w, *kappa;
+  double omega, eta;
+  int kind;                    /* DP_SOFT or DP_HARD */
+  int64_t nrhs;                /* >= 1 */
+  const double* angles;        /* host, nrhs plane-wave angles (dp_rhs_plane_wave), or NULL */
+  const double* f;             /* host n x nrhs complex data, used when angles == NULL */
+  dp_solve_opts solve;         /* use_precond = 1 builds the preconditioner (default options) */
+} dp_request;
+
+typedef struct {
+  double t_submit, t_admit, t_done;  /* seconds since dp_server_create */
+  int64_t mem_estimate;              /* bytes charged against the budget while running */
+  int slot;                          /* worker that ran it */
+} dp_request_times;
+
+typedef struct {
+  int64_t submitted, completed, failed, running, queued;
+  int64_t mem_in_use, mem_budget, mem_peak;  /* bytes, by estimate */
+} dp_server_stats;
+
+/* opts may be NULL.  Errors: DP_EINVAL (bad device or options), DP_EDEVICE. */
+int dp_server_create(int device, const dp_server_opts* opts, dp_server** out);
+/* Queue a request (returns at once) and give its id.  The request is
+ * validated as dp_problem_create would; DP_ENOMEM if its estimated footprint
+ * exceeds the whole budget (it could never be admitted). */
+int dp_server_submit(dp_server* s, const dp_request* r, int64_t* id);
+/* Block until request id has finished; copy its solution (host n x nrhs
+ * complex, may be NULL), solve info and times (may be NULL), and forget the
+ * request.  Returns the request's own status (DP_OK, DP_ENOCONV, or the
+ * negative error of the step that failed, described by dp_last_error in the
+ * calling thread); DP_EINVAL for an unknown id. */
+int dp_server_wait(dp_server* s, int64_t id, double* q, dp_solve_info* info, dp_request_times* times);
+int dp_server_get_stats(dp_server* s, dp_server_stats* st);
+/* Finish every queued and running request, then stop the workers. */
+void dp_server_destroy(dp_server* s);
 
 /* ------------------------------------------------------------------ test hooks */
 /* H_0^(1)(z), H_1^(1)(z) for m real z > 0: out[4k..4k+3] = Re H0, Im H0,

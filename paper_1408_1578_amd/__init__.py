@@ -31,6 +31,7 @@ EXPORTED = [
     "dp_problem_destroy", "dp_rhs_plane_wave", "dp_matvec", "dp_matvec_mixed", "dp_layer_apply",
     "dp_precond_build", "dp_precond_apply", "dp_precond_get_info", "dp_precond_export",
     "dp_solve", "dp_hankel_dev", "dp_hankel_host",
+    "dp_server_create", "dp_server_submit", "dp_server_wait", "dp_server_get_stats", "dp_server_destroy",
 ]
 
 
@@ -42,13 +43,13 @@ class DpError(RuntimeError):
 
 class PrecondOpts(ctypes.Structure):
     _fields_ = [("m_ell", ctypes.c_double), ("min_pts", ctypes.c_int),
-                ("m_c", ctypes.c_int), ("t_keep", ctypes.c_double)]
+                ("m_c", ctypes.c_int), ("t_keep", ctypes.c_double), ("w_solver", ctypes.c_int)]
 
 
 class PrecondInfo(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n_classes", ctypes.c_int64), ("NW", ctypes.c_int64),
                 ("nnzE", ctypes.c_int64), ("nnzW", ctypes.c_int64), ("nnzLU", ctypes.c_int64),
-                ("levels", ctypes.c_int64), ("t_setup", ctypes.c_double)]
+                ("levels", ctypes.c_int64), ("t_setup", ctypes.c_double), ("dense_w", ctypes.c_int64)]
 
 
 DP_PREC_FP64, DP_PREC_MIXED = 0, 1
@@ -68,6 +69,27 @@ class SolveInfo(ctypes.Structure):
                 ("sweep_launches", ctypes.c_int64), ("t_sweep", ctypes.c_double),
                 ("refinements", ctypes.c_int64), ("matvecs_fp32", ctypes.c_int64),
                 ("sweep_launches_fp32", ctypes.c_int64), ("t_sweep_fp32", ctypes.c_double)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int), ("mem_budget", ctypes.c_int64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("xy", ctypes.c_void_p), ("nrm", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("kappa", ctypes.c_void_p), ("omega", ctypes.c_double),
+                ("eta", ctypes.c_double), ("kind", ctypes.c_int), ("nrhs", ctypes.c_int64),
+                ("angles", ctypes.c_void_p), ("f", ctypes.c_void_p), ("solve", SolveOpts)]
+
+
+class RequestTimes(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("mem_estimate", ctypes.c_int64), ("slot", ctypes.c_int)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "running", "queued",
+                                              "mem_in_use", "mem_budget", "mem_peak")]
 
 
 _lib = None
@@ -109,6 +131,11 @@ def lib():
         "dp_solve": (ci, [vp, i64, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp, vp]),
         "dp_hankel_dev": (ci, [vp, i64, vp, vp]),
         "dp_hankel_host": (ci, [i64, vp, vp]),
+        "dp_server_create": (ci, [ci, ctypes.POINTER(ServerOpts), pp]),
+        "dp_server_submit": (ci, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]),
+        "dp_server_wait": (ci, [vp, i64, vp, ctypes.POINTER(SolveInfo), ctypes.POINTER(RequestTimes)]),
+        "dp_server_get_stats": (ci, [vp, ctypes.POINTER(ServerStats)]),
+        "dp_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -246,8 +273,11 @@ def dp_layer_apply(p, op, q, y):
     _check("dp_layer_apply", lib().dp_layer_apply(p.h, int(op), nr, _ptr(q), _ptr(y)))
 
 
-def dp_precond_build(p, m_ell=4.0, min_pts=8, m_c=10, t_keep=3.0):
-    o = PrecondOpts(m_ell, min_pts, m_c, t_keep)
+W_AUTO, W_SPARSE, W_DENSE = 0, 1, 2
+
+
+def dp_precond_build(p, m_ell=4.0, min_pts=8, m_c=10, t_keep=3.0, w_solver=W_AUTO):
+    o = PrecondOpts(m_ell, min_pts, m_c, t_keep, int(w_solver))
     _check("dp_precond_build", lib().dp_precond_build(p.h, ctypes.byref(o)))
 
 
@@ -306,3 +336,68 @@ def dp_hankel_host(z):
     _check("dp_hankel_host", lib().dp_hankel_host(za.size, zp, out.ctypes.data_as(ctypes.c_void_p)))
     out = out.reshape(-1, 4)
     return out[:, 0] + 1j * out[:, 1], out[:, 2] + 1j * out[:, 3]
+
+
+class Server:
+    """Request server (dp_server_*): independent solves admitted onto the GPU
+    as worker slots and device memory free up; submit() returns at once,
+    wait() blocks (the GIL is released while it waits)."""
+
+    def __init__(self, device=0, slots=4, mem_budget=0):
+        self.h = ctypes.c_void_p()
+        o = ServerOpts(int(slots), int(mem_budget))
+        _check("dp_server_create", lib().dp_server_create(int(device), ctypes.byref(o), ctypes.byref(self.h)))
+        self._n = {}
+
+    def submit(self, b, omega, eta, kind, angles=None, f=None, tol=1e-8, restart=80, max_iters=2000,
+               use_precond=True, precision=DP_PREC_FP64, inner_tol=1e-5):
+        """b: boundary with x (n, 2), nu (n, 2), w (n,), kappa (n,).  angles: plane-wave angles, or
+        f: (n, nrhs) complex data.  Returns the request id."""
+        xy, xyp = _host(b.x)
+        nu, nup = _host(b.nu)
+        w, wp = _host(b.w)
+        ka, kap = _host(b.kappa)
+        n = w.size
+        if angles is not None:
+            an, anp = _host(np.atleast_1d(angles))
+            nrhs, fp = an.size, None
+        else:
+            fa = np.asarray(f, np.complex128)
+            fa = fa[:, None] if fa.ndim == 1 else fa
+            nrhs = fa.shape[1]
+            fc, fp = _host(np.asfortranarray(fa).ravel(order="F").view(np.float64))
+            anp = None
+        r = Request(n, xyp, nup, wp, kap, float(omega), float(eta), int(kind), nrhs, anp, fp,
+                    SolveOpts(tol, restart, max_iters, 1 if use_precond else 0, int(precision), inner_tol))
+        rid = ctypes.c_int64()
+        _check("dp_server_submit", lib().dp_server_submit(self.h, ctypes.byref(r), ctypes.byref(rid)))
+        self._n[rid.value] = (n, nrhs)
+        return rid.value
+
+    def wait(self, rid):
+        """(q (n, nrhs) complex, solve info dict, times dict, status)."""
+        n, nrhs = self._n.pop(rid, (0, 0))  # unknown ids: the library reports them
+        q = np.zeros(max(1, 2 * n * nrhs))
+        info, t = SolveInfo(), RequestTimes()
+        rc = _check("dp_server_wait", lib().dp_server_wait(self.h, int(rid), q.ctypes.data_as(ctypes.c_void_p)
+                                                           if n else None, ctypes.byref(info), ctypes.byref(t)))
+        out = {f_: getattr(info, f_) for f_, _ in SolveInfo._fields_}
+        out["converged"] = rc == DP_OK
+        times = {f_: getattr(t, f_) for f_, _ in RequestTimes._fields_}
+        return q.view(np.complex128).reshape(nrhs, n).T, out, times, rc
+
+    def stats(self):
+        st = ServerStats()
+        _check("dp_server_get_stats", lib().dp_server_get_stats(self.h, ctypes.byref(st)))
+        return {f_: getattr(st, f_) for f_, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            lib().dp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

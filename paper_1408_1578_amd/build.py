@@ -10,7 +10,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdirprec.so")
-SOURCES = ["capi.cpp", "tables.hip", "sweep.hip", "near.hip", "fft.hip", "krylov.hip", "precond.hip", "sparse_lu.cpp"]
+SOURCES = ["capi.cpp", "tables.hip", "sweep.hip", "near.hip", "fft.hip", "krylov.hip", "precond.hip", "sparse_lu.cpp",
+           "dense_lu.hip",
+           "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -36,7 +38,7 @@ def build(verbose=False, jobs=8):
             _drain(procs)
     _drain(procs)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
+    cmd = [HIPCC, "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", *objs, "-o", tmp]
     out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     if out.returncode != 0:
         raise RuntimeError("link failed:\n" + out.stdout.decode())

@@ -1,0 +1,425 @@
+// Dense LU with partial pivoting of floor(W) (Sec. 2.2) on the device, and
+// the solves with its factors.
+//
+// floor(W) = E + antidiag(T) has one E entry per ordered pair of segments.
+// When the segments are many (strongly curved boundaries) those entries
+// couple the direction variables nearly all-to-all, every fill-reducing
+// ordering leaves a dense Schur complement of a few thousand rows, and a
+// sparse factorisation on the host takes minutes.  Such matrices are factored
+// here instead, as dense complex matrices (N_W <= ~40000, 16 N_W^2 bytes of
+// HBM), by the right-looking blocked algorithm with 64-column panels:
+//   1. panel: for each column, pivot search (largest modulus, ties to the
+//      lower row index; deterministic two-stage reduction), row swap within
+//      the panel, scaling, and rank-1 update of the panel's later columns;
+//   2. the panel's row swaps applied to the other columns;
+//   3. U12 = L11^{-1} A12 (one wave per column, L11 in LDS);
+//   4. A22 -= L21 U12 on the FP64 matrix cores (v_mfma_f64_16x16x4, complex
+//      products in the 3-multiplication form).
+// The solves apply the row permutation, then blocked forward and backward
+// substitution with the same two kernels (diagonal-block solve, matrix-core
+// update of the remaining rows).  Matrices are column-major with leading
+// dimension n; offsets are 64-bit.
+#include <climits>
+#include <vector>
+
+#include "dense_lu.hpp"
+
+namespace dp {
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int kNB = 64;       // panel width and solve block
+constexpr int kParts = 1024;  // largest number of pivot-search partials
+
+__device__ __forceinline__ double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
+
+__device__ __forceinline__ cplx crecip(cplx a) {
+  const double d = cabs2(a);
+  return d > 0.0 ? cplx{a.re / d, -a.im / d} : cplx{0.0, 0.0};
+}
+
+// (v, i) better than (bv, bi): larger modulus, ties to the smaller row
+__device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
+// block (256 threads) reduction of (v, i) pairs; result in slot 0
+__device__ __forceinline__ void reduce_best(double* sv, int* si) {
+  const int t = threadIdx.x;
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s && better(sv[t + s], si[t + s], sv[t], si[t])) {
+      sv[t] = sv[t + s];
+      si[t] = si[t + s];
+    }
+    __syncthreads();
+  }
+}
+
+// partials of max |A[r, c]|^2 over rows c..n-1
+__global__ __launch_bounds__(256) void col_amax(const cplx* __restrict__ A, int n, int c, double* pv, int* pi) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  double bv = -1.0;
+  int bi = INT_MAX;
+  const size_t col = (size_t)c * n;
+  for (int r = c + blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+    const double v = cabs2(A[col + r]);
+    if (better(v, r, bv, bi)) {
+      bv = v;
+      bi = r;
+    }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  reduce_best(sv, si);
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = sv[0];
+    pi[blockIdx.x] = si[0];
+  }
+}
+
+// Pivot of column c (one block): reduce the partials, swap rows c and p in the
+// panel's columns k0..k0+kb-1, record ipiv[c] = p and 1/A[c, c].  A zero (or
+// non-finite) pivot column sets *info = c + 1 once and continues with 1/0 = 0.
+__global__ __launch_bounds__(256) void panel_pivot(cplx* A, int n, int k0, int kb, int c, const double* pv,
+                                                   const int* pi, int nparts, int* ipiv, cplx* inv, int* info) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  double bv = -1.0;
+  int bi = INT_MAX;
+  for (int q = threadIdx.x; q < nparts; q += 256)
+    if (better(pv[q], pi[q], bv, bi)) {
+      bv = pv[q];
+      bi = pi[q];
+    }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  reduce_best(sv, si);
+  const bool bad = !(sv[0] > 0.0) || !(sv[0] < 1e300) || si[0] < c || si[0] >= n;
+  const int p = bad ? c : si[0];
+  if (threadIdx.x == 0) {
+    ipiv[c] = p;
+    if (bad && *info == 0) *info = c + 1;
+  }
+  if (p != c && threadIdx.x < kb) {
+    const size_t col = (size_t)(k0 + threadIdx.x) * n;
+    const cplx a = A[col + c], b = A[col + p];
+    A[col + c] = b;
+    A[col + p] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *inv = crecip(A[(size_t)c * n + c]);
+}
+
+// Column c of the panel below the diagonal: l = a/pivot, and the rank-1
+// update of the panel's later columns; partials of the next column's pivot
+// search over the updated rows (when want_next).
+__global__ __launch_bounds__(256) void panel_update(cplx* A, int n, int k0, int kb, int c, const cplx* inv_p,
+                                                    double* pv, int* pi, int want_next) {
+  __shared__ cplx prow[kNB];
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  const int j = c - k0;
+  if (threadIdx.x < kb) prow[threadIdx.x] = A[(size_t)(k0 + threadIdx.x) * n + c];
+  __syncthreads();
+  const cplx inv = *inv_p;
+  double bv = -1.0;
+  int bi = INT_MAX;
+  for (int r = c + 1 + blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+    const cplx a = A[(size_t)c * n + r];
+    const cplx l = cmul(a, inv);
+    A[(size_t)c * n + r] = l;
+    for (int jj = j + 1; jj < kb; ++jj) {
+      cplx& x = A[(size_t)(k0 + jj) * n + r];
+      const cplx u = prow[jj];
+      x = {x.re - (l.re * u.re - l.im * u.im), x.im - (l.re * u.im + l.im * u.re)};
+    }
+    if (want_next) {
+      const double v = cabs2(A[(size_t)(c + 1) * n + r]);
+      if (better(v, r, bv, bi)) {
+        bv = v;
+        bi = r;
+      }
+    }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  reduce_best(sv, si);
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = sv[0];
+    pi[blockIdx.x] = si[0];
+  }
+}
+
+// the panel's swaps (rows c <-> ipiv[c], c = k0..k0+kb-1, in order) on every
+// column outside the panel; one thread per column
+__global__ __launch_bounds__(256) void laswp(cplx* A, int n, int k0, int kb, const int* __restrict__ ipiv) {
+  const int ncol = n - kb;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < ncol; t += gridDim.x * 256) {
+    const size_t col = (size_t)(t < k0 ? t : t + kb) * n;
+    for (int c = k0; c < k0 + kb; ++c) {
+      const int p = ipiv[c];
+      if (p != c) {
+        const cplx a = A[col + c], b = A[col + p];
+        A[col + c] = b;
+        A[col + p] = a;
+      }
+    }
+  }
+}
+
+// X = L^{-1} X for the unit lower kb x kb block L and kb x ncols X; one wave
+// per column (lane = row), L in LDS.
+__global__ __launch_bounds__(256) void trsm_lower_unit(const cplx* __restrict__ L, int ldl, cplx* X, int ldx, int kb,
+                                                       int ncols) {
+  __shared__ cplx Ls[kNB][kNB + 1];
+  for (int e = threadIdx.x; e < kb * kb; e += 256) {
+    const int r = e % kb, k = e / kb;
+    Ls[r][k] = L[(size_t)k * ldl + r];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (int col = blockIdx.x * 4 + (threadIdx.x >> 6); col < ncols; col += gridDim.x * 4) {
+    cplx* x = X + (size_t)col * ldx;
+    cplx v = lane < kb ? x[lane] : cplx{0.0, 0.0};
+    for (int r = 0; r + 1 < kb; ++r) {
+      const cplx xr = {__shfl(v.re, r), __shfl(v.im, r)};
+      if (lane > r && lane < kb) {
+        const cplx l = Ls[lane][r];
+        v = {v.re - (l.re * xr.re - l.im * xr.im), v.im - (l.re * xr.im + l.im * xr.re)};
+      }
+    }
+    if (lane < kb) x[lane] = v;
+  }
+}
+
+// X = U^{-1} X for the upper kb x kb block U (non-unit diagonal).
+__global__ __launch_bounds__(256) void trsm_upper(const cplx* __restrict__ U, int ldu, cplx* X, int ldx, int kb,
+                                                  int ncols) {
+  __shared__ cplx Us[kNB][kNB + 1];
+  __shared__ cplx dinv[kNB];
+  for (int e = threadIdx.x; e < kb * kb; e += 256) {
+    const int r = e % kb, k = e / kb;
+    Us[r][k] = U[(size_t)k * ldu + r];
+  }
+  __syncthreads();
+  if (threadIdx.x < kb) dinv[threadIdx.x] = crecip(Us[threadIdx.x][threadIdx.x]);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (int col = blockIdx.x * 4 + (threadIdx.x >> 6); col < ncols; col += gridDim.x * 4) {
+    cplx* x = X + (size_t)col * ldx;
+    cplx v = lane < kb ? x[lane] : cplx{0.0, 0.0};
+    for (int r = kb - 1; r >= 0; --r) {
+      if (lane == r) v = cmul(v, dinv[r]);
+      const cplx xr = {__shfl(v.re, r), __shfl(v.im, r)};
+      if (lane < r) {
+        const cplx u = Us[lane][r];
+        v = {v.re - (u.re * xr.re - u.im * xr.im), v.im - (u.re * xr.im + u.im * xr.re)};
+      }
+    }
+    if (lane < kb) x[lane] = v;
+  }
+}
+
+// C (M x N) -= A (M x K) B (K x N), K <= 64, on the FP64 matrix cores.
+// Block: 4 waves, a 64 x 64 tile of C; A and B tiles staged in LDS k-major
+// (As[k][i], Bs[k][j]) so that the MFMA operands A[i][k] (lane i + 16k) and
+// B[k][j] (lane j + 16k) are 16-element contiguous runs.  Each wave owns a
+// 32 x 32 quarter (2 x 2 tiles of 16 x 16) with three accumulators per tile:
+// T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi); C -= (T1 - T2) + i (T3 - T1 - T2).
+// Result layout: register r of lane L holds row 4r + L/16, column L mod 16.
+__global__ __launch_bounds__(256) void zgemm_sub(const cplx* __restrict__ A, int lda, const cplx* __restrict__ B,
+                                                 int ldb, cplx* C, int ldc, int M, int N, int K) {
+  __shared__ cplx As[kNB][kNB + 1];
+  __shared__ cplx Bs[kNB][kNB + 1];
+  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int i = e & 63, k = e >> 6;
+    As[k][i] = (m0 + i < M && k < K) ? A[(size_t)k * lda + m0 + i] : cplx{0.0, 0.0};
+    const int kk = e & 63, jj = e >> 6;
+    Bs[kk][jj] = (kk < K && n0 + jj < N) ? B[(size_t)(n0 + jj) * ldb + kk] : cplx{0.0, 0.0};
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int i0 = 32 * (w & 1), j0 = 32 * (w >> 1);
+  dbl4 T1[2][2], T2[2][2], T3[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      T1[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+      T2[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+      T3[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+  const int ks = (K + 3) / 4;
+  for (int s = 0; s < ks; ++s) {
+    const int k = 4 * s + lk;
+    cplx a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      a[t] = As[k][i0 + 16 * t + li];
+      b[t] = Bs[k][j0 + 16 * t + li];
+    }
+#pragma unroll
+    for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb) {
+        T1[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].re, b[tb].re, T1[ta][tb], 0, 0, 0);
+        T2[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].im, b[tb].im, T2[ta][tb], 0, 0, 0);
+        T3[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].re + a[ta].im, b[tb].re + b[tb].im, T3[ta][tb],
+                                                          0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + i0 + 16 * ta + 4 * r + lk;
+        const int j = n0 + j0 + 16 * tb + li;
+        if (i < M && j < N) {
+          const double t1 = T1[ta][tb][r], t2 = T2[ta][tb][r], t3 = T3[ta][tb][r];
+          cplx& c = C[(size_t)j * ldc + i];
+          c = {c.re - (t1 - t2), c.im - (t3 - t1 - t2)};
+        }
+      }
+}
+
+__global__ void dense_scatter(cplx* A, int n, const int* __restrict__ rows, const int* __restrict__ cols,
+                              const cplx* __restrict__ vals, int nnz) {
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < nnz; q += gridDim.x * 256)
+    A[(size_t)cols[q] * n + rows[q]] = vals[q];
+}
+
+__global__ void gather_perm(const cplx* __restrict__ z, cplx* t, const int* __restrict__ perm, int n, int nrhs) {
+  const size_t tot = (size_t)n * nrhs;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot; idx += (size_t)gridDim.x * blockDim.x) {
+    const int i = idx % n;
+    const size_t c = idx / n;
+    t[idx] = z[c * n + perm[i]];
+  }
+}
+
+int nblocks(int64_t rows, int cap) {
+  int64_t g = (rows + 255) / 256;
+  if (g < 1) g = 1;
+  return (int)(g > cap ? cap : g);
+}
+
+void launch_gemm_sub(hipStream_t st, const cplx* A, int lda, const cplx* B, int ldb, cplx* C, int ldc, int M, int N,
+                     int K) {
+  if (M <= 0 || N <= 0 || K <= 0) return;
+  dim3 grid((M + 63) / 64, (N + 63) / 64);
+  zgemm_sub<<<grid, 256, 0, st>>>(A, lda, B, ldb, C, ldc, M, N, K);
+}
+
+}  // namespace
+
+int DenseLU::assemble(hipStream_t st, int n_, const std::vector<int>& rows, const std::vector<int>& cols,
+                      const std::vector<cplx>& vals) {
+  n = n_;
+  const size_t bytes = (size_t)n * n * sizeof(cplx);
+  DP_TRY(a.reserve(bytes));
+  DP_HIP(hipMemsetAsync(a.p, 0, bytes, st));
+  DevBuf dr, dc, dv;
+  DP_TRY(dr.reserve(std::max<size_t>(1, rows.size()) * sizeof(int)));
+  DP_TRY(dc.reserve(std::max<size_t>(1, cols.size()) * sizeof(int)));
+  DP_TRY(dv.reserve(std::max<size_t>(1, vals.size()) * sizeof(cplx)));
+  const int nnz = (int)vals.size();
+  if (nnz > 0) {
+    DP_HIP(hipMemcpyAsync(dr.p, rows.data(), nnz * sizeof(int), hipMemcpyHostToDevice, st));
+    DP_HIP(hipMemcpyAsync(dc.p, cols.data(), nnz * sizeof(int), hipMemcpyHostToDevice, st));
+    DP_HIP(hipMemcpyAsync(dv.p, vals.data(), nnz * sizeof(cplx), hipMemcpyHostToDevice, st));
+    dense_scatter<<<nblocks(nnz, 4096), 256, 0, st>>>(a.as<cplx>(), n, dr.as<int>(), dc.as<int>(), dv.as<cplx>(),
+                                                      nnz);
+    DP_HIP(hipGetLastError());
+  }
+  DP_HIP(hipStreamSynchronize(st));
+  dr.release();
+  dc.release();
+  dv.release();
+  return DP_OK;
+}
+
+int DenseLU::factor(hipStream_t st) {
+  cplx* A = a.as<cplx>();
+  DP_TRY(ipiv.reserve((size_t)n * sizeof(int)));
+  DP_TRY(work.reserve(kParts * (sizeof(double) + sizeof(int)) + 64));
+  double* pv = work.as<double>();
+  int* pi = reinterpret_cast<int*>(pv + kParts);
+  cplx* inv = reinterpret_cast<cplx*>(pi + kParts);
+  int* info = reinterpret_cast<int*>(inv + 1);
+  DP_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
+  int* ip = ipiv.as<int>();
+  for (int k0 = 0; k0 < n; k0 += kNB) {
+    const int kb = std::min(kNB, n - k0);
+    int parts = nblocks(n - k0, kParts);
+    col_amax<<<parts, 256, 0, st>>>(A, n, k0, pv, pi);
+    for (int j = 0; j < kb; ++j) {
+      const int c = k0 + j;
+      panel_pivot<<<1, 256, 0, st>>>(A, n, k0, kb, c, pv, pi, parts, ip, inv, info);
+      const int g = nblocks(n - c - 1, kParts);
+      panel_update<<<g, 256, 0, st>>>(A, n, k0, kb, c, inv, pv, pi, j + 1 < kb ? 1 : 0);
+      parts = g;
+    }
+    if (n > kb) laswp<<<nblocks(n - kb, 4096), 256, 0, st>>>(A, n, k0, kb, ip);
+    const int rest = n - k0 - kb;
+    if (rest > 0) {
+      trsm_lower_unit<<<std::min(1024, (rest + 3) / 4), 256, 0, st>>>(A + (size_t)k0 * n + k0, n,
+                                                                       A + (size_t)(k0 + kb) * n + k0, n, kb, rest);
+      launch_gemm_sub(st, A + (size_t)k0 * n + k0 + kb, n, A + (size_t)(k0 + kb) * n + k0, n,
+                      A + (size_t)(k0 + kb) * n + k0 + kb, n, rest, rest, kb);
+    }
+    DP_HIP(hipGetLastError());
+  }
+  // permutation of the row swaps: (P z)[i] = z[perm[i]]
+  std::vector<int> h(n), pm(n);
+  int hinfo = 0;
+  DP_HIP(hipMemcpyAsync(h.data(), ip, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
+  DP_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
+  DP_HIP(hipStreamSynchronize(st));
+  if (hinfo != 0) {
+    set_error("dense LU of floor(W): zero pivot in column %d", hinfo - 1);
+    return DP_ESINGULAR;
+  }
+  for (int i = 0; i < n; ++i) pm[i] = i;
+  for (int c = 0; c < n; ++c) std::swap(pm[c], pm[h[c]]);
+  DP_TRY(perm.reserve((size_t)n * sizeof(int)));
+  DP_HIP(hipMemcpyAsync(perm.p, pm.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, st));
+  DP_HIP(hipStreamSynchronize(st));
+  return DP_OK;
+}
+
+int DenseLU::solve(hipStream_t st, const cplx* z, cplx* u, int nrhs) {
+  const cplx* A = a.as<cplx>();
+  gather_perm<<<nblocks((int64_t)n * nrhs, 8192), 256, 0, st>>>(z, u, perm.as<int>(), n, nrhs);
+  for (int b0 = 0; b0 < n; b0 += kNB) {
+    const int kb = std::min(kNB, n - b0);
+    trsm_lower_unit<<<std::min(1024, (nrhs + 3) / 4), 256, 0, st>>>(A + (size_t)b0 * n + b0, n, u + b0, n, kb,
+                                                                    nrhs);
+    launch_gemm_sub(st, A + (size_t)b0 * n + b0 + kb, n, u + b0, n, u + b0 + kb, n, n - b0 - kb, nrhs, kb);
+  }
+  for (int b0 = ((n - 1) / kNB) * kNB; b0 >= 0; b0 -= kNB) {
+    const int kb = std::min(kNB, n - b0);
+    trsm_upper<<<std::min(1024, (nrhs + 3) / 4), 256, 0, st>>>(A + (size_t)b0 * n + b0, n, u + b0, n, kb, nrhs);
+    launch_gemm_sub(st, A + (size_t)b0 * n, n, u + b0, n, u, n, b0, nrhs, kb);
+  }
+  DP_HIP(hipGetLastError());
+  return DP_OK;
+}
+
+void DenseLU::release() {
+  a.release();
+  ipiv.release();
+  perm.release();
+  work.release();
+  n = 0;
+}
+
+}  // namespace dp

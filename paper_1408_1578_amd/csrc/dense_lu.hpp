@@ -1,0 +1,26 @@
+// Dense LU with partial pivoting of floor(W) on the device (dense_lu.hip).
+#pragma once
+
+#include <vector>
+
+#include "dp_internal.hpp"
+
+namespace dp {
+
+struct DenseLU {
+  int n = 0;
+  DevBuf a;     // n x n column-major: unit lower L below the diagonal, U on and above
+  DevBuf ipiv;  // row swapped with row c at step c
+  DevBuf perm;  // (P z)[i] = z[perm[i]]
+  DevBuf work;  // pivot-search partials, 1/pivot, singularity flag
+  // zero n x n matrix with the given (row, col, value) entries (no duplicates)
+  int assemble(hipStream_t st, int n, const std::vector<int>& rows, const std::vector<int>& cols,
+               const std::vector<cplx>& vals);
+  // P A = L U in place; DP_ESINGULAR on a zero pivot column
+  int factor(hipStream_t st);
+  // u = A^{-1} z for nrhs columns (n x nrhs column-major, z and u distinct)
+  int solve(hipStream_t st, const cplx* z, cplx* u, int nrhs);
+  void release();
+};
+
+}  // namespace dp

@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "dp_internal.hpp"
+#include "dense_lu.hpp"
 #include "sparse_lu.hpp"
 
 namespace dp {
@@ -59,6 +60,9 @@ struct Precond {
   // level-ordered copies for the LDS-resident solve
   DevBuf itL, itU, jL2, vL2, jU2, vU2, uinv;
   bool lds_solve = false;
+  // dense device LU of floor(W) (when the sparse factors would fill in)
+  bool dense_w = false;
+  DenseLU dlu;
   int64_t nnzW = 0;
   DevBuf wy, wg, wz, wu, wt, wn;  // apply workspaces
   double t_setup = 0;
@@ -851,54 +855,80 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     cp[c + 1] = (int)ri.size();
   }
   P->nnzW = (int64_t)ri.size();
-  if ((rc = sparse_lu_factor(NW, cp, ri, vx, P->lu))) return fail(rc);
-  auto to_c = [](const std::vector<zc>& a) {
-    std::vector<cplx> r(a.size());
-    for (size_t q = 0; q < a.size(); ++q) r[q] = {a[q].real(), a[q].imag()};
-    return r;
-  };
-  const SparseLU& lu = P->lu;
-  if ((rc = upload(P->Lp, lu.Lp, st)) || (rc = upload(P->Lj, lu.Lj, st)) || (rc = upload(P->Lx, to_c(lu.Lx), st)) ||
-      (rc = upload(P->Up, lu.Up, st)) || (rc = upload(P->Uj, lu.Uj, st)) || (rc = upload(P->Ux, to_c(lu.Ux), st)) ||
-      (rc = upload(P->Ud, to_c(lu.Ud), st)) || (rc = upload(P->lvlL, lu.lvlL_ptr, st)) ||
-      (rc = upload(P->lvlLr, lu.lvlL_rows, st)) || (rc = upload(P->lvlU, lu.lvlU_ptr, st)) ||
-      (rc = upload(P->lvlUr, lu.lvlU_rows, st)) || (rc = upload(P->pin, lu.perm_in, st)) ||
-      (rc = upload(P->pout, lu.perm_out, st)))
-    return fail(rc);
-  P->nlevL = (int)lu.lvlL_ptr.size() - 1;
-  P->nlevU = (int)lu.lvlU_ptr.size() - 1;
-  {
-    // level-ordered items (row, first entry, count) and entries
-    auto order = [&](const std::vector<int>& rows, const std::vector<int>& Pp, const std::vector<int>& Jj,
-                     const std::vector<zc>& Vv, std::vector<int4>& items, std::vector<int>& j2,
-                     std::vector<cplx>& v2) {
-      for (int r : rows) {
-        items.push_back(int4{r, (int)j2.size(), Pp[r + 1] - Pp[r], 0});
-        for (int q = Pp[r]; q < Pp[r + 1]; ++q) {
-          j2.push_back(Jj[q]);
-          v2.push_back({Vv[q].real(), Vv[q].imag()});
-        }
-      }
-    };
-    std::vector<int4> itl, itu;
-    std::vector<int> jl, ju;
-    std::vector<cplx> vl, vu, ui(NW);
-    order(lu.lvlL_rows, lu.Lp, lu.Lj, lu.Lx, itl, jl, vl);
-    order(lu.lvlU_rows, lu.Up, lu.Uj, lu.Ux, itu, ju, vu);
-    for (int r = 0; r < NW; ++r) {
-      const zc inv = 1.0 / lu.Ud[r];
-      ui[r] = {inv.real(), inv.imag()};
+  // Host sparse LU unless the ordering predicts heavy fill (many segments
+  // coupled all-to-all through E); then a dense LU on the device.
+  const int64_t fill_cap =
+      o->w_solver == 1 ? INT64_MAX : std::max<int64_t>(1500000, 8 * P->nnzW);
+  rc = o->w_solver == 2 ? kSparseFillLimit : sparse_lu_factor(NW, cp, ri, vx, P->lu, fill_cap);
+  if (rc == kSparseFillLimit) {
+    if ((double)NW * NW * sizeof(cplx) > 48.0 * (1 << 30)) {
+      set_error("floor(W) of dimension %d needs a dense factorisation larger than 48 GiB", NW);
+      return fail(DP_ENOMEM);
     }
-    if ((rc = upload(P->itL, itl, st)) || (rc = upload(P->itU, itu, st)) || (rc = upload(P->jL2, jl, st)) ||
-        (rc = upload(P->vL2, vl, st)) || (rc = upload(P->jU2, ju, st)) || (rc = upload(P->vU2, vu, st)) ||
-        (rc = upload(P->uinv, ui, st)))
+    std::vector<int> rows_, cols_;
+    std::vector<cplx> vals_;
+    rows_.reserve(ri.size());
+    cols_.reserve(ri.size());
+    vals_.reserve(ri.size());
+    for (int c = 0; c < NW; ++c)
+      for (int q = cp[c]; q < cp[c + 1]; ++q) {
+        rows_.push_back(ri[q]);
+        cols_.push_back(c);
+        vals_.push_back({vx[q].real(), vx[q].imag()});
+      }
+    if ((rc = P->dlu.assemble(st, NW, rows_, cols_, vals_)) || (rc = P->dlu.factor(st))) return fail(rc);
+    P->dense_w = true;
+  } else if (rc) {
+    return fail(rc);
+  } else {
+    auto to_c = [](const std::vector<zc>& a) {
+      std::vector<cplx> r(a.size());
+      for (size_t q = 0; q < a.size(); ++q) r[q] = {a[q].real(), a[q].imag()};
+      return r;
+    };
+    const SparseLU& lu = P->lu;
+    if ((rc = upload(P->Lp, lu.Lp, st)) || (rc = upload(P->Lj, lu.Lj, st)) || (rc = upload(P->Lx, to_c(lu.Lx), st)) ||
+        (rc = upload(P->Up, lu.Up, st)) || (rc = upload(P->Uj, lu.Uj, st)) || (rc = upload(P->Ux, to_c(lu.Ux), st)) ||
+        (rc = upload(P->Ud, to_c(lu.Ud), st)) || (rc = upload(P->lvlL, lu.lvlL_ptr, st)) ||
+        (rc = upload(P->lvlLr, lu.lvlL_rows, st)) || (rc = upload(P->lvlU, lu.lvlU_ptr, st)) ||
+        (rc = upload(P->lvlUr, lu.lvlU_rows, st)) || (rc = upload(P->pin, lu.perm_in, st)) ||
+        (rc = upload(P->pout, lu.perm_out, st)))
       return fail(rc);
-    int maxlds = 0;
-    DP_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->ctx->device));
-    P->lds_solve = (size_t)NW * sizeof(cplx) <= (size_t)maxlds;
-    if (P->lds_solve)
-      DP_HIP(hipFuncSetAttribute((const void*)tri_solve_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)(NW * sizeof(cplx))));
+    P->nlevL = (int)lu.lvlL_ptr.size() - 1;
+    P->nlevU = (int)lu.lvlU_ptr.size() - 1;
+    {
+      // level-ordered items (row, first entry, count) and entries
+      auto order = [&](const std::vector<int>& rows, const std::vector<int>& Pp, const std::vector<int>& Jj,
+                       const std::vector<zc>& Vv, std::vector<int4>& items, std::vector<int>& j2,
+                       std::vector<cplx>& v2) {
+        for (int r : rows) {
+          items.push_back(int4{r, (int)j2.size(), Pp[r + 1] - Pp[r], 0});
+          for (int q = Pp[r]; q < Pp[r + 1]; ++q) {
+            j2.push_back(Jj[q]);
+            v2.push_back({Vv[q].real(), Vv[q].imag()});
+          }
+        }
+      };
+      std::vector<int4> itl, itu;
+      std::vector<int> jl, ju;
+      std::vector<cplx> vl, vu, ui(NW);
+      order(lu.lvlL_rows, lu.Lp, lu.Lj, lu.Lx, itl, jl, vl);
+      order(lu.lvlU_rows, lu.Up, lu.Uj, lu.Ux, itu, ju, vu);
+      for (int r = 0; r < NW; ++r) {
+        const zc inv = 1.0 / lu.Ud[r];
+        ui[r] = {inv.real(), inv.imag()};
+      }
+      if ((rc = upload(P->itL, itl, st)) || (rc = upload(P->itU, itu, st)) || (rc = upload(P->jL2, jl, st)) ||
+          (rc = upload(P->vL2, vl, st)) || (rc = upload(P->jU2, ju, st)) || (rc = upload(P->vU2, vu, st)) ||
+          (rc = upload(P->uinv, ui, st)))
+        return fail(rc);
+      int maxlds = 0;
+      DP_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->ctx->device));
+      P->lds_solve = (size_t)NW * sizeof(cplx) <= (size_t)maxlds;
+      if (P->lds_solve)
+        DP_HIP(hipFuncSetAttribute((const void*)tri_solve_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(NW * sizeof(cplx))));
+    }
   }
 
   // ---- apply tables
@@ -986,7 +1016,9 @@ int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
   // z = floor(T) g
   DP_TRY(run_seg_gemm(p, TT, 1, 1, 1, 0, g, NW, nullptr, z, NW, nrhs));
   // u = floor(W)^{-1} z
-  if (P->lds_solve) {
+  if (P->dense_w) {
+    DP_TRY(P->dlu.solve(st, z, u, nrhs));
+  } else if (P->lds_solve) {
     tri_solve_lds<<<nrhs, 256, (size_t)NW * sizeof(cplx), st>>>(
         z, u, NW, P->pin.as<int>(), P->pout.as<int>(), P->itL.as<int4>(), P->lvlL.as<int>(), P->nlevL,
         P->jL2.as<int>(), P->vL2.as<cplx>(), P->itU.as<int4>(), P->lvlU.as<int>(), P->nlevU, P->jU2.as<int>(),
@@ -1024,6 +1056,7 @@ void precond_destroy(Precond* P) {
                     &P->lvlL, &P->lvlLr, &P->lvlU, &P->lvlUr, &P->pin, &P->pout, &P->wy, &P->wg, &P->wz, &P->wu,
                     &P->wt, &P->wn, &P->itL, &P->itU, &P->jL2, &P->vL2, &P->jU2, &P->vU2, &P->uinv})
     b->release();
+  P->dlu.release();
   delete P;
 }
 
@@ -1034,8 +1067,9 @@ int precond_info(dp_problem* p, dp_precond_info* info) {
   info->NW = P->NW;
   info->nnzE = (int64_t)P->m * (P->m - 1);
   info->nnzW = P->nnzW;
-  info->nnzLU = (int64_t)P->lu.Lx.size() + (int64_t)P->lu.Ux.size() + P->NW;
-  info->levels = P->nlevL + P->nlevU;
+  info->nnzLU = P->dense_w ? (int64_t)P->NW * P->NW : (int64_t)P->lu.Lx.size() + (int64_t)P->lu.Ux.size() + P->NW;
+  info->levels = P->dense_w ? 0 : P->nlevL + P->nlevU;
+  info->dense_w = P->dense_w ? 1 : 0;
   info->t_setup = P->t_setup;
   return DP_OK;
 }

@@ -9,11 +9,16 @@
 //      search in the graph of L);
 //   3. row-oriented copies of L and U and their dependency levels, so that
 //      the device solves process one level per step.
+// When the segments couple nearly all-to-all through E the factors fill in
+// (the Schur complement of the last few thousand nodes is dense); the caller
+// then gets kSparseFillLimit, decided from the ordering's symbolic fill
+// before any numeric work, and factors floor(W) densely on the device.
 // This is setup work of O(nnz(L + U)) on the host; the per-iteration solves
 // run on the GPU.
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <cstdio>
 #include <set>
 #include <vector>
@@ -26,7 +31,12 @@ namespace dp {
 using zc = std::complex<double>;
 
 // Minimum degree ordering of the symmetric pattern given by adjacency lists.
-static std::vector<int> min_degree(int n, std::vector<std::vector<int>> adj) {
+// The degree of each node when it is eliminated is the size of its column in
+// the symbolic factor; their sum (times two, plus n) predicts nnz(L + U)
+// without pivoting.  The ordering stops early, returning an empty order,
+// once that prediction exceeds max_fill.
+static std::vector<int> min_degree(int n, std::vector<std::vector<int>> adj, int64_t max_fill) {
+  int64_t fill = n;
   std::vector<char> elim(n, 0);
   std::vector<int> mark(n, -1);
   std::set<std::pair<int, int>> pq;
@@ -43,6 +53,8 @@ static std::vector<int> min_degree(int n, std::vector<std::vector<int>> adj) {
     nb.clear();
     for (int a : adj[v])
       if (!elim[a]) nb.push_back(a);
+    fill += 2 * (int64_t)nb.size();
+    if (fill > max_fill) return {};
     for (int a : nb) {
       pq.erase({(int)adj[a].size(), a});
       ++stamp;
@@ -66,7 +78,7 @@ static std::vector<int> min_degree(int n, std::vector<std::vector<int>> adj) {
 }
 
 int sparse_lu_factor(int n, const std::vector<int>& cp, const std::vector<int>& ri, const std::vector<zc>& vx,
-                     SparseLU& out) {
+                     SparseLU& out, int64_t max_fill) {
   // ---- ordering on the symmetrised pattern
   std::vector<std::vector<int>> adj(n);
   for (int j = 0; j < n; ++j)
@@ -80,7 +92,8 @@ int sparse_lu_factor(int n, const std::vector<int>& cp, const std::vector<int>& 
     std::sort(a.begin(), a.end());
     a.erase(std::unique(a.begin(), a.end()), a.end());
   }
-  std::vector<int> Q = min_degree(n, adj);
+  std::vector<int> Q = min_degree(n, adj, max_fill);
+  if (Q.empty() && n > 0) return kSparseFillLimit;
   std::vector<int> Qinv(n);
   for (int a = 0; a < n; ++a) Qinv[Q[a]] = a;
   // A' = W(Q, Q) in CSC: column b of A' is column Q[b] of W with rows relabelled
@@ -184,6 +197,8 @@ int sparse_lu_factor(int n, const std::vector<int>& cp, const std::vector<int>& 
       x[r] = 0.0;
     }
     Lcp.push_back((int)Lri.size());
+    // pivoting can fill more than the symbolic prediction: stop at twice it
+    if (max_fill < INT64_MAX / 2 && (int64_t)(Lri.size() + Uri.size()) > 2 * max_fill) return kSparseFillLimit;
   }
   for (auto& r : Lri) r = pinv[r];
   // ---- row-oriented copies (pivot numbering)

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <complex>
+#include <cstdint>
 #include <vector>
 
 namespace dp {
@@ -17,8 +18,12 @@ struct SparseLU {
   std::vector<int> lvlL_ptr, lvlL_rows, lvlU_ptr, lvlU_rows;
 };
 
-// W given in CSC (colptr, rowind, values), n x n.
+// W given in CSC (colptr, rowind, values), n x n.  Returns DP_OK,
+// DP_ESINGULAR, or kSparseFillLimit when nnz(L + U) would exceed max_fill
+// (predicted from the ordering) or twice it (in the numeric factorisation).
+constexpr int kSparseFillLimit = 2;
 int sparse_lu_factor(int n, const std::vector<int>& colptr, const std::vector<int>& rowind,
-                     const std::vector<std::complex<double>>& val, SparseLU& out);
+                     const std::vector<std::complex<double>>& val, SparseLU& out,
+                     int64_t max_fill = INT64_MAX);
 
 }  // namespace dp

@@ -72,3 +72,32 @@ def test_mixed_solve_full_size_point_source():
     for c in (0, 17, 63):
         u = ny.field(b, om, eta, kind, Q[:, c] * np.exp(-1j * c), pts)
         assert np.max(np.abs(u - ue)) / np.max(np.abs(ue)) < 1e-6
+
+
+def test_random_star_131072_mixed_single_rhs():
+    # the 131072-point seeded random star (omega = 11889, sound-soft, one
+    # right-hand side): FP32 sweep, FP64 near field and residuals.  Checked by
+    # a property that holds at any size: data from an interior point source
+    # reproduces its exterior field; plus oracle rows of A q at sampled targets
+    # for the FP64 operator on the solution
+    b, om, eta, kind = config_boundary("randstar", 131072)
+    z0 = np.array([0.05, -0.1])
+    f = ny.point_source_data(b, om, z0, kind)
+    p = problem(b, om, eta, kind)
+    dp.dp_precond_build(p)
+    # 320 segments coupled all-to-all: floor(W) (N_W = 26922) is factored densely on the device
+    assert dp.dp_precond_get_info(p)["dense_w"] == 1
+    q = empty(b.n, 1)
+    info = dp.dp_solve(p, to_dev(f[:, None]), q, tol=1e-8, use_precond=True, precision=dp.DP_PREC_MIXED)
+    assert info["converged"] and info["relres_max"] <= 1e-8
+    Q = to_host(q)[:, 0]
+    th = np.linspace(0, 2 * np.pi, 6, endpoint=False)
+    pts = np.stack([1.8 * np.cos(th), 1.8 * np.sin(th)], 1)
+    ue = ny.green(om, pts, z0)
+    u = ny.field(b, om, eta, kind, Q, pts)
+    assert np.max(np.abs(u - ue)) / np.max(np.abs(ue)) < 1e-6
+    rows = np.arange(0, b.n, b.n // 12)[:12]
+    lay = ny.layer_rows(b, om, rows)
+    Arow = 0.5 * np.eye(b.n)[rows] + lay["D"] - 1j * eta * lay["S"]
+    res = np.abs(Arow @ Q - f[rows]) / np.linalg.norm(f) * np.sqrt(b.n)
+    assert np.max(res) < 1e-6

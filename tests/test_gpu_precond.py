@@ -82,3 +82,47 @@ def test_full_size_kite_hard_apply():
     z = empty(b.n, 2)
     dp.dp_precond_apply(p, to_dev(v), z)
     assert relerr(to_host(z), pc.apply(P, v)) < 1e-10
+
+
+@pytest.mark.parametrize("cfg,n,kind", [("disk", 1024, 1), ("star", 4096, 0), ("kite", 4096, 1)])
+def test_dense_w_apply_parity(cfg, n, kind):
+    # floor(W) factored densely on the device (forced): same apply as the
+    # oracle's dense LU, for column counts below, at and above one 64-column tile
+    b, om, eta, _ = config_boundary(cfg, n)
+    P = pc.build(b, om, eta, kind)
+    p = problem(b, om, eta, kind)
+    dp.dp_precond_build(p, w_solver=dp.W_DENSE)
+    info = dp.dp_precond_get_info(p)
+    assert info["dense_w"] == 1 and info["nnzLU"] == P.NW ** 2
+    for nrhs in (1, 64, 70):
+        v = random_density(b.n, nrhs, seed=nrhs + 3)
+        z = empty(b.n, nrhs)
+        dp.dp_precond_apply(p, to_dev(v), z)
+        assert relerr(to_host(z), pc.apply(P, v)) < 1e-10
+    # and the same as the host sparse factors
+    p2 = problem(b, om, eta, kind)
+    dp.dp_precond_build(p2, w_solver=dp.W_SPARSE)
+    assert dp.dp_precond_get_info(p2)["dense_w"] == 0
+    v = random_density(b.n, 3, seed=1)
+    z1, z2 = empty(b.n, 3), empty(b.n, 3)
+    dp.dp_precond_apply(p, to_dev(v), z1)
+    dp.dp_precond_apply(p2, to_dev(v), z2)
+    assert relerr(to_host(z1), to_host(z2)) < 1e-12
+
+
+def test_random_star_32768_chooses_dense_w():
+    # 173 segments couple all-to-all through E: the ordering predicts ~6e6 factor
+    # entries, so floor(W) (N_W = 6829) is factored densely on the device
+    b, om, eta, kind = config_boundary("randstar1", 32768)
+    p = problem(b, om, eta, kind)
+    dp.dp_precond_build(p)
+    info = dp.dp_precond_get_info(p)
+    assert info["dense_w"] == 1 and info["m"] > 100
+    F = np.exp(1j * om * b.x[:, 0])[:, None] * -1.0
+    q = empty(b.n, 1)
+    res = dp.dp_solve(p, to_dev(F), q, tol=1e-8, use_precond=True)
+    assert res["converged"] and res["relres_max"] <= 1e-8
+    q2 = empty(b.n, 1)
+    res2 = dp.dp_solve(p, to_dev(F), q2, tol=1e-8, use_precond=False, max_iters=400)
+    assert res["iters_max"] < res2["iters_max"]
+    assert relerr(to_host(q), to_host(q2)) < 1e-6
