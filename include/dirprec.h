@@ -111,8 +111,8 @@ typedef struct {
   int m_c;         /* Chebyshev grid size for e_ij (Sec. 3: 10); default 10 */
   double t_keep;   /* floor(T_i) keeps ~t_keep*|K_i| entries (Sec. 2.2); 0 = all; default 3 */
   int w_solver;    /* factorisation of floor(W): 0 = automatic (host sparse LU unless the
-                      fill-reducing ordering predicts more than max(1.5e6, 8 nnz) factor
-                      entries, then dense LU on the device), 1 = sparse, 2 = dense; default 0 */
+                      fill-reducing ordering predicts more than 32 NW factor entries, then
+                      dense LU on the device), 1 = sparse, 2 = dense; default 0 */
 } dp_precond_opts;
 
 typedef struct {

@@ -226,25 +226,44 @@ __global__ __launch_bounds__(256) void trsm_upper(const cplx* __restrict__ U, in
 }
 
 // C (M x N) -= A (M x K) B (K x N), K <= 64, on the FP64 matrix cores.
-// Block: 4 waves, a 64 x 64 tile of C; A and B tiles staged in LDS k-major
-// (As[k][i], Bs[k][j]) so that the MFMA operands A[i][k] (lane i + 16k) and
-// B[k][j] (lane j + 16k) are 16-element contiguous runs.  Each wave owns a
-// 32 x 32 quarter (2 x 2 tiles of 16 x 16) with three accumulators per tile:
+// Block: 4 waves, a 64 x 64 tile of C.  K runs in chunks of 16 through a
+// double-buffered LDS stage, k-major (As[k][i], Bs[k][j]) so that the MFMA
+// operands A[i][k] (lane i + 16k) and B[k][j] (lane j + 16k) are 16-element
+// contiguous runs; each thread loads its 4 + 4 elements of the next chunk
+// into registers before the current chunk's products and stores them after
+// the barrier (67 KB of LDS: two blocks per CU).  Each wave owns a 32 x 32
+// quarter (2 x 2 tiles of 16 x 16) with three accumulators per tile:
 // T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi); C -= (T1 - T2) + i (T3 - T1 - T2).
 // Result layout: register r of lane L holds row 4r + L/16, column L mod 16.
+constexpr int kKC = 16;
 __global__ __launch_bounds__(256) void zgemm_sub(const cplx* __restrict__ A, int lda, const cplx* __restrict__ B,
                                                  int ldb, cplx* C, int ldc, int M, int N, int K) {
-  __shared__ cplx As[kNB][kNB + 1];
-  __shared__ cplx Bs[kNB][kNB + 1];
+  __shared__ cplx As[2][kKC][kNB + 1];
+  __shared__ cplx Bs[2][kKC][kNB + 1];
   const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int i = e & 63, k = e >> 6;
-    As[k][i] = (m0 + i < M && k < K) ? A[(size_t)k * lda + m0 + i] : cplx{0.0, 0.0};
-    const int kk = e & 63, jj = e >> 6;
-    Bs[kk][jj] = (kk < K && n0 + jj < N) ? B[(size_t)(n0 + jj) * ldb + kk] : cplx{0.0, 0.0};
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  // element q of a chunk (q = tid + 256 e, e < 4): A (i = q mod 64, k = q / 64),
+  // B (k = q mod 16, j = q / 16)
+  cplx ra[4], rb[4];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int q = tid + 256 * e;
+      const int i = q & 63, ka = kc + (q >> 6);
+      ra[e] = (m0 + i < M && ka < K) ? A[(size_t)ka * lda + m0 + i] : cplx{0.0, 0.0};
+      const int kb = kc + (q & 15), j = q >> 4;
+      rb[e] = (kb < K && n0 + j < N) ? B[(size_t)(n0 + j) * ldb + kb] : cplx{0.0, 0.0};
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int q = tid + 256 * e;
+      As[buf][q >> 6][q & 63] = ra[e];
+      Bs[buf][q & 15][q >> 4] = rb[e];
+    }
+  };
+  const int lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int i0 = 32 * (w & 1), j0 = 32 * (w >> 1);
   dbl4 T1[2][2], T2[2][2], T3[2][2];
@@ -256,24 +275,35 @@ __global__ __launch_bounds__(256) void zgemm_sub(const cplx* __restrict__ A, int
       T2[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
       T3[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
     }
-  const int ks = (K + 3) / 4;
-  for (int s = 0; s < ks; ++s) {
-    const int k = 4 * s + lk;
-    cplx a[2], b[2];
+  const int nch = (K + kKC - 1) / kKC;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nch;
+    if (more) load((ch + 1) * kKC);
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      a[t] = As[k][i0 + 16 * t + li];
-      b[t] = Bs[k][j0 + 16 * t + li];
-    }
+    for (int s = 0; s < kKC / 4; ++s) {
+      const int k = 4 * s + lk;
+      cplx a[2], b[2];
 #pragma unroll
-    for (int ta = 0; ta < 2; ++ta)
-#pragma unroll
-      for (int tb = 0; tb < 2; ++tb) {
-        T1[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].re, b[tb].re, T1[ta][tb], 0, 0, 0);
-        T2[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].im, b[tb].im, T2[ta][tb], 0, 0, 0);
-        T3[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].re + a[ta].im, b[tb].re + b[tb].im, T3[ta][tb],
-                                                          0, 0, 0);
+      for (int t = 0; t < 2; ++t) {
+        a[t] = As[buf][k][i0 + 16 * t + li];
+        b[t] = Bs[buf][k][j0 + 16 * t + li];
       }
+#pragma unroll
+      for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb) {
+          T1[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].re, b[tb].re, T1[ta][tb], 0, 0, 0);
+          T2[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].im, b[tb].im, T2[ta][tb], 0, 0, 0);
+          T3[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].re + a[ta].im, b[tb].re + b[tb].im,
+                                                            T3[ta][tb], 0, 0, 0);
+        }
+    }
+    if (more) store(buf ^ 1);  // the other buffer was last read before the previous barrier
+    __syncthreads();
   }
 #pragma unroll
   for (int ta = 0; ta < 2; ++ta)

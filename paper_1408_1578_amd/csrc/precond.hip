@@ -855,10 +855,11 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     cp[c + 1] = (int)ri.size();
   }
   P->nnzW = (int64_t)ri.size();
-  // Host sparse LU unless the ordering predicts heavy fill (many segments
-  // coupled all-to-all through E); then a dense LU on the device.
-  const int64_t fill_cap =
-      o->w_solver == 1 ? INT64_MAX : std::max<int64_t>(1500000, 8 * P->nnzW);
+  // Host sparse LU unless the ordering predicts more than 32 factor entries
+  // per row (many segments coupled all-to-all through E): then the sparse
+  // solves are slower than dense ones and the host factorisation takes
+  // seconds, so floor(W) is factored densely on the device instead.
+  const int64_t fill_cap = o->w_solver == 1 ? INT64_MAX : 32 * (int64_t)NW;
   rc = o->w_solver == 2 ? kSparseFillLimit : sparse_lu_factor(NW, cp, ri, vx, P->lu, fill_cap);
   if (rc == kSparseFillLimit) {
     if ((double)NW * NW * sizeof(cplx) > 48.0 * (1 << 30)) {
