@@ -103,6 +103,91 @@ def cpu_baseline(b, om, eta, nrhs, budget_s=25.0):
     }
 
 
+def serve_stream(dp, nreq, rate, slots, seed=7):
+    """Serving stream: Poisson arrivals of independent solve requests on the
+    seeded random-star family, n = 2^k log-uniform in [2048, 65536], soft and
+    hard 50/50, 1-16 plane waves each, 10 points per wavelength, eta = omega,
+    preconditioned, tolerance 1e-8 (FP64 residual).  The same stream (same
+    arrival times) is served by the mixed-precision and by the FP64 solver."""
+    import threading
+    from synth import omega_for_ppw, sample_boundary
+
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    arrivals -= arrivals[0]
+    geo = {}
+    reqs = []
+    t0 = time.perf_counter()
+    for k in range(nreq):
+        n = int(2 ** int(np.rint(rng.uniform(11, 16))))
+        gs = int(rng.integers(0, 4))
+        kind = int(rng.integers(0, 2))
+        nrhs = int(rng.integers(1, 17))
+        ang = rng.uniform(0, 2 * np.pi, nrhs)
+        if (gs, n) not in geo:
+            geo[(gs, n)] = sample_boundary(f"randstar{gs}", n)
+        b = geo[(gs, n)]
+        om = omega_for_ppw(n, b.L, 10.0)
+        reqs.append((b, om, kind, ang))
+    t_geo = time.perf_counter() - t0
+
+    def run(precision):
+        srv = dp.Server(slots=slots)
+        # warm-up: one small request (kernel loading)
+        b, om, kind, ang = reqs[0]
+        srv.wait(srv.submit(b, om, om, kind, angles=ang, precision=precision))
+        ids = [None] * nreq
+        start = time.perf_counter()
+
+        def submitter():
+            for k, (b, om, kind, ang) in enumerate(reqs):
+                d = start + arrivals[k] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                ids[k] = srv.submit(b, om, om, kind, angles=ang, precision=precision)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        res = []
+        for k in range(nreq):
+            while ids[k] is None:
+                time.sleep(0.001)
+            res.append(srv.wait(ids[k]))
+        th.join()
+        st = srv.stats()
+        srv.close()
+        lat = np.array([t["t_done"] - t["t_submit"] for _, _, t, _ in res])
+        qw = np.array([t["t_admit"] - t["t_submit"] for _, _, t, _ in res])
+        t_first = min(t["t_submit"] for _, _, t, _ in res)
+        t_last = max(t["t_done"] for _, _, t, _ in res)
+        ev = sorted([(t["t_admit"], 1) for _, _, t, _ in res] + [(t["t_done"], -1) for _, _, t, _ in res])
+        conc = peak = 0
+        for _, d in ev:
+            conc += d
+            peak = max(peak, conc)
+        solves = sum(r[3].size for r in reqs)
+        return {
+            "solves_per_s": solves / (t_last - t_first),
+            "requests_per_s": nreq / (t_last - t_first),
+            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+                           "max": float(lat.max() * 1e3)},
+            "queue_wait_ms_mean": float(qw.mean() * 1e3),
+            "makespan_s": t_last - t_first,
+            "peak_concurrent": peak,
+            "converged": all(r[3] == dp.DP_OK for r in res),
+            "relres_max": float(max(r[1]["relres_max"] for r in res)),
+            "mem_peak_gb": st["mem_peak"] / 1e9,
+        }
+
+    out = {"requests": nreq, "arrival_rate_per_s": rate, "slots": slots, "rhs_total": int(sum(r[3].size for r in reqs)),
+           "n_range": [int(min(r[0].n for r in reqs)), int(max(r[0].n for r in reqs))],
+           "hard_fraction": float(np.mean([r[2] for r in reqs])), "geometry_prep_s": t_geo}
+    for name, prec in (("mixed", dp.DP_PREC_MIXED), ("fp64", dp.DP_PREC_FP64)):
+        out[name] = run(prec)
+        log(f"serve [{name}]: {json.dumps(out[name])}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +201,10 @@ def main():
                     help="fp64: GMRES on the FP64 operator; mixed: iterative refinement with "
                          "FP32-operator corrections and FP64 residuals (same 1e-8 FP64 residual); "
                          "both (default): mixed is the reported value, FP64 is reported beside it")
+    ap.add_argument("--serve", type=int, default=32, metavar="N",
+                    help="also serve a stream of N independent requests (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=2.5, help="mean arrivals per second")
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -266,6 +355,9 @@ def main():
     out["precond_setup_s"] = float(pinfo.get("t_setup", 0.0))
     if pinfo:
         out["precond"] = {k: pinfo[k] for k in ("m", "NW", "nnzW", "nnzLU", "levels")}
+    if args.serve > 0:
+        log(f"serving stream: {args.serve} requests ...")
+        out["serving"] = serve_stream(dp, args.serve, args.serve_rate, args.serve_slots)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(b, om, eta, nrhs)
