@@ -111,6 +111,8 @@ struct dp_problem {
   dp::DevBuf near_ptr;  // int[n + 1]
   dp::DevBuf near_col;  // int[near_nnz]
   dp::DevBuf near_out;  // near-field sums [nd][nrp][n]
+  dp::DevBuf near_kv[5];       // kernel values of the entries, per sweep operator ([q][nd])
+  bool near_kv_ready[5] = {};
   dp::DevBuf tmp1, tmp2, tmp3;
   dp::Precond* pc = nullptr;
   dp::SweepClock clock;    // FP64 sweep launches

@@ -7,8 +7,9 @@
 // and return 0 for pairs with r^2 < r2near = (DP_HANKEL_ZA/omega)^2.  Those
 // pairs, about 2 DP_HANKEL_ZA/(omega h) per row for node spacing h (about 80
 // at 10 points per wavelength), are listed here once per problem (CSR by
-// target row, sources ascending) and applied by near_apply in FP64, which
-// writes its sums to a buffer that the sweep epilogue adds.  Both sides decide
+// target row, sources ascending), their kernel values are evaluated once per
+// operator on first use, and near_apply multiplies them into the densities in
+// FP64, writing sums that the sweep epilogue adds.  Both sides decide
 // "near" with pair_r2, so every off-diagonal pair is applied exactly once.
 #include "sweep_pair.hpp"
 
@@ -64,13 +65,35 @@ struct NearParams {
   const double* C;
   const int* ptr;
   const int* col;
+  const cplx* kv;    // kernel values of the entries [q][nd], computed once per operator
   const void* dens;  // packed densities [j][nd][nrp] (cplx or cplxf)
   cplx* out;         // [nd][nrp][n]
   int n, nrp;
   double omega, eta, dt;
 };
 
-// One wave per target row (4 rows per block).  Lane l evaluates the kernel
+// Kernel values of every near-field entry (one wave per row, lanes over the
+// row's entries); they depend only on the problem and the operator.
+template <int OP>
+__global__ __launch_bounds__(256) void near_values(NearParams p, cplx* kv) {
+  constexpr int ND = Nd<OP>::v;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= p.n) return;
+  const int lane = threadIdx.x & 63;
+  const SrcRec tr = p.src[i];
+  const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
+  for (int q = p.ptr[i] + lane; q < p.ptr[i + 1]; q += 64) {
+    const int j = p.col[q];
+    int k = i - j;
+    k += (k < 0) ? p.n : 0;
+    cplx K[ND];
+    pair_kernel_near<OP>(t, p.src[j], p.C[k], p.omega, p.eta, p.dt, K);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) kv[(size_t)q * ND + d] = K[d];
+  }
+}
+
+// One wave per target row (4 rows per block).  Lane l reads the kernel
 // values of the row's near entry base + l; then lane (g, c), c < nrp,
 // g < 64/nrp, accumulates entries l = g (mod 64/nrp) of column c, taking the
 // values by cross-lane shuffles, and a butterfly over g sums the groups.
@@ -88,8 +111,6 @@ __global__ __launch_bounds__(256) void near_apply(NearParams p) {
   const int nrp = p.nrp;
   const int G = 64 / nrp;
   const int c = lane % nrp, g = lane / nrp;
-  const SrcRec tr = p.src[i];
-  const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
   const DT* dens = static_cast<const DT*>(p.dens);
   cplx acc[ND];
 #pragma unroll
@@ -103,9 +124,8 @@ __global__ __launch_bounds__(256) void near_apply(NearParams p) {
     for (int d = 0; d < ND; ++d) K[d] = {0.0, 0.0};
     if (lane < cnt) {
       j = p.col[base + lane];
-      int k = i - j;
-      k += (k < 0) ? p.n : 0;
-      pair_kernel_near<OP>(t, p.src[j], p.C[k], p.omega, p.eta, p.dt, K);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) K[d] = p.kv[(size_t)(base + lane) * ND + d];
     }
     for (int l0 = 0; l0 < cnt; l0 += G) {
       const int l = l0 + g;  // < 64
@@ -129,6 +149,17 @@ __global__ __launch_bounds__(256) void near_apply(NearParams p) {
   if (g == 0)
 #pragma unroll
     for (int d = 0; d < ND; ++d) p.out[((size_t)d * nrp + c) * p.n + i] = acc[d];
+}
+
+void launch_values(int op, const NearParams& np, cplx* kv, hipStream_t st) {
+  const int grid = (np.n + 3) / 4;
+  switch (op) {
+    case OP_SOFT: near_values<OP_SOFT><<<grid, 256, 0, st>>>(np, kv); break;
+    case OP_HARD: near_values<OP_HARD><<<grid, 256, 0, st>>>(np, kv); break;
+    case OP_S: near_values<OP_S><<<grid, 256, 0, st>>>(np, kv); break;
+    case OP_D: near_values<OP_D><<<grid, 256, 0, st>>>(np, kv); break;
+    default: near_values<OP_DP><<<grid, 256, 0, st>>>(np, kv); break;
+  }
 }
 
 template <class DT>
@@ -199,6 +230,13 @@ int near_apply_group(dp_problem* p, int op, int nrp, const void* dens, bool dens
   np.omega = p->omega;
   np.eta = p->eta;
   np.dt = 2.0 * kPi / p->n;
+  if (!p->near_kv_ready[op]) {
+    DP_TRY(p->near_kv[op].reserve((size_t)p->near_nnz * nd * sizeof(cplx)));
+    launch_values(op, np, p->near_kv[op].as<cplx>(), p->ctx->stream);
+    DP_HIP(hipGetLastError());
+    p->near_kv_ready[op] = true;
+  }
+  np.kv = p->near_kv[op].as<cplx>();
   if (dens32) launch_near<cplxf>(op, np, p->ctx->stream);
   else launch_near<cplx>(op, np, p->ctx->stream);
   DP_HIP(hipGetLastError());
