@@ -113,6 +113,9 @@ typedef struct {
   int w_solver;    /* factorisation of floor(W): 0 = automatic (host sparse LU unless the
                       fill-reducing ordering predicts more than 32 NW factor entries, then
                       dense LU on the device), 1 = sparse, 2 = dense; default 0 */
+  int graphs;      /* 1: after the first dp_precond_apply with a given column count,
+                      capture the apply's kernels into a HIP graph and replay it;
+                      0: launch them one by one; default 1 */
 } dp_precond_opts;
 
 typedef struct {

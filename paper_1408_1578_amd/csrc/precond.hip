@@ -65,6 +65,11 @@ struct Precond {
   DenseLU dlu;
   int64_t nnzW = 0;
   DevBuf wy, wg, wz, wu, wt, wn;  // apply workspaces
+  // graph of the apply (input win, output wq), captured for g_nrhs columns
+  bool graphs = true;
+  hipGraphExec_t gexec = nullptr;
+  int g_nrhs = -1, g_calls = 0;
+  DevBuf win, wq;
   double t_setup = 0;
 };
 
@@ -689,6 +694,7 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
   const int n = (int)p->n;
   const double L = p->L, ds = L / n, omega = p->omega;
   P->m_c = o->m_c;
+  P->graphs = o->graphs != 0;
   segment_boundary(p, o, P->off, P->len);
   P->m = (int)P->off.size();
   const int m = P->m;
@@ -997,16 +1003,12 @@ static int run_seg_gemm(dp_problem* p, int which, int mrows, int kin, int yoff, 
   return DP_OK;
 }
 
-int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
+// eq. (19) on nrhs columns, kernels only (no allocation, no host sync): the
+// sequence that is captured into a graph.  Workspaces must hold nrhs columns.
+static int apply_core(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
   Precond* P = p->pc;
   hipStream_t st = p->ctx->stream;
   const int n = (int)p->n, NW = P->NW;
-  DP_TRY(P->wy.reserve((size_t)n * nrhs * sizeof(cplx)));
-  DP_TRY(P->wn.reserve((size_t)n * nrhs * sizeof(cplx)));
-  DP_TRY(P->wg.reserve((size_t)NW * nrhs * sizeof(cplx)));
-  DP_TRY(P->wz.reserve((size_t)NW * nrhs * sizeof(cplx)));
-  DP_TRY(P->wu.reserve((size_t)NW * nrhs * sizeof(cplx)));
-  DP_TRY(P->wt.reserve((size_t)NW * nrhs * sizeof(cplx)));
   cplx *y = P->wy.as<cplx>(), *g = P->wg.as<cplx>(), *z = P->wz.as<cplx>(), *u = P->wu.as<cplx>(),
        *t = P->wt.as<cplx>(), *un = P->wn.as<cplx>();
   enum { BINV = 0, UU = 1, UT = 2, TT = 3 };
@@ -1044,6 +1046,59 @@ int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
   return DP_OK;
 }
 
+// Capture apply_core on the workspace input/output into an executable graph.
+static int capture_apply(dp_problem* p, int nrhs) {
+  Precond* P = p->pc;
+  hipStream_t st = p->ctx->stream;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return DP_EDEVICE;
+  const int rc = apply_core(p, nrhs, P->win.as<cplx>(), P->wq.as<cplx>());
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  hipGraphExec_t x = nullptr;
+  const bool ok = rc == DP_OK && e == hipSuccess && g && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+  if (!ok) return DP_EDEVICE;
+  P->gexec = x;
+  return DP_OK;
+}
+
+// z = P v.  The first call for a column count runs eagerly (and sizes the
+// workspaces); the next one captures the kernel sequence into a HIP graph,
+// which later calls replay between a copy of v into the graph's input buffer
+// and a copy of its output into z: one launch instead of a dozen (sparse
+// floor(W)) to a few hundred (dense floor(W)).  If capture fails the
+// preconditioner stays eager.
+int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
+  Precond* P = p->pc;
+  hipStream_t st = p->ctx->stream;
+  const int n = (int)p->n, NW = P->NW;
+  const size_t bn = (size_t)n * nrhs * sizeof(cplx), bw = (size_t)NW * nrhs * sizeof(cplx);
+  DP_TRY(P->wy.reserve(bn));
+  DP_TRY(P->wn.reserve(bn));
+  DP_TRY(P->wg.reserve(bw));
+  DP_TRY(P->wz.reserve(bw));
+  DP_TRY(P->wu.reserve(bw));
+  DP_TRY(P->wt.reserve(bw));
+  if (!P->graphs) return apply_core(p, nrhs, v, q);
+  if (P->g_nrhs != nrhs) {
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    P->gexec = nullptr;
+    P->g_nrhs = nrhs;
+    P->g_calls = 0;
+  }
+  if (!P->gexec && P->g_calls++ >= 1) {
+    DP_TRY(P->win.reserve(bn));
+    DP_TRY(P->wq.reserve(bn));
+    if (capture_apply(p, nrhs) != DP_OK) P->graphs = false;
+  }
+  if (!P->gexec) return apply_core(p, nrhs, v, q);
+  DP_HIP(hipMemcpyAsync(P->win.p, v, bn, hipMemcpyDeviceToDevice, st));
+  DP_HIP(hipGraphLaunch(P->gexec, st));
+  DP_HIP(hipMemcpyAsync(q, P->wq.p, bn, hipMemcpyDeviceToDevice, st));
+  return DP_OK;
+}
+
 void precond_destroy(Precond* P) {
   if (!P) return;
   for (auto& c : P->classes) {
@@ -1058,6 +1113,9 @@ void precond_destroy(Precond* P) {
                     &P->wt, &P->wn, &P->itL, &P->itU, &P->jL2, &P->vL2, &P->jU2, &P->vU2, &P->uinv})
     b->release();
   P->dlu.release();
+  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  P->win.release();
+  P->wq.release();
   delete P;
 }
 

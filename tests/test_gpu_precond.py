@@ -126,3 +126,36 @@ def test_random_star_32768_chooses_dense_w():
     res2 = dp.dp_solve(p, to_dev(F), q2, tol=1e-8, use_precond=False, max_iters=400)
     assert res["iters_max"] < res2["iters_max"]
     assert relerr(to_host(q), to_host(q2)) < 1e-6
+
+
+@pytest.mark.parametrize("cfg,n,kind,ws", [("disk", 1024, 1, dp.W_AUTO), ("kite", 4096, 1, dp.W_DENSE)])
+def test_apply_graph_replays_match_eager(cfg, n, kind, ws):
+    # the apply is replayed from a captured HIP graph from its second call on:
+    # every replay, with eager work and host synchronisation in between, gives
+    # the bits of the apply launched kernel by kernel
+    b, om, eta, _ = config_boundary(cfg, n)
+    pg = problem(b, om, eta, kind)
+    dp.dp_precond_build(pg, w_solver=ws, graphs=True)
+    pe = problem(b, om, eta, kind)
+    dp.dp_precond_build(pe, w_solver=ws, graphs=False)
+    vs = [random_density(b.n, 5, seed=s) for s in range(4)]
+    refs = []
+    for v in vs:
+        z = empty(b.n, 5)
+        dp.dp_precond_apply(pe, to_dev(v), z)
+        refs.append(to_host(z))
+    for rep in range(3):
+        for k, v in enumerate(vs):
+            z = empty(b.n, 5)
+            dp.dp_precond_apply(pg, to_dev(v), z)
+            assert np.array_equal(to_host(z), refs[k]), (rep, k)
+            y = empty(b.n, 5)
+            dp.dp_matvec(pg, to_dev(v), y)
+    # another column count: captured again
+    v = random_density(b.n, 2, seed=9)
+    z2 = empty(b.n, 2)
+    dp.dp_precond_apply(pe, to_dev(v), z2)
+    for _ in range(3):
+        z1 = empty(b.n, 2)
+        dp.dp_precond_apply(pg, to_dev(v), z1)
+        assert np.array_equal(to_host(z1), to_host(z2))
