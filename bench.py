@@ -33,9 +33,10 @@ METRIC = "CFIE solves/s at n=32768 to 1e-8 residual (mixed vs FP64); p50/p99 lat
 PEAK_FP64_VALU = 78.6
 # dense FP32 matrix-core peak, TFLOP/s (the mixed-precision correction sweeps)
 PEAK_FP32_MFMA = 157.3
-# HBM bytes per launch of the two 64-column hard sweeps at n = 32768 (rocprofv3
-# FETCH_SIZE and WRITE_SIZE, scaled by the counts of a 512 MiB device copy in
-# the same run).  They describe the current kernels; a changed kernel must be
+# HBM bytes per launch of the two 64-column hard sweeps at n = 32768 with a
+# 2048-block grid (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the counts of
+# a 512 MiB device copy in the same run).  They describe the current kernels in
+# that configuration; another configuration or a changed kernel must be
 # measured again before these are reported.
 TRAFFIC_FP32_SWEEP = 0.6905e9
 TRAFFIC_FP64_SWEEP = 1.3985e9
@@ -302,19 +303,29 @@ def main():
                                  "frac_fp32_mfma_peak": ach32 / PEAK_FP32_MFMA}
         return out
 
+    # launch configuration of the sweep for this shape, chosen before the timed region
+    tuned = {}
+    for precision in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
+        tuned[precision] = dp.dp_autotune(prob, nrhs, dp.DP_PREC_MIXED if precision == "mixed" else dp.DP_PREC_FP64)
+        log(f"autotune [{precision}]: {tuned[precision]}")
     runs = {}
     for precision in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
         runs[precision] = summary(precision, *run(precision))
     head = "mixed" if "mixed" in runs else "fp64"
     main_run = runs[head]
     pinfo = dp.dp_precond_get_info(prob) if use_pc else {}
+
+    def measured_cfg(precision):
+        # the counters were taken at this shape with a 2048-block grid
+        return b.n == 32768 and nrhs == 64 and tuned.get(precision, {}).get("target_blocks") == 2048
+
     if head == "mixed":
         sw = main_run["sweep_fp32"]
         roof = {"kernel": "sweep_mfma<hard, 64 columns, FP32> (FP32 kernel values and v_mfma_f32_16x16x4 "
                           "products, FP64 phase reduction; 8 waves, shared kernel values, LDS density tiles)",
                 "bound": "mfma", "achieved": sw["tflops"], "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
                 "frac": sw["tflops"] / PEAK_FP32_MFMA,
-                "traffic": TRAFFIC_FP32_SWEEP if (b.n == 32768 and nrhs == 64) else None, "launch_ms": sw["launch_ms"],
+                "traffic": TRAFFIC_FP32_SWEEP if measured_cfg("mixed") else None, "launch_ms": sw["launch_ms"],
                 "launches": sw["launches"], "flops_per_launch": flops}
     else:
         sw = main_run["sweep_fp64"]
@@ -322,7 +333,7 @@ def main():
                           "shared kernel values, LDS density tiles)",
                 "bound": "mfma", "achieved": sw["tflops"], "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
                 "frac": sw["tflops"] / PEAK_FP64_VALU,
-                "traffic": TRAFFIC_FP64_SWEEP if (b.n == 32768 and nrhs == 64) else None, "launch_ms": sw["launch_ms"],
+                "traffic": TRAFFIC_FP64_SWEEP if measured_cfg("fp64") else None, "launch_ms": sw["launch_ms"],
                 "launches": sw["launches"], "flops_per_launch": flops}
     out = {
         "metric": METRIC,
@@ -351,6 +362,7 @@ def main():
         "latency_ms": main_run["latency_ms"],
         "roofline": roof,
         "precision_runs": runs,
+        "autotune": tuned,
     }
     out["precond_setup_s"] = float(pinfo.get("t_setup", 0.0))
     if pinfo:

@@ -196,6 +196,25 @@ typedef struct {
 int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_solve_opts* opts,
              dp_solve_info* info, int64_t* iters, double* relres);
 
+/* ------------------------------------------------------------------ autotuning */
+typedef struct {
+  double t_default_ms;   /* one sweep of nrhs columns with the default launch configuration */
+  double t_best_ms;      /* with the chosen configuration */
+  int64_t target_blocks; /* grid size the source chunking aims at (1024..8192) */
+  int64_t matrix_cores;  /* 1 if the chosen sweep runs on the matrix cores */
+  int64_t candidates;    /* configurations timed */
+} dp_tune_info;
+
+/* Time the problem's operator sweep (nrhs columns, up to 64, in the given
+ * precision: DP_PREC_FP64 or DP_PREC_MIXED) over its candidate launch
+ * configurations (grid sizes; for FP64 with 5-16 columns also the VALU kernel
+ * against the matrix-core kernel padded to 32 columns) and keep the fastest
+ * for later calls on this problem with the same column count.  A
+ * configuration fixes the order of the partial sums, so results are
+ * reproducible once it is chosen; they may differ in the last bits from
+ * another configuration's.  info may be NULL. */
+int dp_autotune(dp_problem* p, int64_t nrhs, int precision, dp_tune_info* info);
+
 /* ------------------------------------------------------------------ serving */
 /* A request server for streams of independent solves (different n, omega,
  * geometries, boundary conditions and right-hand-side counts).  Each request

@@ -31,7 +31,7 @@ EXPORTED = [
     "dp_problem_destroy", "dp_rhs_plane_wave", "dp_matvec", "dp_matvec_mixed", "dp_layer_apply",
     "dp_precond_build", "dp_precond_apply", "dp_precond_get_info", "dp_precond_export",
     "dp_solve", "dp_hankel_dev", "dp_hankel_host",
-    "dp_server_create", "dp_server_submit", "dp_server_wait", "dp_server_get_stats", "dp_server_destroy",
+    "dp_autotune", "dp_server_create", "dp_server_submit", "dp_server_wait", "dp_server_get_stats", "dp_server_destroy",
 ]
 
 
@@ -70,6 +70,11 @@ class SolveInfo(ctypes.Structure):
                 ("sweep_launches", ctypes.c_int64), ("t_sweep", ctypes.c_double),
                 ("refinements", ctypes.c_int64), ("matvecs_fp32", ctypes.c_int64),
                 ("sweep_launches_fp32", ctypes.c_int64), ("t_sweep_fp32", ctypes.c_double)]
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("t_default_ms", ctypes.c_double), ("t_best_ms", ctypes.c_double),
+                ("target_blocks", ctypes.c_int64), ("matrix_cores", ctypes.c_int64), ("candidates", ctypes.c_int64)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -132,6 +137,7 @@ def lib():
         "dp_solve": (ci, [vp, i64, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp, vp]),
         "dp_hankel_dev": (ci, [vp, i64, vp, vp]),
         "dp_hankel_host": (ci, [i64, vp, vp]),
+        "dp_autotune": (ci, [vp, i64, ci, ctypes.POINTER(TuneInfo)]),
         "dp_server_create": (ci, [ci, ctypes.POINTER(ServerOpts), pp]),
         "dp_server_submit": (ci, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]),
         "dp_server_wait": (ci, [vp, i64, vp, ctypes.POINTER(SolveInfo), ctypes.POINTER(RequestTimes)]),
@@ -325,6 +331,12 @@ def dp_solve(p, f, q, tol=1e-8, restart=80, max_iters=2000, use_precond=False, p
     out["iters"] = its
     out["relres"] = rel
     return out
+
+
+def dp_autotune(p, nrhs, precision=DP_PREC_FP64):
+    info = TuneInfo()
+    _check("dp_autotune", lib().dp_autotune(p.h, int(nrhs), int(precision), ctypes.byref(info)))
+    return {f_: getattr(info, f_) for f_, _ in TuneInfo._fields_}
 
 
 def dp_hankel_dev(ctx, z, out):

@@ -227,6 +227,13 @@ int dp_layer_apply(dp_problem* p, int op, int64_t nrhs, const double* q, double*
   return DP_OK;
 }
 
+int dp_autotune(dp_problem* p, int64_t nrhs, int precision, dp_tune_info* info) {
+  DP_CHECK(p != nullptr && nrhs >= 1, "dp_autotune: bad argument");
+  DP_CHECK(precision == DP_PREC_FP64 || precision == DP_PREC_MIXED, "dp_autotune: precision %d", precision);
+  DP_SETDEV(p->ctx);
+  return autotune(p, (int)std::min<int64_t>(nrhs, 64), precision, info);
+}
+
 int dp_precond_build(dp_problem* p, const dp_precond_opts* opts) {
   DP_CHECK(p != nullptr, "dp_precond_build: NULL problem");
   DP_CHECK(p->equispaced, "dp_precond_build: nodes must be arclength-equispaced (equal weights)");

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/dirprec.h"
@@ -115,6 +116,13 @@ struct dp_problem {
   bool near_kv_ready[5] = {};
   dp::DevBuf tmp1, tmp2, tmp3;
   dp::Precond* pc = nullptr;
+  // sweep launch configuration per (precision, operator, padded column count),
+  // chosen by dp_autotune; absent keys use the default rule
+  struct SweepCfg {
+    int target_blocks = 2048;  // blocks of the sweep grid the source chunking aims at
+    int mfma = -1;             // FP64, 8-16 columns: 0 VALU kernel, 1 matrix cores (padded to 32), -1 default
+  };
+  std::map<int, SweepCfg> tuned;
   dp::SweepClock clock;    // FP64 sweep launches
   dp::SweepClock clock32;  // single-precision sweep launches
 };
@@ -127,6 +135,7 @@ int build_tables(dp_problem* p);
 // geometry, phase reduction, small-argument Hankel values and diagonal terms)
 int sweep_apply(dp_problem* p, int op, int nrhs, const cplx* q, cplx* y, int prec = 0);
 int near_build(dp_problem* p);
+int autotune(dp_problem* p, int nrhs, int prec, dp_tune_info* info);
 // near.hip: near-field sums of one sweep group into p->near_out (no-op without near pairs)
 int near_apply_group(dp_problem* p, int op, int nrp, const void* dens, bool dens32);
 int matvec(dp_problem* p, int nrhs, const cplx* q, cplx* y, int prec = 0);

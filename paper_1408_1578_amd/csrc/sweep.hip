@@ -455,6 +455,8 @@ static int pad_cols(int nrhs) {
   return r;
 }
 
+static int tune_key(int prec, int op, int nrp) { return prec * 1000 + op * 100 + nrp; }
+
 // Core sweep over one group of <= 64 columns.  a (and b for hard) are the
 // densities; results go to out0 (and out1).
 static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a, const cplx* b,
@@ -463,11 +465,18 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   const int n = (int)p->n;
   const int nd = op == OP_HARD ? 2 : 1;
   int nrp = pad_cols(nrhs);
-  if (prec && nrp > 4 && nrp < 32) nrp = 32;  // matrix-core shape for every multi-column mixed sweep
+  dp_problem::SweepCfg cfg;
+  {
+    const auto it = p->tuned.find(tune_key(prec, op, nrp));
+    if (it != p->tuned.end()) cfg = it->second;
+  }
+  // matrix-core shape for every multi-column mixed sweep, and for FP64 sweeps
+  // of 8-16 columns when the autotuner found it faster than the VALU kernel
+  if (nrp > 4 && nrp < 32 && (prec || cfg.mfma == 1)) nrp = 32;
   const bool part32 = prec && nrp > 4;
   const int rows_per_block = nrp <= 4 ? 256 : 64;
   const int bx = (n + rows_per_block - 1) / rows_per_block;
-  int nchunks = (2048 + bx - 1) / bx;
+  int nchunks = (cfg.target_blocks + bx - 1) / bx;
   int maxch = n / 64 > 0 ? n / 64 : 1;
   if (nchunks > maxch) nchunks = maxch;
   if (nchunks < 1) nchunks = 1;
@@ -542,6 +551,83 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   if (part32) sweep_epilogue<cplxf><<<grid1d((size_t)n * nrhs), 256, 0, st>>>(e);
   else sweep_epilogue<cplx><<<grid1d((size_t)n * nrhs), 256, 0, st>>>(e);
   DP_HIP(hipGetLastError());
+  return DP_OK;
+}
+
+// Time whole single-group sweeps (packing, sweep, near field, epilogue) of
+// this problem's operator over the candidate launch configurations and keep
+// the fastest for (precision, operator, column count).  The configuration
+// changes the order in which partial sums are added, so results are
+// reproducible for a given configuration, which stays fixed once chosen.
+int autotune(dp_problem* p, int nrhs, int prec, dp_tune_info* info) {
+  hipStream_t st = p->ctx->stream;
+  const int n = (int)p->n;
+  const int op = p->kind == DP_HARD ? OP_HARD : OP_SOFT;
+  const int ng = nrhs < 64 ? nrhs : 64;
+  const int nrp = pad_cols(ng);
+  const int key = tune_key(prec, op, nrp);
+  const size_t bytes = (size_t)n * ng * sizeof(cplx);
+  DevBuf a, b, o0, o1;
+  DP_TRY(a.reserve(bytes));
+  DP_TRY(b.reserve(bytes));
+  DP_TRY(o0.reserve(bytes));
+  DP_TRY(o1.reserve(bytes));
+  DP_HIP(hipMemsetAsync(a.p, 0, bytes, st));
+  DP_HIP(hipMemsetAsync(b.p, 0, bytes, st));
+  std::vector<dp_problem::SweepCfg> cands;
+  const int modes = (!prec && (nrp == 8 || nrp == 16)) ? 2 : 1;
+  for (int mode = 0; mode < modes; ++mode)
+    for (int tb : {1024, 2048, 4096, 8192}) {
+      dp_problem::SweepCfg c;
+      c.target_blocks = tb;
+      c.mfma = modes == 2 ? mode : -1;
+      cands.push_back(c);
+    }
+  hipEvent_t e0, e1;
+  DP_HIP(hipEventCreate(&e0));
+  DP_HIP(hipEventCreate(&e1));
+  double best = 1e30, t_default = 0;
+  dp_problem::SweepCfg bestc;
+  int rc = DP_OK;
+  for (const auto& c : cands) {
+    p->tuned[key] = c;
+    double t = 1e30;
+    for (int rep = 0; rep < 3 && rc == DP_OK; ++rep) {
+      (void)hipEventRecord(e0, st);
+      rc = sweep_group(p, op, ng, 0, a.as<cplx>(), b.as<cplx>(), o0.as<cplx>(), o1.as<cplx>(), prec);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) rc = DP_EDEVICE;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) t = std::min(t, (double)ms);  // the first run also allocates
+    }
+    if (rc != DP_OK) break;
+    if (c.target_blocks == 2048 && c.mfma <= 0) t_default = t;
+    if (t < best) {
+      best = t;
+      bestc = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->clock.reset();
+  p->clock32.reset();
+  a.release();
+  b.release();
+  o0.release();
+  o1.release();
+  if (rc != DP_OK) {
+    p->tuned.erase(key);
+    return rc;
+  }
+  p->tuned[key] = bestc;
+  if (info) {
+    info->t_default_ms = t_default;
+    info->t_best_ms = best;
+    info->target_blocks = bestc.target_blocks;
+    info->matrix_cores = bestc.mfma == 1 || (prec && nrp > 4) || nrp >= 32 ? 1 : 0;
+    info->candidates = (int64_t)cands.size();
+  }
   return DP_OK;
 }
 

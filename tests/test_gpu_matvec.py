@@ -184,3 +184,20 @@ def test_hard_layers_sampled_rows_32768():
         y = empty(b.n, 2)
         dp.dp_layer_apply(p, op, to_dev(q), y)
         assert relerr(to_host(y)[rows], lay[name] @ q) < 5 * TOL
+
+
+@pytest.mark.parametrize("kind,nrhs,prec", [(1, 16, 0), (1, 64, 1), (0, 3, 0), (0, 8, 0)])
+def test_autotune_keeps_parity_and_determinism(kind, nrhs, prec):
+    b = sample_boundary("kite", 2048)
+    om = omega_for_ppw(2048, b.L, 10.0)
+    A = ny.cfie_matrix(b, om, om, kind)
+    q = random_density(b.n, nrhs, seed=21)
+    p = problem(b, om, om, kind)
+    info = dp.dp_autotune(p, nrhs, prec)
+    assert info["candidates"] >= 4 and 0 < info["t_best_ms"] <= info["t_default_ms"]
+    mv = dp.dp_matvec if prec == 0 else dp.dp_matvec_mixed
+    y1, y2 = empty(b.n, nrhs), empty(b.n, nrhs)
+    mv(p, to_dev(q), y1)
+    mv(p, to_dev(q), y2)
+    assert np.array_equal(to_host(y1), to_host(y2))
+    assert relerr(to_host(y1), A @ q) < (1e-11 if prec == 0 else 1e-5)
