@@ -143,6 +143,13 @@ int dp_precond_build(dp_problem* p, const dp_precond_opts* opts);
  * complex arrays (must not overlap).  DP_ESTATE before dp_precond_build. */
 int dp_precond_apply(dp_problem* p, int64_t nrhs, const double* v, double* z);
 
+/* The same apply with single-precision copies of the size-class tables
+ * (B^{-1}, U, U^t, floor(T)) and of the sparse factors of floor(W), and
+ * single-precision vectors (FP64 in and out; a dense floor(W) is solved in
+ * FP64 between conversions): the preconditioner of the correction solves of
+ * DP_PREC_MIXED.  Relative difference from dp_precond_apply ~1e-6. */
+int dp_precond_apply_mixed(dp_problem* p, int64_t nrhs, const double* v, double* z);
+
 int dp_precond_get_info(dp_problem* p, dp_precond_info* info);
 
 /* Structure export for tests (host arrays, caller-allocated):
@@ -165,7 +172,8 @@ typedef struct {
                        operator (FP32 kernel values and matrix-core products;
                        FP64 geometry, phase reduction, small-argument Hankel
                        values, diagonal terms, Krylov vectors and Givens
-                       rotations) and whose residuals f - A q are FP64 */
+                       rotations) preconditioned by dp_precond_apply_mixed,
+                       and whose residuals f - A q are FP64 */
   double inner_tol; /* mixed: relative tolerance of the correction solves, at least the one
                        that takes every column from its current FP64 residual r to
                        tol/10 (0.1 tol/r for the worst column); default 1e-5 */

@@ -258,6 +258,18 @@ int dp_precond_apply(dp_problem* p, int64_t nrhs, const double* v, double* z) {
   return DP_OK;
 }
 
+int dp_precond_apply_mixed(dp_problem* p, int64_t nrhs, const double* v, double* z) {
+  DP_CHECK(p && v && z && nrhs >= 1 && v != z, "dp_precond_apply_mixed: bad argument");
+  if (!p->pc) {
+    set_error("dp_precond_apply_mixed: call dp_precond_build first");
+    return DP_ESTATE;
+  }
+  DP_SETDEV(p->ctx);
+  DP_TRY(precond_apply(p, (int)nrhs, reinterpret_cast<const cplx*>(v), reinterpret_cast<cplx*>(z), 1));
+  DP_HIP(hipStreamSynchronize(p->ctx->stream));
+  return DP_OK;
+}
+
 int dp_precond_get_info(dp_problem* p, dp_precond_info* info) {
   DP_CHECK(p && info, "dp_precond_get_info: NULL argument");
   if (!p->pc) {

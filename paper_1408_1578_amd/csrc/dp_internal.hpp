@@ -41,7 +41,6 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
-// One source record: geometry of node j, 64 bytes so one scalar load fetches it.
 // One boundary node (64 bytes): position, outward normal, speed |x'(t)| and
 // curvature in FP64, and FP32 copies of the normal, the trapezoid weight
 // (2 pi/n) |x'(t)| and the speed for the single-precision sweep.
@@ -151,7 +150,8 @@ int solve(dp_problem* p, int nrhs, const cplx* f, cplx* q, const dp_solve_opts* 
           int64_t* iters, double* relres);
 // precond
 int precond_build(dp_problem* p, const dp_precond_opts* o);
-int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* z);
+// prec 1: single-precision tables and vectors (FP64 in and out)
+int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* z, int prec = 0);
 void precond_destroy(Precond* pc);
 int precond_info(dp_problem* p, dp_precond_info* info);
 int precond_export(dp_problem* p, int64_t* seg_off, int64_t* seg_len, int64_t* e_idx, double* e_val);

@@ -279,7 +279,7 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
       cplx* zk = Zp + k * blk;
       if (pre) {
         ta.start(st);
-        DP_TRY(precond_apply(p, nrhs, vk, zk));
+        DP_TRY(precond_apply(p, nrhs, vk, zk, prec));
         ta.stop(st);
         ++applies;
       }

@@ -40,6 +40,7 @@ constexpr double kInv4Pi_p = 0.079577471545947667884441881686257181;
 struct SizeClass {
   int s = 0, J = 0, K = 0;
   DevBuf Binv, U, Ut, Tt, alpha;
+  DevBuf Binv32, U32, Ut32, Tt32;  // single-precision copies (mixed-precision apply)
   std::vector<cplx> T;  // full T_s on the host (antidiagonal goes into floor(W))
 };
 
@@ -49,6 +50,7 @@ struct Precond {
   std::vector<SizeClass> classes;
   DevBuf d_segs;    // int4 per segment: off, len, offK, cls
   DevBuf d_ptrs;    // per class: Binv, U, Ut, Tt pointers
+  DevBuf d_ptrs32;  // the same for the single-precision copies
   DevBuf d_dims;    // per class: s, K
   // E
   std::vector<int> eidx;  // 4 per pair
@@ -59,17 +61,24 @@ struct Precond {
   int nlevL = 0, nlevU = 0;
   // level-ordered copies for the LDS-resident solve
   DevBuf itL, itU, jL2, vL2, jU2, vU2, uinv;
+  DevBuf vL2_32, vU2_32, uinv32;  // single-precision copies
   bool lds_solve = false;
   // dense device LU of floor(W) (when the sparse factors would fill in)
   bool dense_w = false;
   DenseLU dlu;
   int64_t nnzW = 0;
   DevBuf wy, wg, wz, wu, wt, wn;  // apply workspaces
+  DevBuf sy, sg, sz, su, sn, sv, sq;  // single-precision apply workspaces
   // graph of the apply (input win, output wq), captured for g_nrhs columns
   bool graphs = true;
   hipGraphExec_t gexec = nullptr;
   int g_nrhs = -1, g_calls = 0;
   DevBuf win, wq;
+  // the same for the single-precision apply
+  bool graphs32 = true;
+  hipGraphExec_t gexec32 = nullptr;
+  int g32_nrhs = -1, g32_calls = 0;
+  std::vector<void*> g_sig, g32_sig;  // workspace addresses each graph was captured with
   double t_setup = 0;
 };
 
@@ -454,13 +463,14 @@ __global__ __launch_bounds__(128) void e_entries(EArgs a) {
 }
 
 // ------------------------------------------------------------------ apply kernels
+template <class C>
 struct SegGemm {
   const int* segs;     // per segment: off, len, offK, cls
-  const cplx* const* A;  // per class: matrix pointer (row-major), chosen by `which`
+  const C* const* A;   // per class: matrix pointer (row-major), chosen by `which`
   const int* dims;     // per class: s, K
-  const cplx* X;       // input, column-major, leading dim ldx
-  const cplx* Z;       // mode 1: out = Z - A X (leading dim ldy)
-  cplx* Y;
+  const C* X;          // input, column-major, leading dim ldx
+  const C* Z;          // mode 1: out = Z - A X (leading dim ldy)
+  C* Y;
   int ldx, ldy, nrhs;
   int mrows;           // 0: rows = s, 1: rows = K
   int kin;             // 0: inner dim = s (X rows at off), 1: inner = K (X rows at offK)
@@ -468,11 +478,20 @@ struct SegGemm {
   int mode;            // 0: Y = A X, 1: Y = Z - A X
 };
 
+// acc += a b for complex a, b of either precision
+template <class C>
+__device__ __forceinline__ void cfma_t(C& acc, C a, C b) {
+  acc.re = fma(a.re, b.re, fma(-a.im, b.im, acc.re));
+  acc.im = fma(a.re, b.im, fma(a.im, b.re, acc.im));
+}
+
 // Batched per-segment complex GEMM: grid (segment, row tile of 64, column
 // tile of 16); the A tile and the X tile of each 16-deep slice go through LDS.
-__global__ __launch_bounds__(256) void seg_gemm(SegGemm g) {
-  __shared__ cplx As[64][17];
-  __shared__ cplx Xs[16][16];
+// C = cplx (FP64) or cplxf (the single-precision apply).
+template <class C>
+__global__ __launch_bounds__(256) void seg_gemm(SegGemm<C> g) {
+  __shared__ C As[64][17];
+  __shared__ C Xs[16][16];
   const int sg = blockIdx.x;
   const int off = g.segs[4 * sg], offK = g.segs[4 * sg + 2], cls = g.segs[4 * sg + 3];
   const int s = g.dims[2 * cls], K = g.dims[2 * cls + 1];
@@ -481,29 +500,29 @@ __global__ __launch_bounds__(256) void seg_gemm(SegGemm g) {
   const int r0 = blockIdx.y * 64;
   if (r0 >= M) return;
   const int c0 = blockIdx.z * 16;
-  const cplx* A = g.A[cls];
+  const C* A = g.A[cls];
   const int xo = g.kin ? offK : off;
   const int yo = g.yoff ? offK : off;
   const int tr = threadIdx.x / 16;   // 0..15 -> rows tr, tr+16, tr+32, tr+48
   const int tc = threadIdx.x % 16;
-  cplx acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  C acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   for (int k0 = 0; k0 < Kd; k0 += 16) {
     for (int t = threadIdx.x; t < 64 * 16; t += 256) {
       const int rr = t / 16, kk = t % 16;
       const int r = r0 + rr, k = k0 + kk;
-      As[rr][kk] = (r < M && k < Kd) ? A[(size_t)r * Kd + k] : cplx{0.0, 0.0};
+      As[rr][kk] = (r < M && k < Kd) ? A[(size_t)r * Kd + k] : C{0, 0};
     }
     {
       const int kk = threadIdx.x / 16, cc = threadIdx.x % 16;
       const int k = k0 + kk, c = c0 + cc;
-      Xs[kk][cc] = (k < Kd && c < g.nrhs) ? g.X[(size_t)c * g.ldx + xo + k] : cplx{0.0, 0.0};
+      Xs[kk][cc] = (k < Kd && c < g.nrhs) ? g.X[(size_t)c * g.ldx + xo + k] : C{0, 0};
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
-      const cplx xv = Xs[kk][tc];
+      const C xv = Xs[kk][tc];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cfma(acc[q], As[tr + 16 * q][kk], xv);
+      for (int q = 0; q < 4; ++q) cfma_t(acc[q], As[tr + 16 * q][kk], xv);
     }
     __syncthreads();
   }
@@ -515,7 +534,7 @@ __global__ __launch_bounds__(256) void seg_gemm(SegGemm g) {
     if (r >= M) continue;
     const size_t o = (size_t)c * g.ldy + yo + r;
     if (g.mode == 1) {
-      const cplx z = g.Z[o];
+      const C z = g.Z[o];
       g.Y[o] = {z.re - acc[q].re, z.im - acc[q].im};
     } else {
       g.Y[o] = acc[q];
@@ -523,7 +542,16 @@ __global__ __launch_bounds__(256) void seg_gemm(SegGemm g) {
   }
 }
 
-// zp[k] = z[perm[k]] (column-major, leading dim NW)
+// precision conversions of n-element complex arrays
+__global__ void to_single(const cplx* __restrict__ a, cplxf* b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = {(float)a[i].re, (float)a[i].im};
+}
+__global__ void to_double(const cplxf* __restrict__ a, cplx* b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = {(double)a[i].re, (double)a[i].im};
+}
+
 __global__ void gather_rows(const cplx* __restrict__ z, cplx* zp, const int* __restrict__ perm, int NW, int nrhs) {
   const size_t tot = (size_t)NW * nrhs;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
@@ -582,15 +610,17 @@ __global__ __launch_bounds__(1024) void level_solve(cplx* x, const int* __restri
 // dependency level are independent; each row is an item (row, first entry,
 // entry count) in level order, with its entries stored contiguously, so the
 // only accesses that depend on the previous level are LDS reads.
-__global__ __launch_bounds__(256) void tri_solve_lds(const cplx* __restrict__ z, cplx* __restrict__ u, int NW,
+template <class C>
+__global__ __launch_bounds__(256) void tri_solve_lds(const C* __restrict__ z, C* __restrict__ u, int NW,
                                                      const int* __restrict__ pin, const int* __restrict__ pout,
                                                      const int4* __restrict__ itL, const int* __restrict__ lvL,
                                                      int nlevL, const int* __restrict__ jL,
-                                                     const cplx* __restrict__ vL, const int4* __restrict__ itU,
+                                                     const C* __restrict__ vL, const int4* __restrict__ itU,
                                                      const int* __restrict__ lvU, int nlevU,
-                                                     const int* __restrict__ jU, const cplx* __restrict__ vU,
-                                                     const cplx* __restrict__ uinv) {
-  extern __shared__ cplx xs[];
+                                                     const int* __restrict__ jU, const C* __restrict__ vU,
+                                                     const C* __restrict__ uinv) {
+  extern __shared__ unsigned char lds_raw[];
+  C* xs = reinterpret_cast<C*>(lds_raw);
   const size_t c = blockIdx.x;
   for (int k = threadIdx.x; k < NW; k += blockDim.x) xs[k] = z[c * NW + pin[k]];
   __syncthreads();
@@ -603,7 +633,7 @@ __global__ __launch_bounds__(256) void tri_solve_lds(const cplx* __restrict__ z,
     const int4* it_ = pass ? itU : itL;
     const int* lv = pass ? lvU : lvL;
     const int* jj = pass ? jU : jL;
-    const cplx* vv = pass ? vU : vL;
+    const C* vv = pass ? vU : vL;
     const int nlev = pass ? nlevU : nlevL;
     for (int l = 0; l < nlev; ++l) {
       const int b = lv[l], e = lv[l + 1];
@@ -611,9 +641,9 @@ __global__ __launch_bounds__(256) void tri_solve_lds(const cplx* __restrict__ z,
         const int t = t0 + g;
         const bool act = t < e;
         const int4 it = act ? it_[t] : int4{0, 0, 0, 0};
-        cplx acc = {0.0, 0.0};
+        C acc = {0, 0};
         for (int q = it.y + lr; q < it.y + it.z; q += RL) {
-          const cplx a = vv[q], xv = xs[jj[q]];
+          const C a = vv[q], xv = xs[jj[q]];
           acc.re += a.re * xv.re - a.im * xv.im;
           acc.im += a.re * xv.im + a.im * xv.re;
         }
@@ -623,9 +653,12 @@ __global__ __launch_bounds__(256) void tri_solve_lds(const cplx* __restrict__ z,
           acc.im += __shfl_xor(acc.im, off, RL);
         }
         if (act && lr == 0) {
-          const cplx x0 = xs[it.x];
-          cplx r = {x0.re - acc.re, x0.im - acc.im};
-          if (pass) r = cmul(r, uinv[it.x]);
+          const C x0 = xs[it.x];
+          C r = {x0.re - acc.re, x0.im - acc.im};
+          if (pass) {
+            const C w = uinv[it.x];
+            r = {r.re * w.re - r.im * w.im, r.re * w.im + r.im * w.re};
+          }
           xs[it.x] = r;
         }
       }
@@ -925,16 +958,25 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
         const zc inv = 1.0 / lu.Ud[r];
         ui[r] = {inv.real(), inv.imag()};
       }
+      auto single = [](const std::vector<cplx>& a) {
+        std::vector<cplxf> r(a.size());
+        for (size_t q = 0; q < a.size(); ++q) r[q] = {(float)a[q].re, (float)a[q].im};
+        return r;
+      };
       if ((rc = upload(P->itL, itl, st)) || (rc = upload(P->itU, itu, st)) || (rc = upload(P->jL2, jl, st)) ||
           (rc = upload(P->vL2, vl, st)) || (rc = upload(P->jU2, ju, st)) || (rc = upload(P->vU2, vu, st)) ||
-          (rc = upload(P->uinv, ui, st)))
+          (rc = upload(P->uinv, ui, st)) || (rc = upload(P->vL2_32, single(vl), st)) ||
+          (rc = upload(P->vU2_32, single(vu), st)) || (rc = upload(P->uinv32, single(ui), st)))
         return fail(rc);
       int maxlds = 0;
       DP_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->ctx->device));
       P->lds_solve = (size_t)NW * sizeof(cplx) <= (size_t)maxlds;
-      if (P->lds_solve)
-        DP_HIP(hipFuncSetAttribute((const void*)tri_solve_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+      if (P->lds_solve) {
+        DP_HIP(hipFuncSetAttribute((const void*)tri_solve_lds<cplx>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)(NW * sizeof(cplx))));
+        DP_HIP(hipFuncSetAttribute((const void*)tri_solve_lds<cplxf>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(NW * sizeof(cplxf))));
+      }
     }
   }
 
@@ -959,6 +1001,25 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
   if ((rc = upload(P->d_segs, segs, st)) || (rc = upload(P->d_dims, dims, st)) ||
       (rc = upload(P->d_ptrs, ptrs, st)))
     return fail(rc);
+  {
+    std::vector<const cplxf*> ptrs32(4 * nc);
+    for (size_t c = 0; c < nc; ++c) {
+      SizeClass& sc = P->classes[c];
+      const size_t ns = (size_t)sc.s * sc.s, nk = (size_t)sc.s * sc.K, kk = (size_t)sc.K * sc.K;
+      if ((rc = sc.Binv32.reserve(ns * sizeof(cplxf))) || (rc = sc.U32.reserve(nk * sizeof(cplxf))) ||
+          (rc = sc.Ut32.reserve(nk * sizeof(cplxf))) || (rc = sc.Tt32.reserve(kk * sizeof(cplxf))))
+        return fail(rc);
+      to_single<<<grid1(ns), 256, 0, st>>>(sc.Binv.as<cplx>(), sc.Binv32.as<cplxf>(), ns);
+      to_single<<<grid1(nk), 256, 0, st>>>(sc.U.as<cplx>(), sc.U32.as<cplxf>(), nk);
+      to_single<<<grid1(nk), 256, 0, st>>>(sc.Ut.as<cplx>(), sc.Ut32.as<cplxf>(), nk);
+      to_single<<<grid1(kk), 256, 0, st>>>(sc.Tt.as<cplx>(), sc.Tt32.as<cplxf>(), kk);
+      ptrs32[0 * nc + c] = sc.Binv32.as<cplxf>();
+      ptrs32[1 * nc + c] = sc.U32.as<cplxf>();
+      ptrs32[2 * nc + c] = sc.Ut32.as<cplxf>();
+      ptrs32[3 * nc + c] = sc.Tt32.as<cplxf>();
+    }
+    if ((rc = upload(P->d_ptrs32, ptrs32, st))) return fail(rc);
+  }
   DP_HIP(hipStreamSynchronize(st));
   row.release();
   aug.release();
@@ -977,15 +1038,16 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
 }
 
 // ------------------------------------------------------------------ host: apply
-static int run_seg_gemm(dp_problem* p, int which, int mrows, int kin, int yoff, int mode, const cplx* X, int ldx,
-                        const cplx* Z, cplx* Y, int ldy, int nrhs) {
+template <class C>
+static int run_seg_gemm(dp_problem* p, int which, int mrows, int kin, int yoff, int mode, const C* X, int ldx,
+                        const C* Z, C* Y, int ldy, int nrhs) {
   Precond* P = p->pc;
   const size_t nc = P->classes.size();
   int maxM = 0;
   for (auto& c : P->classes) maxM = std::max(maxM, mrows ? c.K : c.s);
-  SegGemm g;
+  SegGemm<C> g;
   g.segs = P->d_segs.as<int>();
-  g.A = P->d_ptrs.as<const cplx*>() + which * nc;
+  g.A = (sizeof(C) == sizeof(cplx) ? P->d_ptrs.as<const C*>() : P->d_ptrs32.as<const C*>()) + which * nc;
   g.dims = P->d_dims.as<int>();
   g.X = X;
   g.Z = Z;
@@ -998,8 +1060,34 @@ static int run_seg_gemm(dp_problem* p, int which, int mrows, int kin, int yoff, 
   g.yoff = yoff;
   g.mode = mode;
   dim3 grid(P->m, (maxM + 63) / 64, (nrhs + 15) / 16);
-  seg_gemm<<<grid, 256, 0, p->ctx->stream>>>(g);
+  seg_gemm<C><<<grid, 256, 0, p->ctx->stream>>>(g);
   DP_HIP(hipGetLastError());
+  return DP_OK;
+}
+
+// u = floor(W)^{-1} z in FP64 (dense device LU, LDS-resident sparse solve, or
+// the level-scheduled sparse solve)
+static int w_solve(dp_problem* p, int nrhs, const cplx* z, cplx* u) {
+  Precond* P = p->pc;
+  hipStream_t st = p->ctx->stream;
+  const int NW = P->NW;
+  if (P->dense_w) return P->dlu.solve(st, z, u, nrhs);
+  if (P->lds_solve) {
+    tri_solve_lds<cplx><<<nrhs, 256, (size_t)NW * sizeof(cplx), st>>>(
+        z, u, NW, P->pin.as<int>(), P->pout.as<int>(), P->itL.as<int4>(), P->lvlL.as<int>(), P->nlevL,
+        P->jL2.as<int>(), P->vL2.as<cplx>(), P->itU.as<int4>(), P->lvlU.as<int>(), P->nlevU, P->jU2.as<int>(),
+        P->vU2.as<cplx>(), P->uinv.as<cplx>());
+    return DP_OK;
+  }
+  cplx* t = P->wt.as<cplx>();
+  gather_rows<<<grid1((size_t)NW * nrhs), 256, 0, st>>>(z, t, P->pin.as<int>(), NW, nrhs);
+  const int cpb = nrhs < 16 ? nrhs : 16;
+  const int nb = (nrhs + cpb - 1) / cpb;
+  level_solve<<<nb, 1024, 0, st>>>(t, P->Lp.as<int>(), P->Lj.as<int>(), P->Lx.as<cplx>(), nullptr,
+                                   P->lvlL.as<int>(), P->lvlLr.as<int>(), P->nlevL, NW, nrhs, cpb);
+  level_solve<<<nb, 1024, 0, st>>>(t, P->Up.as<int>(), P->Uj.as<int>(), P->Ux.as<cplx>(), P->Ud.as<cplx>(),
+                                   P->lvlU.as<int>(), P->lvlUr.as<int>(), P->nlevU, NW, nrhs, cpb);
+  scatter_rows<<<grid1((size_t)NW * nrhs), 256, 0, st>>>(t, u, P->pout.as<int>(), NW, nrhs);
   return DP_OK;
 }
 
@@ -1007,69 +1095,88 @@ static int run_seg_gemm(dp_problem* p, int which, int mrows, int kin, int yoff, 
 // sequence that is captured into a graph.  Workspaces must hold nrhs columns.
 static int apply_core(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
   Precond* P = p->pc;
-  hipStream_t st = p->ctx->stream;
   const int n = (int)p->n, NW = P->NW;
   cplx *y = P->wy.as<cplx>(), *g = P->wg.as<cplx>(), *z = P->wz.as<cplx>(), *u = P->wu.as<cplx>(),
-       *t = P->wt.as<cplx>(), *un = P->wn.as<cplx>();
+       *un = P->wn.as<cplx>();
   enum { BINV = 0, UU = 1, UT = 2, TT = 3 };
   // y = B^{-1} v
-  DP_TRY(run_seg_gemm(p, BINV, 0, 0, 0, 0, v, n, nullptr, y, n, nrhs));
+  DP_TRY(run_seg_gemm<cplx>(p, BINV, 0, 0, 0, 0, v, n, nullptr, y, n, nrhs));
   // g = U^t y
-  DP_TRY(run_seg_gemm(p, UT, 1, 0, 1, 0, y, n, nullptr, g, NW, nrhs));
+  DP_TRY(run_seg_gemm<cplx>(p, UT, 1, 0, 1, 0, y, n, nullptr, g, NW, nrhs));
   // z = floor(T) g
-  DP_TRY(run_seg_gemm(p, TT, 1, 1, 1, 0, g, NW, nullptr, z, NW, nrhs));
+  DP_TRY(run_seg_gemm<cplx>(p, TT, 1, 1, 1, 0, g, NW, nullptr, z, NW, nrhs));
   // u = floor(W)^{-1} z
-  if (P->dense_w) {
-    DP_TRY(P->dlu.solve(st, z, u, nrhs));
-  } else if (P->lds_solve) {
-    tri_solve_lds<<<nrhs, 256, (size_t)NW * sizeof(cplx), st>>>(
-        z, u, NW, P->pin.as<int>(), P->pout.as<int>(), P->itL.as<int4>(), P->lvlL.as<int>(), P->nlevL,
-        P->jL2.as<int>(), P->vL2.as<cplx>(), P->itU.as<int4>(), P->lvlU.as<int>(), P->nlevU, P->jU2.as<int>(),
-        P->vU2.as<cplx>(), P->uinv.as<cplx>());
-  } else {
-    gather_rows<<<grid1((size_t)NW * nrhs), 256, 0, st>>>(z, t, P->pin.as<int>(), NW, nrhs);
-    const int cpb = nrhs < 16 ? nrhs : 16;
-    const int nb = (nrhs + cpb - 1) / cpb;
-    level_solve<<<nb, 1024, 0, st>>>(t, P->Lp.as<int>(), P->Lj.as<int>(), P->Lx.as<cplx>(), nullptr,
-                                     P->lvlL.as<int>(), P->lvlLr.as<int>(), P->nlevL, NW, nrhs, cpb);
-    level_solve<<<nb, 1024, 0, st>>>(t, P->Up.as<int>(), P->Uj.as<int>(), P->Ux.as<cplx>(), P->Ud.as<cplx>(),
-                                     P->lvlU.as<int>(), P->lvlUr.as<int>(), P->nlevU, NW, nrhs, cpb);
-    scatter_rows<<<grid1((size_t)NW * nrhs), 256, 0, st>>>(t, u, P->pout.as<int>(), NW, nrhs);
-  }
+  DP_TRY(w_solve(p, nrhs, z, u));
   // h = z - floor(T) u  (into g)
-  DP_TRY(run_seg_gemm(p, TT, 1, 1, 1, 1, u, NW, z, g, NW, nrhs));
+  DP_TRY(run_seg_gemm<cplx>(p, TT, 1, 1, 1, 1, u, NW, z, g, NW, nrhs));
   // un = U h
-  DP_TRY(run_seg_gemm(p, UU, 0, 1, 0, 0, g, NW, nullptr, un, n, nrhs));
+  DP_TRY(run_seg_gemm<cplx>(p, UU, 0, 1, 0, 0, g, NW, nullptr, un, n, nrhs));
   // q = y - B^{-1} un
-  DP_TRY(run_seg_gemm(p, BINV, 0, 0, 0, 1, un, n, y, q, n, nrhs));
+  DP_TRY(run_seg_gemm<cplx>(p, BINV, 0, 0, 0, 1, un, n, y, q, n, nrhs));
   DP_HIP(hipGetLastError());
   return DP_OK;
 }
 
-// Capture apply_core on the workspace input/output into an executable graph.
-static int capture_apply(dp_problem* p, int nrhs) {
+// The same sequence with single-precision tables and vectors (FP64 in and
+// out).  floor(W) is solved with its single-precision sparse factors in LDS
+// when they fit, otherwise in FP64 between conversions.
+static int apply_core32(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
+  Precond* P = p->pc;
+  hipStream_t st = p->ctx->stream;
+  const int n = (int)p->n, NW = P->NW;
+  const size_t nn = (size_t)n * nrhs, nw = (size_t)NW * nrhs;
+  cplxf *sv = P->sv.as<cplxf>(), *y = P->sy.as<cplxf>(), *g = P->sg.as<cplxf>(), *z = P->sz.as<cplxf>(),
+        *u = P->su.as<cplxf>(), *un = P->sn.as<cplxf>(), *sq = P->sq.as<cplxf>();
+  enum { BINV = 0, UU = 1, UT = 2, TT = 3 };
+  to_single<<<grid1(nn), 256, 0, st>>>(v, sv, nn);
+  DP_TRY(run_seg_gemm<cplxf>(p, BINV, 0, 0, 0, 0, sv, n, nullptr, y, n, nrhs));
+  DP_TRY(run_seg_gemm<cplxf>(p, UT, 1, 0, 1, 0, y, n, nullptr, g, NW, nrhs));
+  DP_TRY(run_seg_gemm<cplxf>(p, TT, 1, 1, 1, 0, g, NW, nullptr, z, NW, nrhs));
+  if (!P->dense_w && P->lds_solve) {
+    tri_solve_lds<cplxf><<<nrhs, 256, (size_t)NW * sizeof(cplxf), st>>>(
+        z, u, NW, P->pin.as<int>(), P->pout.as<int>(), P->itL.as<int4>(), P->lvlL.as<int>(), P->nlevL,
+        P->jL2.as<int>(), P->vL2_32.as<cplxf>(), P->itU.as<int4>(), P->lvlU.as<int>(), P->nlevU, P->jU2.as<int>(),
+        P->vU2_32.as<cplxf>(), P->uinv32.as<cplxf>());
+  } else {
+    to_double<<<grid1(nw), 256, 0, st>>>(z, P->wz.as<cplx>(), nw);
+    DP_TRY(w_solve(p, nrhs, P->wz.as<cplx>(), P->wu.as<cplx>()));
+    to_single<<<grid1(nw), 256, 0, st>>>(P->wu.as<cplx>(), u, nw);
+  }
+  DP_TRY(run_seg_gemm<cplxf>(p, TT, 1, 1, 1, 1, u, NW, z, g, NW, nrhs));
+  DP_TRY(run_seg_gemm<cplxf>(p, UU, 0, 1, 0, 0, g, NW, nullptr, un, n, nrhs));
+  DP_TRY(run_seg_gemm<cplxf>(p, BINV, 0, 0, 0, 1, un, n, y, sq, n, nrhs));
+  to_double<<<grid1(nn), 256, 0, st>>>(sq, q, nn);
+  DP_HIP(hipGetLastError());
+  return DP_OK;
+}
+
+// Capture one of the apply sequences on the workspace input/output into an
+// executable graph.
+static int capture_apply(dp_problem* p, int nrhs, int prec, hipGraphExec_t* out) {
   Precond* P = p->pc;
   hipStream_t st = p->ctx->stream;
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return DP_EDEVICE;
-  const int rc = apply_core(p, nrhs, P->win.as<cplx>(), P->wq.as<cplx>());
+  const int rc = prec ? apply_core32(p, nrhs, P->win.as<cplx>(), P->wq.as<cplx>())
+                      : apply_core(p, nrhs, P->win.as<cplx>(), P->wq.as<cplx>());
   const hipError_t e = hipStreamEndCapture(st, &g);
   hipGraphExec_t x = nullptr;
   const bool ok = rc == DP_OK && e == hipSuccess && g && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess;
   if (g) (void)hipGraphDestroy(g);
   (void)hipGetLastError();
   if (!ok) return DP_EDEVICE;
-  P->gexec = x;
+  *out = x;
   return DP_OK;
 }
 
-// z = P v.  The first call for a column count runs eagerly (and sizes the
-// workspaces); the next one captures the kernel sequence into a HIP graph,
-// which later calls replay between a copy of v into the graph's input buffer
-// and a copy of its output into z: one launch instead of a dozen (sparse
-// floor(W)) to a few hundred (dense floor(W)).  If capture fails the
-// preconditioner stays eager.
-int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
+// z = P v in FP64 (prec 0) or with the single-precision tables (prec 1, the
+// correction solves of the mixed-precision solve).  The first call for a
+// column count runs eagerly (and sizes the workspaces); the next one captures
+// the kernel sequence into a HIP graph, which later calls replay between a
+// copy of v into the graph's input buffer and a copy of its output into z:
+// one launch instead of a dozen (sparse floor(W)) to a few hundred (dense
+// floor(W)).  If capture fails that apply stays eager.
+int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q, int prec) {
   Precond* P = p->pc;
   hipStream_t st = p->ctx->stream;
   const int n = (int)p->n, NW = P->NW;
@@ -1080,21 +1187,46 @@ int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
   DP_TRY(P->wz.reserve(bw));
   DP_TRY(P->wu.reserve(bw));
   DP_TRY(P->wt.reserve(bw));
-  if (!P->graphs) return apply_core(p, nrhs, v, q);
-  if (P->g_nrhs != nrhs) {
-    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
-    P->gexec = nullptr;
-    P->g_nrhs = nrhs;
-    P->g_calls = 0;
+  if (prec) {
+    const size_t sn = bn / 2, sw = bw / 2;
+    DP_TRY(P->sv.reserve(sn));
+    DP_TRY(P->sy.reserve(sn));
+    DP_TRY(P->sn.reserve(sn));
+    DP_TRY(P->sq.reserve(sn));
+    DP_TRY(P->sg.reserve(sw));
+    DP_TRY(P->sz.reserve(sw));
+    DP_TRY(P->su.reserve(sw));
   }
-  if (!P->gexec && P->g_calls++ >= 1) {
+  bool& on = prec ? P->graphs32 : P->graphs;
+  hipGraphExec_t& gx = prec ? P->gexec32 : P->gexec;
+  int& gn = prec ? P->g32_nrhs : P->g_nrhs;
+  int& gc = prec ? P->g32_calls : P->g_calls;
+  std::vector<void*>& gsig = prec ? P->g32_sig : P->g_sig;
+  auto eager = [&]() { return prec ? apply_core32(p, nrhs, v, q) : apply_core(p, nrhs, v, q); };
+  if (!P->graphs || !on) return eager();
+  // a graph holds the workspace addresses it was captured with: a different
+  // column count or any workspace reallocated since (also by the other
+  // precision's apply) means capturing again
+  auto sig = [&]() {
+    return std::vector<void*>{P->wy.p, P->wn.p, P->wg.p, P->wz.p, P->wu.p, P->wt.p, P->sv.p, P->sy.p,
+                              P->sn.p, P->sq.p, P->sg.p, P->sz.p, P->su.p, P->win.p, P->wq.p};
+  };
+  if (gn != nrhs || (gx && sig() != gsig)) {
+    if (gx) (void)hipGraphExecDestroy(gx);
+    gx = nullptr;
+    gc = gn == nrhs ? 1 : 0;
+    gn = nrhs;
+  }
+  if (!gx && gc++ >= 1) {
+    // both precisions' graphs read and write win and wq (never in flight together)
     DP_TRY(P->win.reserve(bn));
     DP_TRY(P->wq.reserve(bn));
-    if (capture_apply(p, nrhs) != DP_OK) P->graphs = false;
+    if (capture_apply(p, nrhs, prec, &gx) != DP_OK) on = false;
+    else gsig = sig();
   }
-  if (!P->gexec) return apply_core(p, nrhs, v, q);
+  if (!gx) return eager();
   DP_HIP(hipMemcpyAsync(P->win.p, v, bn, hipMemcpyDeviceToDevice, st));
-  DP_HIP(hipGraphLaunch(P->gexec, st));
+  DP_HIP(hipGraphLaunch(gx, st));
   DP_HIP(hipMemcpyAsync(q, P->wq.p, bn, hipMemcpyDeviceToDevice, st));
   return DP_OK;
 }
@@ -1114,6 +1246,16 @@ void precond_destroy(Precond* P) {
     b->release();
   P->dlu.release();
   if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  if (P->gexec32) (void)hipGraphExecDestroy(P->gexec32);
+  for (auto& c : P->classes) {
+    c.Binv32.release();
+    c.U32.release();
+    c.Ut32.release();
+    c.Tt32.release();
+  }
+  for (DevBuf* b : {&P->d_ptrs32, &P->vL2_32, &P->vU2_32, &P->uinv32, &P->sy, &P->sg, &P->sz, &P->su, &P->sn,
+                    &P->sv, &P->sq})
+    b->release();
   P->win.release();
   P->wq.release();
   delete P;

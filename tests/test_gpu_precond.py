@@ -159,3 +159,45 @@ def test_apply_graph_replays_match_eager(cfg, n, kind, ws):
         z1 = empty(b.n, 2)
         dp.dp_precond_apply(pg, to_dev(v), z1)
         assert np.array_equal(to_host(z1), to_host(z2))
+
+
+@pytest.mark.parametrize("cfg,n,kind,ws", [("disk", 1024, 0, dp.W_AUTO), ("disk", 1024, 1, dp.W_AUTO),
+                                           ("star", 4096, 0, dp.W_AUTO), ("kite", 4096, 1, dp.W_AUTO),
+                                           ("kite", 4096, 1, dp.W_DENSE)])
+def test_single_precision_apply_parity(cfg, n, kind, ws):
+    # the correction solves' preconditioner: FP32 tables and vectors
+    b, om, eta, _ = config_boundary(cfg, n)
+    P = pc.build(b, om, eta, kind)
+    p = problem(b, om, eta, kind)
+    dp.dp_precond_build(p, w_solver=ws)
+    for nrhs in (1, 20):
+        v = random_density(b.n, nrhs, seed=nrhs + 7)
+        z = empty(b.n, nrhs)
+        for _ in range(3):  # eager, captured, replayed
+            dp.dp_precond_apply_mixed(p, to_dev(v), z)
+            err = relerr(to_host(z), pc.apply(P, v))
+            assert 1e-12 < err < 2e-5
+
+
+def test_graph_recaptured_after_workspace_growth():
+    # a graph keeps the workspace addresses of its capture: growing the
+    # workspaces through the other precision's apply must not leave it stale
+    b, om, eta, kind = config_boundary("disk", 1024)
+    pg = problem(b, om, eta, 1)
+    dp.dp_precond_build(pg)
+    pe = problem(b, om, eta, 1)
+    dp.dp_precond_build(pe, graphs=False)
+    v = random_density(b.n, 5, seed=3)
+    ref = empty(b.n, 5)
+    dp.dp_precond_apply(pe, to_dev(v), ref)
+    z = empty(b.n, 5)
+    for _ in range(3):
+        dp.dp_precond_apply(pg, to_dev(v), z)
+    assert np.array_equal(to_host(z), to_host(ref))
+    w = random_density(b.n, 70, seed=4)
+    for _ in range(3):
+        dp.dp_precond_apply_mixed(pg, to_dev(w), empty(b.n, 70))
+    for _ in range(3):
+        z = empty(b.n, 5)
+        dp.dp_precond_apply(pg, to_dev(v), z)
+        assert np.array_equal(to_host(z), to_host(ref))
