@@ -110,9 +110,10 @@ typedef struct {
   int min_pts;     /* never split a segment below this many points; default 8 */
   int m_c;         /* Chebyshev grid size for e_ij (Sec. 3: 10); default 10 */
   double t_keep;   /* floor(T_i) keeps ~t_keep*|K_i| entries (Sec. 2.2); 0 = all; default 3 */
-  int w_solver;    /* factorisation of floor(W): 0 = automatic (host sparse LU unless the
-                      fill-reducing ordering predicts more than 32 NW factor entries, then
-                      dense LU on the device), 1 = sparse, 2 = dense; default 0 */
+  int w_solver;    /* factorisation of floor(W): 0 = automatic (dense LU on the device when
+                      m (m - 1) > 2 NW or the fill-reducing ordering predicts more than
+                      32 NW factor entries, else host sparse LU), 1 = sparse, 2 = dense;
+                      default 0 */
   int graphs;      /* 1: after the first dp_precond_apply with a given column count,
                       capture the apply's kernels into a HIP graph and replay it;
                       0: launch them one by one; default 1 */

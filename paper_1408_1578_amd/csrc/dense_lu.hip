@@ -15,9 +15,10 @@
 //   3. U12 = L11^{-1} A12 (one wave per column, L11 in LDS);
 //   4. A22 -= L21 U12 on the FP64 matrix cores (v_mfma_f64_16x16x4, complex
 //      products in the 3-multiplication form).
-// The solves apply the row permutation, then blocked forward and backward
-// substitution with the same two kernels (diagonal-block solve, matrix-core
-// update of the remaining rows).  Matrices are column-major with leading
+// After the factorisation the 256 x 256 diagonal blocks of L and U are
+// inverted (with the same kernels); the solves apply the row permutation,
+// then blocked forward and backward substitution made of matrix-core products
+// only (diagonal block by its inverse, update of the remaining rows).  Matrices are column-major with leading
 // dimension n; offsets are 64-bit.
 #include <climits>
 #include <vector>
@@ -225,7 +226,8 @@ __global__ __launch_bounds__(256) void trsm_upper(const cplx* __restrict__ U, in
   }
 }
 
-// C (M x N) -= A (M x K) B (K x N), K <= 64, on the FP64 matrix cores.
+// C (M x N) -= A (M x K) B (K x N) (or C = -A B with overwrite), on the FP64
+// matrix cores.
 // Block: 4 waves, a 64 x 64 tile of C.  K runs in chunks of 16 through a
 // double-buffered LDS stage, k-major (As[k][i], Bs[k][j]) so that the MFMA
 // operands A[i][k] (lane i + 16k) and B[k][j] (lane j + 16k) are 16-element
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(256) void trsm_upper(const cplx* __restrict__ U, in
 // Result layout: register r of lane L holds row 4r + L/16, column L mod 16.
 constexpr int kKC = 16;
 __global__ __launch_bounds__(256) void zgemm_sub(const cplx* __restrict__ A, int lda, const cplx* __restrict__ B,
-                                                 int ldb, cplx* C, int ldc, int M, int N, int K) {
+                                                 int ldb, cplx* C, int ldc, int M, int N, int K, int overwrite) {
   __shared__ cplx As[2][kKC][kNB + 1];
   __shared__ cplx Bs[2][kKC][kNB + 1];
   const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
@@ -316,7 +318,8 @@ __global__ __launch_bounds__(256) void zgemm_sub(const cplx* __restrict__ A, int
         if (i < M && j < N) {
           const double t1 = T1[ta][tb][r], t2 = T2[ta][tb][r], t3 = T3[ta][tb][r];
           cplx& c = C[(size_t)j * ldc + i];
-          c = {c.re - (t1 - t2), c.im - (t3 - t1 - t2)};
+          const cplx c0 = overwrite ? cplx{0.0, 0.0} : c;
+          c = {c0.re - (t1 - t2), c0.im - (t3 - t1 - t2)};
         }
       }
 }
@@ -343,10 +346,24 @@ int nblocks(int64_t rows, int cap) {
 }
 
 void launch_gemm_sub(hipStream_t st, const cplx* A, int lda, const cplx* B, int ldb, cplx* C, int ldc, int M, int N,
-                     int K) {
+                     int K, int overwrite = 0) {
   if (M <= 0 || N <= 0 || K <= 0) return;
   dim3 grid((M + 63) / 64, (N + 63) / 64);
-  zgemm_sub<<<grid, 256, 0, st>>>(A, lda, B, ldb, C, ldc, M, N, K);
+  zgemm_sub<<<grid, 256, 0, st>>>(A, lda, B, ldb, C, ldc, M, N, K, overwrite);
+}
+
+// X (ld x ld) = identity on its first kb rows and columns, zero elsewhere
+__global__ void set_identity(cplx* X, int ld, int kb) {
+  const size_t tot = (size_t)ld * ld;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot; idx += (size_t)gridDim.x * blockDim.x) {
+    const int r = idx % ld, c = idx / ld;
+    X[idx] = (r == c && r < kb) ? cplx{1.0, 0.0} : cplx{0.0, 0.0};
+  }
+}
+
+__global__ void negate(cplx* X, size_t tot) {
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot; idx += (size_t)gridDim.x * blockDim.x)
+    X[idx] = {-X[idx].re, -X[idx].im};
 }
 
 }  // namespace
@@ -423,22 +440,68 @@ int DenseLU::factor(hipStream_t st) {
   DP_TRY(perm.reserve((size_t)n * sizeof(int)));
   DP_HIP(hipMemcpyAsync(perm.p, pm.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, st));
   DP_HIP(hipStreamSynchronize(st));
+  return block_inverses(st);
+}
+
+// -L_bb^{-1} and -U_bb^{-1} for every kSB x kSB diagonal block (the last one
+// may be smaller), by blocked substitution on identity columns with the
+// factorisation's own kernels; stored column-major with leading dimension kSB.
+int DenseLU::block_inverses(hipStream_t st) {
+  const cplx* A = a.as<cplx>();
+  nsb = (n + kSB - 1) / kSB;
+  const size_t per = (size_t)kSB * kSB;
+  DP_TRY(dinvL.reserve(nsb * per * sizeof(cplx)));
+  DP_TRY(dinvU.reserve(nsb * per * sizeof(cplx)));
+  for (int bk = 0; bk < nsb; ++bk) {
+    const int b0 = bk * kSB, kb = std::min(kSB, n - b0);
+    cplx* XL = dinvL.as<cplx>() + bk * per;
+    cplx* XU = dinvU.as<cplx>() + bk * per;
+    set_identity<<<nblocks((int64_t)per, 1024), 256, 0, st>>>(XL, kSB, kb);
+    set_identity<<<nblocks((int64_t)per, 1024), 256, 0, st>>>(XU, kSB, kb);
+    for (int s0 = 0; s0 < kb; s0 += kNB) {
+      const int sk = std::min(kNB, kb - s0);
+      trsm_lower_unit<<<std::min(1024, (kb + 3) / 4), 256, 0, st>>>(A + (size_t)(b0 + s0) * n + b0 + s0, n, XL + s0,
+                                                                    kSB, sk, kb);
+      launch_gemm_sub(st, A + (size_t)(b0 + s0) * n + b0 + s0 + sk, n, XL + s0, kSB, XL + s0 + sk, kSB,
+                      kb - s0 - sk, kb, sk);
+    }
+    for (int s0 = ((kb - 1) / kNB) * kNB; s0 >= 0; s0 -= kNB) {
+      const int sk = std::min(kNB, kb - s0);
+      trsm_upper<<<std::min(1024, (kb + 3) / 4), 256, 0, st>>>(A + (size_t)(b0 + s0) * n + b0 + s0, n, XU + s0, kSB,
+                                                               sk, kb);
+      launch_gemm_sub(st, A + (size_t)(b0 + s0) * n + b0, n, XU + s0, kSB, XU, kSB, s0, kb, sk);
+    }
+    negate<<<nblocks((int64_t)per, 1024), 256, 0, st>>>(XL, per);
+    negate<<<nblocks((int64_t)per, 1024), 256, 0, st>>>(XU, per);
+  }
+  DP_HIP(hipGetLastError());
+  DP_HIP(hipStreamSynchronize(st));
   return DP_OK;
 }
 
+// u = A^{-1} z: t = P z; forward over kSB-row blocks, y_b = L_bb^{-1} t_b
+// (a matrix-core product with the stored inverse) and t_below -= L_below,b y_b;
+// backward, u_b = U_bb^{-1} y_b and y_above -= U_above,b u_b.  Each step is two
+// matrix-core launches; t and y are workspaces, so no product reads what
+// another writes.
 int DenseLU::solve(hipStream_t st, const cplx* z, cplx* u, int nrhs) {
   const cplx* A = a.as<cplx>();
-  gather_perm<<<nblocks((int64_t)n * nrhs, 8192), 256, 0, st>>>(z, u, perm.as<int>(), n, nrhs);
-  for (int b0 = 0; b0 < n; b0 += kNB) {
-    const int kb = std::min(kNB, n - b0);
-    trsm_lower_unit<<<std::min(1024, (nrhs + 3) / 4), 256, 0, st>>>(A + (size_t)b0 * n + b0, n, u + b0, n, kb,
-                                                                    nrhs);
-    launch_gemm_sub(st, A + (size_t)b0 * n + b0 + kb, n, u + b0, n, u + b0 + kb, n, n - b0 - kb, nrhs, kb);
+  const size_t bytes = (size_t)n * nrhs * sizeof(cplx);
+  DP_TRY(tws.reserve(bytes));
+  DP_TRY(yws.reserve(bytes));
+  cplx* t = tws.as<cplx>();
+  cplx* y = yws.as<cplx>();
+  const size_t per = (size_t)kSB * kSB;
+  gather_perm<<<nblocks((int64_t)n * nrhs, 8192), 256, 0, st>>>(z, t, perm.as<int>(), n, nrhs);
+  for (int bk = 0; bk < nsb; ++bk) {
+    const int b0 = bk * kSB, kb = std::min(kSB, n - b0);
+    launch_gemm_sub(st, dinvL.as<cplx>() + bk * per, kSB, t + b0, n, y + b0, n, kb, nrhs, kb, 1);
+    launch_gemm_sub(st, A + (size_t)b0 * n + b0 + kb, n, y + b0, n, t + b0 + kb, n, n - b0 - kb, nrhs, kb);
   }
-  for (int b0 = ((n - 1) / kNB) * kNB; b0 >= 0; b0 -= kNB) {
-    const int kb = std::min(kNB, n - b0);
-    trsm_upper<<<std::min(1024, (nrhs + 3) / 4), 256, 0, st>>>(A + (size_t)b0 * n + b0, n, u + b0, n, kb, nrhs);
-    launch_gemm_sub(st, A + (size_t)b0 * n, n, u + b0, n, u, n, b0, nrhs, kb);
+  for (int bk = nsb - 1; bk >= 0; --bk) {
+    const int b0 = bk * kSB, kb = std::min(kSB, n - b0);
+    launch_gemm_sub(st, dinvU.as<cplx>() + bk * per, kSB, y + b0, n, u + b0, n, kb, nrhs, kb, 1);
+    launch_gemm_sub(st, A + (size_t)b0 * n, n, u + b0, n, y, n, b0, nrhs, kb);
   }
   DP_HIP(hipGetLastError());
   return DP_OK;
@@ -446,6 +509,10 @@ int DenseLU::solve(hipStream_t st, const cplx* z, cplx* u, int nrhs) {
 
 void DenseLU::release() {
   a.release();
+  dinvL.release();
+  dinvU.release();
+  tws.release();
+  yws.release();
   ipiv.release();
   perm.release();
   work.release();

@@ -13,11 +13,17 @@ struct DenseLU {
   DevBuf ipiv;  // row swapped with row c at step c
   DevBuf perm;  // (P z)[i] = z[perm[i]]
   DevBuf work;  // pivot-search partials, 1/pivot, singularity flag
+  static constexpr int kSB = 256;  // block size of the solves
+  int nsb = 0;                     // diagonal blocks
+  DevBuf dinvL, dinvU;  // -(L_bb)^{-1}, -(U_bb)^{-1} per diagonal block (kSB x kSB, column-major)
+  DevBuf tws, yws;      // solve workspaces (n x nrhs)
   // zero n x n matrix with the given (row, col, value) entries (no duplicates)
   int assemble(hipStream_t st, int n, const std::vector<int>& rows, const std::vector<int>& cols,
                const std::vector<cplx>& vals);
-  // P A = L U in place; DP_ESINGULAR on a zero pivot column
+  // P A = L U in place, then the inverses of the diagonal blocks; DP_ESINGULAR
+  // on a zero pivot column
   int factor(hipStream_t st);
+  int block_inverses(hipStream_t st);
   // u = A^{-1} z for nrhs columns (n x nrhs column-major, z and u distinct)
   int solve(hipStream_t st, const cplx* z, cplx* u, int nrhs);
   void release();

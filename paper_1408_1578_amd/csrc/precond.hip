@@ -898,8 +898,11 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
   // per row (many segments coupled all-to-all through E): then the sparse
   // solves are slower than dense ones and the host factorisation takes
   // seconds, so floor(W) is factored densely on the device instead.
+  // With more than 2 N_W pair entries (m (m - 1) > 2 N_W) the coupling is
+  // all-to-all enough that the ordering need not be tried.
   const int64_t fill_cap = o->w_solver == 1 ? INT64_MAX : 32 * (int64_t)NW;
-  rc = o->w_solver == 2 ? kSparseFillLimit : sparse_lu_factor(NW, cp, ri, vx, P->lu, fill_cap);
+  const bool go_dense = o->w_solver == 2 || (o->w_solver == 0 && (int64_t)m * (m - 1) > 2 * (int64_t)NW);
+  rc = go_dense ? kSparseFillLimit : sparse_lu_factor(NW, cp, ri, vx, P->lu, fill_cap);
   if (rc == kSparseFillLimit) {
     if ((double)NW * NW * sizeof(cplx) > 48.0 * (1 << 30)) {
       set_error("floor(W) of dimension %d needs a dense factorisation larger than 48 GiB", NW);
@@ -1209,7 +1212,8 @@ int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q, int prec) {
   // precision's apply) means capturing again
   auto sig = [&]() {
     return std::vector<void*>{P->wy.p, P->wn.p, P->wg.p, P->wz.p, P->wu.p, P->wt.p, P->sv.p, P->sy.p,
-                              P->sn.p, P->sq.p, P->sg.p, P->sz.p, P->su.p, P->win.p, P->wq.p};
+                              P->sn.p, P->sq.p, P->sg.p, P->sz.p, P->su.p, P->win.p, P->wq.p,
+                              P->dlu.tws.p, P->dlu.yws.p};
   };
   if (gn != nrhs || (gx && sig() != gsig)) {
     if (gx) (void)hipGraphExecDestroy(gx);
