@@ -58,8 +58,8 @@ def log(*a):
 def cpu_baseline(b, om, eta, nrhs, budget_s=25.0):
     """The oracle (dense Nystrom assembly + LU) timed on the host, on a sample.
 
-    Sample: (a) oracle S and D' rows for 96 target rows at the full n (pair
-    evaluations scale with n^2 -> x n/96); (b) the oracle's dense hard matrix at
+    Sample: (a) oracle S and D' rows for 256 target rows at the full n (pair
+    evaluations scale with n^2 -> x n/256); (b) the oracle's dense hard matrix at
     n0 = 2048 on the same curve and its LU + 64 triangular solves (cubic parts
     scale with (n/n0)^3).  The extrapolated time of one 64-RHS dense solve at n
     gives solves/s = nrhs / T.
@@ -70,7 +70,7 @@ def cpu_baseline(b, om, eta, nrhs, budget_s=25.0):
 
     n = b.n
     t0 = time.perf_counter()
-    rows = np.arange(0, n, n // 96)[:96]
+    rows = np.arange(0, n, n // 256)[:256]
     ny.layer_rows(b, om, rows)
     t_rows = time.perf_counter() - t0
     t_pairs = t_rows * n / len(rows)
