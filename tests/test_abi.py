@@ -67,3 +67,26 @@ def test_problem_create_validates_without_gpu():
                              x.ctypes.data_as(ctypes.c_void_p), x.ctypes.data_as(ctypes.c_void_p),
                              1.0, 1.0, 0, ctypes.byref(h))
     assert rc == dp.DP_EINVAL
+
+
+def test_new_entry_points_validate_without_gpu():
+    # every check below happens before any device call
+    L = dp.lib()
+    vp = ctypes.c_void_p
+    assert L.dp_matvec_mixed(None, 1, None, None) == dp.DP_EINVAL
+    assert L.dp_precond_apply_mixed(None, 1, None, None) == dp.DP_EINVAL
+    assert L.dp_autotune(None, 4, 0, None) == dp.DP_EINVAL
+    assert L.dp_server_create(0, None, None) == dp.DP_EINVAL
+    assert L.dp_server_submit(None, None, None) == dp.DP_EINVAL
+    assert L.dp_server_wait(None, 1, None, None, None) == dp.DP_EINVAL
+    assert L.dp_server_get_stats(None, None) == dp.DP_EINVAL
+    L.dp_server_destroy(None)  # no-op
+    assert b"NULL" in L.dp_last_error() or len(L.dp_last_error()) > 0
+
+
+def test_server_options_validated():
+    L = dp.lib()
+    out = ctypes.c_void_p()
+    bad = dp.ServerOpts(0, -5)           # negative memory budget
+    assert L.dp_server_create(0, ctypes.byref(bad), ctypes.byref(out)) == dp.DP_EINVAL
+    assert not out.value
