@@ -72,10 +72,15 @@ const char* dp_last_error(void);
  *   nrm   n x 2 row-major outward unit normals;
  *   w     n quadrature weights w_j = (2*pi/n)|x'(t_j)| (trapezoid weights);
  *   kappa n signed curvatures (positive where convex); needed by the
- *         diagonal of D and D'.
+ *         diagonal of D and D'.  May be NULL when n is a power of two: the
+ *         library then computes kappa = (x' y'' - y' x'') / |x'|^3 from the
+ *         FFT t-derivatives of the node positions (the same trigonometric
+ *         interpolation as D_s), exact for band-limited curves up to
+ *         rounding that grows like n^2 * 1e-16 relative to max|x''|.
  * omega > 0 frequency, eta > 0 coupling (typically omega), kind DP_SOFT or
- * DP_HARD.  Errors (DP_EINVAL): n odd or n < 16, DP_HARD with n not a power
- * of two (the spectral derivative uses a radix-2 FFT), a non-finite entry,
+ * DP_HARD.  Errors (DP_EINVAL): n odd or n < 16, DP_HARD or kappa == NULL
+ * with n not a power of two (the spectral derivative uses a radix-2 FFT),
+ * a non-finite entry,
  * |nrm_j| differing from 1 by more than 1e-10, w_j <= 0, omega <= 0,
  * eta <= 0.  The problem keeps device copies of the geometry and the Kress
  * correction table C_k (k = 0..n-1). */
@@ -83,6 +88,10 @@ int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nr
                       const double* w, const double* kappa, double omega, double eta,
                       int kind, dp_problem** out);
 void dp_problem_destroy(dp_problem* p);
+
+/* The curvatures the problem uses (the caller's, or those computed when
+ * kappa was NULL).  kappa: host, n doubles, written.  Errors: DP_EINVAL. */
+int dp_problem_kappa(const dp_problem* p, double* kappa);
 
 /* Incident plane waves u_I = exp(i omega d_k . x), d_k = (cos a_k, sin a_k)
  * (Sec. 3 uses a_0 = 0).  angles: host, nrhs doubles.  f: device n x nrhs

@@ -28,7 +28,7 @@ DP_OP_S, DP_OP_D, DP_OP_DP, DP_OP_DS = 2, 3, 4, 5
 # every symbol declared in include/dirprec.h
 EXPORTED = [
     "dp_ctx_create", "dp_ctx_destroy", "dp_last_error", "dp_problem_create",
-    "dp_problem_destroy", "dp_rhs_plane_wave", "dp_matvec", "dp_matvec_mixed", "dp_layer_apply",
+    "dp_problem_destroy", "dp_problem_kappa", "dp_rhs_plane_wave", "dp_matvec", "dp_matvec_mixed", "dp_layer_apply",
     "dp_precond_build", "dp_precond_apply", "dp_precond_apply_mixed", "dp_precond_get_info", "dp_precond_export",
     "dp_solve", "dp_hankel_dev", "dp_hankel_host",
     "dp_autotune", "dp_server_create", "dp_server_submit", "dp_server_wait", "dp_server_get_stats", "dp_server_destroy",
@@ -126,6 +126,7 @@ def lib():
         "dp_last_error": (ctypes.c_char_p, []),
         "dp_problem_create": (ci, [vp, i64, vp, vp, vp, vp, dbl, dbl, ci, pp]),
         "dp_problem_destroy": (None, [vp]),
+        "dp_problem_kappa": (ci, [vp, vp]),
         "dp_rhs_plane_wave": (ci, [vp, i64, vp, vp]),
         "dp_matvec": (ci, [vp, i64, vp, vp]),
         "dp_matvec_mixed": (ci, [vp, i64, vp, vp]),
@@ -221,7 +222,7 @@ class Problem:
         xa, xp = _host(np.asarray(x).reshape(n, 2))
         na, np_ = _host(np.asarray(nu).reshape(n, 2))
         wa, wp = _host(w)
-        ka, kp = _host(kappa)
+        ka, kp = (None, None) if kappa is None else _host(kappa)  # None: computed by the library
         h = ctypes.c_void_p()
         _check("dp_problem_create", lib().dp_problem_create(ctx.h, n, xp, np_, wp, kp, float(omega),
                                                             float(eta), int(kind), ctypes.byref(h)))
@@ -250,6 +251,13 @@ def dp_problem_create(ctx, x, nu, w, kappa, omega, eta, kind):
 
 def dp_problem_destroy(p):
     p.close()
+
+
+def dp_problem_kappa(p):
+    """The curvatures the problem uses, (n,) float64."""
+    k = np.empty(p.n, np.float64)
+    _check("dp_problem_kappa", lib().dp_problem_kappa(p.h, k.ctypes.data_as(ctypes.c_void_p)))
+    return k
 
 
 def dp_rhs_plane_wave(p, angles, f):
@@ -372,12 +380,12 @@ class Server:
 
     def submit(self, b, omega, eta, kind, angles=None, f=None, tol=1e-8, restart=80, max_iters=2000,
                use_precond=True, precision=DP_PREC_FP64, inner_tol=1e-5):
-        """b: boundary with x (n, 2), nu (n, 2), w (n,), kappa (n,).  angles: plane-wave angles, or
+        """b: boundary with x (n, 2), nu (n, 2), w (n,), kappa (n,) or None.  angles: plane-wave angles, or
         f: (n, nrhs) complex data.  Returns the request id."""
         xy, xyp = _host(b.x)
         nu, nup = _host(b.nu)
         w, wp = _host(b.w)
-        ka, kap = _host(b.kappa)
+        ka, kap = (None, None) if b.kappa is None else _host(b.kappa)
         n = w.size
         if angles is not None:
             an, anp = _host(np.atleast_1d(angles))

@@ -3,6 +3,7 @@
 // translation units.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -95,7 +96,9 @@ void dp_ctx_destroy(dp_ctx* c) {
 
 int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nrm, const double* w,
                       const double* kappa, double omega, double eta, int kind, dp_problem** out) {
-  DP_CHECK(ctx && out && xy && nrm && w && kappa, "dp_problem_create: NULL argument");
+  DP_CHECK(ctx && out && xy && nrm && w, "dp_problem_create: NULL argument");
+  DP_CHECK(kappa || is_pow2(n), "dp_problem_create: kappa == NULL needs a power-of-two n (got %lld)",
+           (long long)n);
   DP_CHECK(n >= 16 && n % 2 == 0 && n <= (1LL << 26), "dp_problem_create: n = %lld must be even, >= 16",
            (long long)n);
   DP_CHECK(kind == DP_SOFT || kind == DP_HARD, "dp_problem_create: kind %d", kind);
@@ -106,7 +109,7 @@ int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nr
   const double w0 = w[0];
   bool equi = true;
   for (int64_t i = 0; i < n; ++i) {
-    const double v[6] = {xy[2 * i], xy[2 * i + 1], nrm[2 * i], nrm[2 * i + 1], w[i], kappa[i]};
+    const double v[6] = {xy[2 * i], xy[2 * i + 1], nrm[2 * i], nrm[2 * i + 1], w[i], kappa ? kappa[i] : 0.0};
     for (double t : v) DP_CHECK(std::isfinite(t), "dp_problem_create: non-finite input at node %lld", (long long)i);
     DP_CHECK(w[i] > 0, "dp_problem_create: weight %lld is not positive", (long long)i);
     const double nn = std::hypot(nrm[2 * i], nrm[2 * i + 1]);
@@ -135,7 +138,7 @@ int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nr
     p->hnx[i] = nrm[2 * i];
     p->hny[i] = nrm[2 * i + 1];
     p->hsp[i] = w[i] * (double)n / (2.0 * kPi);
-    p->hkap[i] = kappa[i];
+    p->hkap[i] = kappa ? kappa[i] : 0.0;
     L += w[i];
     rec[i] = {p->hx[i],        p->hy[i],        p->hnx[i],
               p->hny[i],       p->hsp[i],       p->hkap[i],
@@ -150,6 +153,7 @@ int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nr
     rc = DP_EDEVICE;
   }
   if (rc == DP_OK) rc = build_tables(p);
+  if (rc == DP_OK && !kappa) rc = curvature_spectral(p, p->hkap.data());
   if (rc == DP_OK) rc = near_build(p);
   if (rc != DP_OK) {
     dp_problem_destroy(p);
@@ -179,6 +183,12 @@ void dp_problem_destroy(dp_problem* p) {
   p->tmp2.release();
   p->tmp3.release();
   delete p;
+}
+
+int dp_problem_kappa(const dp_problem* p, double* kappa) {
+  DP_CHECK(p && kappa, "dp_problem_kappa: NULL argument");
+  std::copy(p->hkap.begin(), p->hkap.end(), kappa);
+  return DP_OK;
 }
 
 int dp_rhs_plane_wave(dp_problem* p, int64_t nrhs, const double* angles, double* f) {

@@ -140,6 +140,9 @@ int near_apply_group(dp_problem* p, int op, int nrp, const void* dens, bool dens
 int matvec(dp_problem* p, int nrhs, const cplx* q, cplx* y, int prec = 0);
 // fft.hip
 int spectral_derivative(dp_problem* p, int nrhs, const cplx* in, cplx* out);
+// Curvature from the spectral t-derivatives of the node positions (power-of-two
+// n, twiddles built): written into the source records and into hkap (host, n).
+int curvature_spectral(dp_problem* p, double* hkap);
 // rhs
 int rhs_plane_wave(dp_problem* p, int nrhs, const double* angles_dev, cplx* f);
 // hankel test hook

@@ -155,20 +155,73 @@ static void fft_passes(dp_problem* p, cplx* d, int nb, int dir) {
   }
 }
 
+static int grid_for(size_t tot) {
+  const size_t g = (tot + 255) / 256;
+  return (int)(g > 8192 ? 8192 : g);
+}
+
+// In place: d <- d/dt of each of nb columns (trigonometric interpolant).
+static void t_derivative(dp_problem* p, cplx* d, int nb) {
+  const int n = (int)p->n;
+  fft_passes(p, d, nb, -1);
+  const int logn = ilog2(n);
+  const int log1 = logn <= 12 ? logn : (logn + 1) / 2;
+  deriv_scale<<<grid_for((size_t)n * nb), 256, 0, p->ctx->stream>>>(d, n, 1 << log1, 1 << (logn - log1), nb);
+  fft_passes(p, d, nb, +1);
+}
+
 int spectral_derivative(dp_problem* p, int nrhs, const cplx* in, cplx* out) {
   const int n = (int)p->n;
   const size_t tot = (size_t)n * nrhs;
   hipStream_t st = p->ctx->stream;
-  size_t g = (tot + 255) / 256;
-  const int grid = (int)(g > 8192 ? 8192 : g);
+  const int grid = grid_for(tot);
   copy_div_speed<<<grid, 256, 0, st>>>(in, out, p->src.as<SrcRec>(), n, tot, 0);
-  fft_passes(p, out, nrhs, -1);
-  const int logn = ilog2(n);
-  const int log1 = logn <= 12 ? logn : (logn + 1) / 2;
-  deriv_scale<<<grid, 256, 0, st>>>(out, n, 1 << log1, 1 << (logn - log1), nrhs);
-  fft_passes(p, out, nrhs, +1);
+  t_derivative(p, out, nrhs);
   copy_div_speed<<<grid, 256, 0, st>>>(out, out, p->src.as<SrcRec>(), n, tot, 1);
   DP_HIP(hipGetLastError());
+  return DP_OK;
+}
+
+// z[i] = x_i + i y_i, duplicated into the second column.
+__global__ void pack_position(const SrcRec* __restrict__ src, cplx* z, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const cplx v = {src[i].x, src[i].y};
+    z[i] = v;
+    z[n + i] = v;
+  }
+}
+
+// Column 0 holds z', column 1 holds z''.  Signed curvature of a
+// counter-clockwise curve: (x' y'' - y' x'') / |z'|^3.
+__global__ void curvature_from_derivs(const cplx* __restrict__ z, SrcRec* src, double* kap, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const cplx a = z[i], b = z[n + i];
+    const double s2 = a.re * a.re + a.im * a.im;
+    const double k = (a.re * b.im - a.im * b.re) / (s2 * sqrt(s2));
+    src[i].kappa = k;
+    kap[i] = k;
+  }
+}
+
+int curvature_spectral(dp_problem* p, double* hkap) {
+  const int n = (int)p->n;
+  hipStream_t st = p->ctx->stream;
+  DevBuf z;
+  struct Release {
+    DevBuf& b;
+    ~Release() { b.release(); }
+  } release{z};
+  DP_TRY(z.reserve((size_t)2 * n * sizeof(cplx) + (size_t)n * sizeof(double)));
+  cplx* zc = z.as<cplx>();
+  double* kap = reinterpret_cast<double*>(zc + 2 * (size_t)n);
+  const int grid = grid_for((size_t)n);
+  pack_position<<<grid, 256, 0, st>>>(p->src.as<SrcRec>(), zc, n);
+  t_derivative(p, zc, 2);   // both columns: z'
+  t_derivative(p, zc + n, 1);  // second column: z''
+  curvature_from_derivs<<<grid, 256, 0, st>>>(zc, p->src.as<SrcRec>(), kap, n);
+  DP_HIP(hipGetLastError());
+  DP_HIP(hipMemcpyAsync(hkap, kap, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
+  DP_HIP(hipStreamSynchronize(st));
   return DP_OK;
 }
 

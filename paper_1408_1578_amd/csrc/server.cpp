@@ -110,7 +110,7 @@ void run_request(dp_ctx* ctx, Request& r) {
     r.rc = rc;
     r.err = dp_last_error();
   };
-  int rc = dp_problem_create(ctx, r.n, r.xy.data(), r.nrm.data(), r.w.data(), r.kappa.data(), r.omega, r.eta,
+  int rc = dp_problem_create(ctx, r.n, r.xy.data(), r.nrm.data(), r.w.data(), r.kappa.empty() ? nullptr : r.kappa.data(), r.omega, r.eta,
                              r.kind, &p);
   if (rc != DP_OK) {
     fail(rc);
@@ -241,7 +241,7 @@ int dp_server_submit(dp_server* s, const dp_request* rq, int64_t* id) {
     return DP_EINVAL;
   }
   const int64_t n = rq->n;
-  if (!rq->xy || !rq->nrm || !rq->w || !rq->kappa || n < 16 || n % 2 || n > (1LL << 26) || rq->nrhs < 1 ||
+  if (!rq->xy || !rq->nrm || !rq->w || (!rq->kappa && (n & (n - 1))) || n < 16 || n % 2 || n > (1LL << 26) || rq->nrhs < 1 ||
       rq->nrhs > (1LL << 20) || (rq->kind != DP_SOFT && rq->kind != DP_HARD) ||
       (rq->kind == DP_HARD && (n & (n - 1))) || (!rq->angles && !rq->f) || !(rq->omega > 0) || !(rq->eta > 0)) {
     dp::set_error("dp_server_submit: invalid request (n = %lld, nrhs = %lld, kind = %d)", (long long)n,
@@ -257,7 +257,7 @@ int dp_server_submit(dp_server* s, const dp_request* rq, int64_t* id) {
   r->xy.assign(rq->xy, rq->xy + 2 * n);
   r->nrm.assign(rq->nrm, rq->nrm + 2 * n);
   r->w.assign(rq->w, rq->w + n);
-  r->kappa.assign(rq->kappa, rq->kappa + n);
+  if (rq->kappa) r->kappa.assign(rq->kappa, rq->kappa + n);  // empty: computed from the nodes
   if (rq->angles) r->angles.assign(rq->angles, rq->angles + rq->nrhs);
   else r->f.assign(rq->f, rq->f + 2 * n * rq->nrhs);
   r->opts = rq->solve;
