@@ -31,15 +31,23 @@ sys.path.insert(0, ROOT)
 METRIC = "CFIE solves/s at n=32768 to 1e-8 residual (mixed vs FP64); p50/p99 latency"
 # FP64 peak, TFLOP/s: dense MFMA and vector FMA are both 256 CU x 4 SIMD x 32 flop/clk x 2.4 GHz
 PEAK_FP64_VALU = 78.6
-# dense FP32 matrix-core peak, TFLOP/s (the mixed-precision correction sweeps)
-PEAK_FP32_MFMA = 157.3
-# HBM bytes per launch of the two 64-column hard sweeps at n = 32768 with a
+# FP32 vector peak (256 CU x 4 SIMD x 64 flop/clk x 2.4 GHz, packed FP32) and
+# dense FP16 matrix-core peak, TFLOP/s: the single-precision sweep evaluates
+# its kernel values on the vector ALUs and multiplies split-FP16 operands on
+# the matrix cores; the two do not issue concurrently on one SIMD, so its
+# time is bounded below by the sum of the two.
+PEAK_FP32_VALU = 157.3
+PEAK_FP16_MFMA = 2500.0
+# Executed matrix-core flops per pair, density and column in that sweep: a
+# complex product is 4 real products, each split into 3 FP16 products.
+FLOPS_MFMA16_PER_COL = 24
+# HBM bytes per launch of the 64-column FP64 hard sweep at n = 32768 with a
 # 2048-block grid (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the counts of
-# a 512 MiB device copy in the same run).  They describe the current kernels in
+# a 512 MiB device copy in the same run).  It describes the current kernel in
 # that configuration; another configuration or a changed kernel must be
-# measured again before these are reported.
-TRAFFIC_FP32_SWEEP = 0.6905e9
+# measured again before it is reported.
 TRAFFIC_FP64_SWEEP = 1.3985e9
+TRAFFIC_FP32_SWEEP = None
 
 # Algorithmic FP64 flops of one ordered pair in the sound-hard sweep (far-field
 # evaluation path; an FMA counts 2): geometry 5, 1/r 8, r and z 2, H0/H1 142,
@@ -271,6 +279,11 @@ def main():
     pairs = b.n * (b.n - 1)
     flops = pairs * (FLOPS_PAIR_HARD + FLOPS_PAIR_PER_RHS_HARD * nrp)
 
+    # lower bound on one single-precision sweep: pair arithmetic on the vector
+    # ALUs plus the executed split-FP16 products on the matrix cores
+    t_bound32 = pairs * (FLOPS_PAIR_HARD / (PEAK_FP32_VALU * 1e12)
+                         + 2 * nrp * FLOPS_MFMA16_PER_COL / (PEAK_FP16_MFMA * 1e12))
+
     def sweep_rate(infos, key_l, key_t):
         launches = sum(i[key_l] for i in infos)
         t = sum(i[key_t] for i in infos)
@@ -300,7 +313,7 @@ def main():
             out["refinements"] = int(max(i["refinements"] for i in infos))
             out["matvecs_fp32"] = int(max(i["matvecs_fp32"] for i in infos))
             out["sweep_fp32"] = {"launch_ms": a32 * 1e3, "launches": l32, "tflops": ach32,
-                                 "frac_fp32_mfma_peak": ach32 / PEAK_FP32_MFMA}
+                                 "frac_of_bound": t_bound32 / a32 if a32 > 0 else 0.0}
         return out
 
     # launch configuration of the sweep for this shape, chosen before the timed region
@@ -321,12 +334,14 @@ def main():
 
     if head == "mixed":
         sw = main_run["sweep_fp32"]
-        roof = {"kernel": "sweep_mfma<hard, 64 columns, FP32> (FP32 kernel values and v_mfma_f32_16x16x4 "
-                          "products, FP64 phase reduction; 8 waves, shared kernel values, LDS density tiles)",
-                "bound": "mfma", "achieved": sw["tflops"], "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-                "frac": sw["tflops"] / PEAK_FP32_MFMA,
+        roof = {"kernel": "sweep_mfma16<hard, 64 columns> (FP32 kernel values, FP64 phase reduction; "
+                          "split-FP16 operands on v_mfma_f32_16x16x32_f16 with FP32 accumulation; 8 waves x "
+                          "16 targets, LDS density tiles)",
+                "bound": "alu+mfma", "achieved": sw["tflops"], "peak": flops / t_bound32 / 1e12,
+                "unit": "TFLOP/s", "frac": sw["frac_of_bound"],
                 "traffic": TRAFFIC_FP32_SWEEP if measured_cfg("mixed") else None, "launch_ms": sw["launch_ms"],
-                "launches": sw["launches"], "flops_per_launch": flops}
+                "launches": sw["launches"], "flops_per_launch": flops, "t_bound_ms": t_bound32 * 1e3,
+                "valu_peak_tflops": PEAK_FP32_VALU, "mfma_peak_tflops": PEAK_FP16_MFMA}
     else:
         sw = main_run["sweep_fp64"]
         roof = {"kernel": "sweep_mfma<hard, 64 columns, FP64> (v_mfma_f64_16x16x4 products; 8 waves, "

@@ -138,12 +138,13 @@ int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nr
     p->hnx[i] = nrm[2 * i];
     p->hny[i] = nrm[2 * i + 1];
     p->hsp[i] = w[i] * (double)n / (2.0 * kPi);
+    p->spmax = std::max(p->spmax, p->hsp[i]);
     p->hkap[i] = kappa ? kappa[i] : 0.0;
     L += w[i];
     rec[i] = {p->hx[i],        p->hy[i],        p->hnx[i],
               p->hny[i],       p->hsp[i],       p->hkap[i],
-              (float)p->hnx[i], (float)p->hny[i], (float)(2.0 * kPi / (double)n * p->hsp[i]),
-              (float)p->hsp[i]};
+              (float)p->hnx[i], (float)p->hny[i], (float)(0.5 * kPi / (double)n * p->hsp[i]),
+              (float)(p->hsp[i] / (4.0 * kPi))};
   }
   p->L = L;
   int rc = p->src.reserve(n * sizeof(SrcRec));
@@ -175,6 +176,9 @@ void dp_problem_destroy(dp_problem* p) {
   p->twiddle.release();
   p->dens.release();
   p->partial.release();
+  p->dens16.release();
+  p->C32.release();
+  p->sc16.release();
   p->near_ptr.release();
   p->near_col.release();
   p->near_out.release();

@@ -42,8 +42,8 @@ struct DevBuf {
 };
 
 // One boundary node (64 bytes): position, outward normal, speed |x'(t)| and
-// curvature in FP64, and FP32 copies of the normal, the trapezoid weight
-// (2 pi/n) |x'(t)| and the speed for the single-precision sweep.
+// curvature in FP64, and for the single-precision sweep the FP32 normal,
+// a quarter of the trapezoid weight, (2 pi/n) |x'(t)| / 4, and |x'(t)| / (4 pi).
 struct SrcRec {
   double x, y, nx, ny, sp, kappa;
   float nxf, nyf, wf, spf;
@@ -55,10 +55,14 @@ enum SweepOp { OP_SOFT = 0, OP_HARD = 1, OP_S = 2, OP_D = 3, OP_DP = 4 };
 struct SweepParams {
   const SrcRec* src;       // n records
   const double* C;         // n: Kress correction C_k (index (i - j) mod n)
+  const float* C32;        // its FP32 copy
   const cplx* dens;        // [j][nd][nrp] source densities (transposed layout)
   cplx* partial;           // [chunk][nd][nrp][n] partial sums
-  const cplxf* dens32;     // FP32 copies for the mixed-precision matrix-core sweep
+  const cplxf* dens32;     // FP32 copies (near field and the few-column FP32 sweep)
   cplxf* partial32;
+  const uint4* dens16;     // split-FP16 density tiles of the many-column FP32 sweep
+  const float* unscale16;  // [nd][nrp]: 1 / (kernel scale x density scale)
+  float ksc[2];            // power-of-two scales of the FP32 kernel values, per density
   int n, nrp, nd, chunk_len, nchunks;
   double omega, eta, dt;   // dt = 2 pi / n
   double r2near;           // pairs with r^2 < r2near are left to the near-field pass
@@ -100,9 +104,14 @@ struct dp_problem {
   std::vector<double> hx, hy, hnx, hny, hsp, hkap;  // host copies
   dp::DevBuf src;       // SrcRec[n]
   dp::DevBuf C;         // double[n]
+  dp::DevBuf C32;       // float[n], FP32 copy of C
   dp::DevBuf twiddle;   // cplx[n]   (e^{-2 pi i l/n})
   dp::DevBuf dens;      // sweep operands
   dp::DevBuf partial;   // sweep partial sums
+  dp::DevBuf dens16;    // split-FP16 density tiles
+  dp::DevBuf sc16;      // their per-column scales
+  double cmax = 0;      // max |C_k| over k = 1..n-1
+  double spmax = 0;     // max speed |x'(t_j)|
   // near-field pairs (i != j, r^2 < r2near = (DP_HANKEL_ZA/omega)^2), CSR by
   // target row, columns ascending; their kernel values use the small-argument
   // Hankel branch and are applied by a separate pass

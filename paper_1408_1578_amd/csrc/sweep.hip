@@ -25,9 +25,13 @@
 //            them through LDS, and each wave multiplies the whole tile into
 //            its own group of nrp/WAVES columns.
 //   mfma   : nrp >= 16 columns.  The column contraction runs on the FP64
-//            matrix cores (see sweep_mfma).
+//            matrix cores (see sweep_mfma); single precision: split-FP16
+//            operands on the FP16 matrix cores (see sweep_mfma16).
 // Sources are split into chunks (grid.y) so that large problems fill the
 // chip; per-chunk partial sums are reduced in a fixed order (deterministic).
+#include <algorithm>
+#include <cmath>
+
 #include "sweep_pair.hpp"
 
 namespace dp {
@@ -40,6 +44,8 @@ __global__ __launch_bounds__(256) void sweep_private(SweepParams p) {
   const int ii = i < n ? i : n - 1;
   const SrcRec tr = p.src[ii];
   const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
+  const float tnx = (float)tr.nx, tny = (float)tr.ny;
+  const Far32 f = far32_consts(p.omega, p.eta, p.r2near, 1.0f, 1.0f);
   const int j0 = blockIdx.y * p.chunk_len;
   const int j1 = min(n, j0 + p.chunk_len);
   cplx acc[ND][NR];
@@ -133,12 +139,9 @@ __global__ __launch_bounds__(64 * WAVES) void sweep_shared(SweepParams p) {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
-// Precision traits of the matrix-core sweep.  FP64: v_mfma_f64_16x16x4,
-// result D[i][c] in register r of lane c + 16 (i mod 4), i = 4r + lane/16.
-// FP32: v_mfma_f32_16x16x4 (FP32 products and accumulation within a source
-// chunk), result D[i][c] in register r of lane c + 16 (i / 4),
-// i = 4 (lane/16) + r.  Either way A[i][k] sits in lane i + 16k and
-// B[k][c] in lane c + 16k.
+// Precision traits of the FP64 matrix-core sweep: v_mfma_f64_16x16x4,
+// A[i][k] in lane i + 16k, B[k][c] in lane c + 16k, result D[i][c] in
+// register r of lane c + 16 (i mod 4), i = 4r + lane/16.
 struct Mfma64 {
   using C = cplx;
   using V4 = dbl4;
@@ -152,22 +155,6 @@ struct Mfma64 {
   static __device__ __forceinline__ void far(const Tgt& t, const SrcRec& s, double Ck, bool self,
                                              const SweepParams& p, C* K) {
     pair_kernel_far<OP>(t, s, Ck, self, p.omega, p.eta, p.dt, p.r2near, K);
-  }
-};
-
-struct Mfma32 {
-  using C = cplxf;
-  using V4 = flt4;
-  static __device__ __forceinline__ V4 mma(float a, float b, V4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int r, int lk) { return 4 * lk + r; }
-  static __device__ __forceinline__ const C* dens(const SweepParams& p) { return p.dens32; }
-  static __device__ __forceinline__ C* partial(const SweepParams& p) { return p.partial32; }
-  template <int OP>
-  static __device__ __forceinline__ void far(const Tgt& t, const SrcRec& s, double Ck, bool self,
-                                             const SweepParams& p, C* K) {
-    pair_kernel_far32<OP>(t, s, Ck, self, p.omega, p.eta, p.r2near, K);
   }
 };
 
@@ -336,6 +323,8 @@ __global__ __launch_bounds__(256) void sweep_private32(SweepParams p) {
   const int ii = i < n ? i : n - 1;
   const SrcRec tr = p.src[ii];
   const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
+  const float tnx = (float)tr.nx, tny = (float)tr.ny;
+  const Far32 f = far32_consts(p.omega, p.eta, p.r2near, 1.0f, 1.0f);
   const int j0 = blockIdx.y * p.chunk_len;
   const int j1 = min(n, j0 + p.chunk_len);
   cplx acc[ND][NR];
@@ -347,9 +336,8 @@ __global__ __launch_bounds__(256) void sweep_private32(SweepParams p) {
   k += (k < 0) ? n : 0;
   for (int j = j0; j < j1; ++j) {
     const SrcRec s = p.src[j];
-    const double Ck = p.C[k];
     cplxf K[ND];
-    pair_kernel_far32<OP>(t, s, Ck, ii == j, p.omega, p.eta, p.r2near, K);
+    pair_kernel_far32<OP>(t, tnx, tny, s, (float)p.C[k], ii == j, f, K);
     const cplx* dj = p.dens + (size_t)j * ND * NR;
 #pragma unroll
     for (int d = 0; d < ND; ++d)
@@ -378,6 +366,257 @@ __global__ void pack_dens32(const cplx* __restrict__ a, const cplx* __restrict__
     const cplx* src = d == 0 ? a : b;
     const cplx v = (c < nrhs) ? src[(size_t)(col0 + c) * n + j] : cplx{0.0, 0.0};
     dens[idx] = {(float)v.re, (float)v.im};
+  }
+}
+
+// ------------------------------------------------ split-FP16 matrix-core sweep
+// The single-precision contraction on the FP16 matrix cores
+// (v_mfma_f32_16x16x32_f16: 16 targets x 32 sources x 16 columns, FP32
+// accumulation).  Both operands are scaled by powers of two and split as
+// x = hi + lo with hi = fp16(x), lo = fp16(x - hi) (round toward zero); each
+// real product takes hi*hi + hi*lo + lo*hi, which keeps about 21 bits of the
+// FP32 operands, below the error of the FP32 kernel values themselves.
+//   kernel values: scale 2^eK[d], fixed per problem and operator from a bound
+//                  on the far-field values (|H0|, |H1| <= 0.25 for omega r >= 25);
+//   densities    : scale 2^eB[d][c] per column, from the column's largest part.
+// A complex product takes four real ones: Re += Kr Br + (-Ki) Bi,
+// Im += Kr Bi + Ki Br.
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
+// hi = fp16(a, b) and lo = fp16 of the remainders, both round toward zero
+// (never overflows to infinity), packed two halves per word.
+__device__ __forceinline__ void split_h2(float a, float b, uint32_t& hi, uint32_t& lo) {
+  const auto h = __builtin_amdgcn_cvt_pkrtz(a, b);
+  const auto l = __builtin_amdgcn_cvt_pkrtz(a - (float)h[0], b - (float)h[1]);
+  hi = __builtin_bit_cast(uint32_t, h);
+  lo = __builtin_bit_cast(uint32_t, l);
+}
+
+__device__ __forceinline__ flt4 mma16(const uint32_t (&a)[4], const uint4& b, flt4 c) {
+  const uint4 av = {a[0], a[1], a[2], a[3]};
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8, av), __builtin_bit_cast(half8, b), c,
+                                                0, 0, 0);
+}
+
+// Density tiles: for each block of 32 sources b, density d, part
+// (re hi, re lo, im hi, im lo) and column c, the 32 halves of the block's
+// sources, i.e. uint4 index (((b * nd + d) * 4 + part) * nrp + c) * 4 + g for
+// sources 32 b + 8 g .. + 7.  Sources past n and columns past nrhs are zero.
+// Block: 8 waves, each 16 targets x all nrp columns; per 32-source step
+// every lane evaluates 8 pairs (target lane % 16, sources 8 (lane / 16) + e),
+// which is exactly its A fragment.  The step's density tile, its 32 source
+// records and the C_k window of the block (FP32 copy of the table) reach LDS
+// by direct global-to-LDS loads issued one step ahead into the other of two
+// buffers; the steps alternate between two separate sets of LDS arrays so
+// that reads of one set never wait for the loads into the other.  In LDS the
+// tile row (d, part, c) holds its four 16-byte chunks g at positions
+// g ^ ((row / 4) % 4), which keeps the 16 lanes reading one chunk of 16
+// consecutive rows on distinct banks.
+template <int OP, int NCB>
+__global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
+  constexpr int ND = Nd<OP>::v;
+  constexpr int NC = 16 * NCB;
+  constexpr int TQ = ND * 4 * NC * 4;      // uint4 per tile
+  constexpr int NQ = TQ / 64;              // wave loads per tile
+  __shared__ uint4 Bt0[TQ], Bt1[TQ];
+  __shared__ uint4 Ss0[128], Ss1[128];     // 32 source records (64 bytes each)
+  __shared__ float Cs0[192], Cs1[192];     // C_k for k = kb .. kb + 159 (mod n)
+  const int n = p.n;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int i0 = blockIdx.x * 128;
+  const int ti = wv * 16 + li;             // target within the block
+  const int i = i0 + ti;
+  const int ii = i < n ? i : n - 1;
+  const SrcRec tr = p.src[ii];
+  const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
+  const float tnx = (float)tr.nx, tny = (float)tr.ny;
+  const Far32 f = far32_consts(p.omega, p.eta, p.r2near, p.ksc[0], p.ksc[1]);
+  const int j0 = blockIdx.y * p.chunk_len;  // multiple of 32
+  const int j1 = min(n, j0 + p.chunk_len);
+  const int nsteps = (j1 - j0 + 31) / 32;
+  const uint4* srcq = reinterpret_cast<const uint4*>(p.src);
+  const int gsw = lk ^ (li >> 2);          // swizzled chunk of this lane's B fragments
+  // wave-uniform direct loads of step st into one buffer set
+  auto dma = [&](int st, uint4* Bt, uint4* Ss, float* Cs) {
+    const int jb = j0 + 32 * st;
+    const uint4* tile = p.dens16 + (size_t)(jb / 32) * TQ;
+    for (int q = wv; q < NQ; q += 8) {
+      const int P = 64 * q + lane;
+      const int row = P >> 2;
+      __builtin_amdgcn_global_load_lds(tile + row * 4 + ((P & 3) ^ ((row >> 2) & 3)), &Bt[64 * q], 16, 0, 0);
+    }
+    if (wv >= 6) {
+      const int P = 64 * (wv - 6) + lane;
+      const int js = min(jb + (P >> 2), n - 1);
+      __builtin_amdgcn_global_load_lds(srcq + (size_t)js * 4 + (P & 3), &Ss[64 * (wv - 6)], 16, 0, 0);
+    } else if (wv >= 3) {
+      const int P = 64 * (wv - 3) + lane;
+      int k = (i0 - jb - 31 + min(P, 159)) % n;
+      k += (k < 0) ? n : 0;
+      __builtin_amdgcn_global_load_lds(p.C32 + k, &Cs[64 * (wv - 3)], 4, 0, 0);
+    }
+  };
+  flt4 Re[ND][NCB], Im[ND][NCB];
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      Re[d][cb] = flt4{0, 0, 0, 0};
+      Im[d][cb] = flt4{0, 0, 0, 0};
+    }
+  auto step = [&](int st, const uint4* Bt, const uint4* Ss, const float* Cs, uint4* Btn, uint4* Ssn, float* Csn) {
+    if (st + 1 < nsteps) dma(st + 1, Btn, Ssn, Csn);
+    const int jb = j0 + 32 * st;
+    // A fragments: this lane's 8 pairs, hi and lo parts of Re K and Im K
+    uint32_t arh[ND][4], arl[ND][4], aih[ND][4], ail[ND][4];
+    const SrcRec* ss = reinterpret_cast<const SrcRec*>(Ss);
+#pragma unroll
+    for (int e2 = 0; e2 < 4; ++e2) {
+      cplxf K[2][ND];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int jj = 8 * lk + 2 * e2 + h;
+        const int j = jb + jj;
+        pair_kernel_far32<OP>(t, tnx, tny, ss[jj], Cs[31 + ti - jj], ii == j || j >= j1, f, K[h]);
+      }
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        split_h2(K[0][d].re, K[1][d].re, arh[d][e2], arl[d][e2]);
+        split_h2(K[0][d].im, K[1][d].im, aih[d][e2], ail[d][e2]);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      uint32_t nih[4], nil[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        nih[e] = aih[d][e] ^ 0x80008000u;
+        nil[e] = ail[d][e] ^ 0x80008000u;
+      }
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int row = d * 4 * NC + cb * 16 + li;
+        const uint4 brh = Bt[row * 4 + gsw];
+        const uint4 brl = Bt[(row + NC) * 4 + gsw];
+        const uint4 bih = Bt[(row + 2 * NC) * 4 + gsw];
+        const uint4 bil = Bt[(row + 3 * NC) * 4 + gsw];
+        flt4 r = Re[d][cb], m = Im[d][cb];
+        r = mma16(arh[d], brh, r);
+        m = mma16(arh[d], bih, m);
+        r = mma16(arh[d], brl, r);
+        m = mma16(arh[d], bil, m);
+        r = mma16(arl[d], brh, r);
+        m = mma16(arl[d], bih, m);
+        r = mma16(nih, bih, r);
+        m = mma16(aih[d], brh, m);
+        r = mma16(nih, bil, r);
+        m = mma16(aih[d], brl, m);
+        r = mma16(nil, bih, r);
+        m = mma16(ail[d], brh, m);
+        Re[d][cb] = r;
+        Im[d][cb] = m;
+      }
+    }
+    // the next step's loads are complete and this step's reads are done
+    __syncthreads();
+  };
+  dma(0, Bt0, Ss0, Cs0);
+  __syncthreads();
+  for (int st = 0; st < nsteps; st += 2) {
+    step(st, Bt0, Ss0, Cs0, Bt1, Ss1, Cs1);
+    if (st + 1 < nsteps) step(st + 1, Bt1, Ss1, Cs1, Bt0, Ss0, Cs0);
+  }
+  cplxf* part = p.partial32;
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int c = cb * 16 + li;
+      const float us = p.unscale16[d * NC + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + wv * 16 + 4 * lk + r;
+        if (row < n)
+          part[(((size_t)blockIdx.y * ND + d) * NC + c) * n + row] = cplxf{Re[d][cb][r] * us, Im[d][cb][r] * us};
+      }
+    }
+}
+
+// Per-column power-of-two scales of the densities: one block per (d, c).
+// eK: the kernel-value exponent of density d.  The density scale puts the
+// column's largest |re| or |im| below 2^14; the combined exponent stays in
+// [-120, 120] so that the FP32 unscale factor is a normal number.
+__global__ __launch_bounds__(256) void dens16_scales(const cplx* __restrict__ a, const cplx* __restrict__ b,
+                                                     int n, int nrhs, int nrp, int col0, int eK0, int eK1,
+                                                     double* __restrict__ bscale, float* __restrict__ unscale) {
+  const int d = blockIdx.x / nrp, c = blockIdx.x % nrp;
+  __shared__ double red[256];
+  double m = 0.0;
+  if (c < nrhs) {
+    const cplx* src = (d == 0 ? a : b) + (size_t)(col0 + c) * n;
+    for (int j = threadIdx.x; j < n; j += 256) {
+      const cplx v = src[j];
+      m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
+    }
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int eK = d == 0 ? eK0 : eK1;
+    int eB = 0;
+    if (red[0] > 0.0) {
+      int e;
+      (void)frexp(red[0], &e);  // red[0] < 2^e
+      eB = 14 - e;
+    }
+    eB = max(eB, max(-100, -120 - eK));
+    eB = min(eB, min(100, 120 - eK));
+    bscale[blockIdx.x] = ldexp(1.0, eB);
+    unscale[blockIdx.x] = (float)ldexp(1.0, -(eK + eB));
+  }
+}
+
+// Split-FP16 density tiles (layout in sweep_mfma16); one thread per 8
+// sources of one (block, density, column).
+__global__ void pack_dens16(const cplx* __restrict__ a, const cplx* __restrict__ b,
+                            const double* __restrict__ bscale, uint4* __restrict__ out, int n, int nrhs,
+                            int nrp, int nd, int col0, int nb) {
+  const size_t tot = (size_t)nb * 4 * nd * nrp;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int g = idx & 3;
+    const size_t bi = (idx >> 2) % nb;
+    const int dc = (int)((idx >> 2) / nb);  // d * nrp + c
+    const int d = dc / nrp, c = dc % nrp;
+    const double sc = bscale[dc];
+    const cplx* src = (d == 0 ? a : b) + (size_t)(col0 + c) * n;
+    uint32_t rh[4], rl[4], ih[4], il[4];
+#pragma unroll
+    for (int e2 = 0; e2 < 4; ++e2) {
+      float v[2][2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const size_t j = bi * 32 + 8 * g + 2 * e2 + h;
+        const cplx x = (c < nrhs && j < (size_t)n) ? src[j] : cplx{0.0, 0.0};
+        v[h][0] = (float)(x.re * sc);
+        v[h][1] = (float)(x.im * sc);
+      }
+      split_h2(v[0][0], v[1][0], rh[e2], rl[e2]);
+      split_h2(v[0][1], v[1][1], ih[e2], il[e2]);
+    }
+    uint4* o = out + ((((bi * nd + d) * 4) * nrp + c) * 4 + g);
+    const size_t ps = (size_t)nrp * 4;  // uint4 between parts
+    o[0] = uint4{rh[0], rh[1], rh[2], rh[3]};
+    o[ps] = uint4{rl[0], rl[1], rl[2], rl[3]};
+    o[2 * ps] = uint4{ih[0], ih[1], ih[2], ih[3]};
+    o[3 * ps] = uint4{il[0], il[1], il[2], il[3]};
   }
 }
 
@@ -443,9 +682,34 @@ static void launch_sweep32(const SweepParams& sp, int nrp, hipStream_t st) {
       default: sweep_private32<OP, 4><<<grid, 256, 0, st>>>(sp); break;
     }
   } else {
-    dim3 grid((n + 63) / 64, sp.nchunks);
-    if (nrp == 32) sweep_mfma<OP, 1, Mfma32><<<grid, 512, 0, st>>>(sp);
-    else sweep_mfma<OP, 2, Mfma32><<<grid, 512, 0, st>>>(sp);
+    dim3 grid((n + 127) / 128, sp.nchunks);
+    switch (nrp) {
+      case 16: sweep_mfma16<OP, 1><<<grid, 512, 0, st>>>(sp); break;
+      case 32: sweep_mfma16<OP, 2><<<grid, 512, 0, st>>>(sp); break;
+      default: sweep_mfma16<OP, 4><<<grid, 512, 0, st>>>(sp); break;
+    }
+  }
+}
+
+// Exponents eK[d] of the power-of-two scales of the FP32 kernel values in the
+// split-FP16 sweep: 2^eK times a bound on |Re K| and |Im K| of a far pair
+// stays below 2^14.  For omega r >= 25, |H0| and |H1| are below 0.17; 0.25
+// is used.  With w = dt |x'_j| and c = max_k |C_k| |x'_j|, the S-type part is
+// at most 0.25 (w/4 + c/(4 pi)) and the D-type part omega times that.
+static void kernel_scales(const dp_problem* p, int op, int eK[2]) {
+  const double base = 0.25 * (0.25 * (2.0 * kPi / (double)p->n) * p->spmax + p->cmax * p->spmax * kInv4Pi);
+  double bnd[2] = {base, base};
+  switch (op) {
+    case OP_SOFT: bnd[0] = (p->omega + p->eta) * base; break;
+    case OP_S: break;
+    case OP_D:
+    case OP_DP: bnd[0] = p->omega * base; break;
+    default: bnd[1] = (p->omega * p->omega / p->eta + p->omega) * base; break;
+  }
+  for (int d = 0; d < 2; ++d) {
+    int e = 0;
+    (void)std::frexp(bnd[d], &e);  // bnd < 2^e
+    eK[d] = std::min(60, std::max(-60, 14 - e));
   }
 }
 
@@ -472,9 +736,10 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   }
   // matrix-core shape for every multi-column mixed sweep, and for FP64 sweeps
   // of 8-16 columns when the autotuner found it faster than the VALU kernel
-  if (nrp > 4 && nrp < 32 && (prec || cfg.mfma == 1)) nrp = 32;
+  if (prec && nrp > 4 && nrp < 16) nrp = 16;
+  if (!prec && nrp > 4 && nrp < 32 && cfg.mfma == 1) nrp = 32;
   const bool part32 = prec && nrp > 4;
-  const int rows_per_block = nrp <= 4 ? 256 : 64;
+  const int rows_per_block = nrp <= 4 ? 256 : (part32 ? 128 : 64);
   const int bx = (n + rows_per_block - 1) / rows_per_block;
   int nchunks = (cfg.target_blocks + bx - 1) / bx;
   int maxch = n / 64 > 0 ? n / 64 : 1;
@@ -485,20 +750,38 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   nchunks = (n + chunk_len - 1) / chunk_len;
   DP_TRY(p->dens.reserve((size_t)n * nrp * nd * sizeof(cplx)));
   DP_TRY(p->partial.reserve((size_t)nchunks * nd * nrp * n * sizeof(cplx)));
+  int eK[2] = {0, 0};
+  const int nb = (n + 31) / 32;
+  if (part32) {
+    kernel_scales(p, op, eK);
+    DP_TRY(p->dens16.reserve((size_t)nb * nd * nrp * 256));
+    DP_TRY(p->sc16.reserve((size_t)nd * nrp * (sizeof(double) + sizeof(float))));
+  }
+  double* bscale = p->sc16.as<double>();
+  float* unscale = reinterpret_cast<float*>(bscale + nd * nrp);
   {
     size_t tot = (size_t)n * nrp * nd;
-    if (part32)
+    if (part32) {
       pack_dens32<<<grid1d(tot), 256, 0, st>>>(a, b, reinterpret_cast<cplxf*>(p->dens.p), n, nrhs, nrp, nd, col0);
-    else
+      dens16_scales<<<nd * nrp, 256, 0, st>>>(a, b ? b : a, n, nrhs, nrp, col0, eK[0], eK[1], bscale, unscale);
+      pack_dens16<<<grid1d((size_t)nb * 4 * nd * nrp), 256, 0, st>>>(a, b ? b : a, bscale, p->dens16.as<uint4>(),
+                                                                      n, nrhs, nrp, nd, col0, nb);
+    } else {
       pack_dens<<<grid1d(tot), 256, 0, st>>>(a, b, p->dens.as<cplx>(), n, nrhs, nrp, nd, col0);
+    }
   }
   SweepParams sp;
   sp.src = p->src.as<SrcRec>();
   sp.C = p->C.as<double>();
+  sp.C32 = p->C32.as<float>();
   sp.dens = p->dens.as<cplx>();
   sp.partial = p->partial.as<cplx>();
   sp.dens32 = reinterpret_cast<const cplxf*>(p->dens.p);
   sp.partial32 = reinterpret_cast<cplxf*>(p->partial.p);
+  sp.dens16 = part32 ? p->dens16.as<uint4>() : nullptr;
+  sp.unscale16 = part32 ? unscale : nullptr;
+  sp.ksc[0] = std::ldexp(1.0f, eK[0]);
+  sp.ksc[1] = std::ldexp(1.0f, eK[1]);
   sp.n = n;
   sp.nrp = nrp;
   sp.nd = nd;

@@ -105,62 +105,75 @@ struct Nd32 {
   static constexpr int v = Nd<OP>::v;
 };
 
-// Kernel values of one pair from FP32 Hankel values; the source's normal,
-// trapezoid weight and speed come from its FP32 copies.
-template <int OP>
-__device__ __forceinline__ void assemble_pair32(const Tgt& t, const SrcRec& s, float dx, float dy, float rinv,
-                                                const H01f& h, float Ck, bool self, float omega, float eta,
-                                                cplxf* K) {
-  constexpr float k4 = (float)kInv4Pi;
-  const float w = s.wf;
-  const float ck = Ck * s.spf;
-  if constexpr (OP == OP_SOFT) {
-    const float nd = (s.nxf * dx + s.nyf * dy) * rinv;
-    const float a = 0.25f * omega * nd, b = 0.25f * eta;
-    K[0].re = w * fmaf(-a, h.h1.im, b * h.h0.re) - ck * (omega * k4) * nd * h.h1.re;
-    K[0].im = w * fmaf(a, h.h1.re, b * h.h0.im) + ck * (eta * k4) * h.h0.re;
-  } else if constexpr (OP == OP_S) {
-    K[0].re = -0.25f * w * h.h0.im - ck * k4 * h.h0.re;
-    K[0].im = 0.25f * w * h.h0.re;
-  } else if constexpr (OP == OP_D) {
-    const float nd = (s.nxf * dx + s.nyf * dy) * rinv;
-    K[0].re = -0.25f * omega * nd * w * h.h1.im - ck * omega * k4 * nd * h.h1.re;
-    K[0].im = 0.25f * omega * nd * w * h.h1.re;
-  } else if constexpr (OP == OP_DP) {
-    const float ni = ((float)t.nx * dx + (float)t.ny * dy) * rinv;
-    K[0].re = 0.25f * omega * ni * w * h.h1.im + ck * omega * k4 * ni * h.h1.re;
-    K[0].im = -0.25f * omega * ni * w * h.h1.re;
-  } else {
-    const float ni = ((float)t.nx * dx + (float)t.ny * dy) * rinv;
-    const float Sre = -0.25f * w * h.h0.im - ck * k4 * h.h0.re;
-    const float Sim = 0.25f * w * h.h0.re;
-    const float Dre = 0.25f * omega * ni * w * h.h1.im + ck * omega * k4 * ni * h.h1.re;
-    const float Dim = -0.25f * omega * ni * w * h.h1.re;
-    const float g = (omega * omega / eta) * ((float)t.nx * s.nxf + (float)t.ny * s.nyf);
-    K[0] = {Sre, Sim};
-    K[1] = {g * Sim - Dre, -g * Sre - Dim};
-  }
-  if (self) {
-#pragma unroll
-    for (int d = 0; d < Nd<OP>::v; ++d) K[d] = {0.0f, 0.0f};
-  }
+// Per-launch constants of the FP32 kernel values, with power-of-two output
+// scales sc[d] (1 when unscaled) folded in.
+struct Far32 {
+  double omega, r2near;
+  float sc0;      // scale of density 0
+  float om_sc0;   // omega sc0
+  float om_sc1;   // omega sc1
+  float eta_sc0;  // eta sc0 (soft)
+  float g_sc1;    // (omega^2/eta) sc1 (hard)
+};
+
+__host__ __device__ inline Far32 far32_consts(double omega, double eta, double r2near, float sc0, float sc1) {
+  Far32 f;
+  f.omega = omega;
+  f.r2near = r2near;
+  f.sc0 = sc0;
+  f.om_sc0 = (float)(omega * sc0);
+  f.om_sc1 = (float)(omega * sc1);
+  f.eta_sc0 = (float)(eta * sc0);
+  f.g_sc1 = (float)(omega * omega / eta * sc1);
+  return f;
 }
 
-// Far-field pair with FP32 kernel values.  1/r comes from the FP32 reciprocal
-// square root refined by one Newton step in FP64 (relative error ~2e-14), so
-// the phase omega r keeps an absolute error below 1e-9 for omega r < 5e4.
+// Far-field pair with FP32 kernel values.  r comes from the FP32 reciprocal
+// square root y0 refined by one Newton step for sqrt in FP64 (relative error
+// ~1e-14), so the phase omega r keeps an absolute error below 1e-9 for
+// omega r < 5e4; 1/r in the FP32 factors is y0 itself.  With the source's
+// FP32 fields wf = dt |x'_j| / 4 and spf = |x'_j| / (4 pi), the S-type and
+// D-type values share
+//   A0 = wf Im H0 + cq Re H0,  B1 = wf Im H1 + cq Re H1,  cq = C_k spf,
+// (S = -A0 + i wf Re H0, D' = omega nu_i.rhat (B1 - i wf Re H1)).  Pairs with
+// zero set (self, near field, outside the caller's range) get wf = cq = 0
+// and hence K = 0; their distance is replaced by 1 so every value is finite.
 template <int OP>
-__device__ __forceinline__ void pair_kernel_far32(const Tgt& t, const SrcRec& s, double Ck, bool self, double omega,
-                                                  double eta, double r2near, cplxf* K) {
+__device__ __forceinline__ void pair_kernel_far32(const Tgt& t, float tnx, float tny, const SrcRec& s, float Ck,
+                                                  bool zero, const Far32& f, cplxf* K) {
   const double dx = t.x - s.x, dy = t.y - s.y;
   double r2 = pair_r2(t.x, t.y, s.x, s.y);
-  const bool zero = self || r2 < r2near;
-  r2 = self ? 1.0 : r2;
-  const double y0 = (double)dp_rsqrtf((float)r2);
-  const double rinv = y0 * fma(-0.5 * r2, y0 * y0, 1.5);
-  const double z = omega * (r2 * rinv);
-  const H01f h = hankel01_far32(fmax(z, DP_HANKEL_ZA));
-  assemble_pair32<OP>(t, s, (float)dx, (float)dy, (float)rinv, h, (float)Ck, zero, (float)omega, (float)eta, K);
+  zero = zero || r2 < f.r2near;
+  r2 = zero ? 1.0 : r2;
+  const float y0 = dp_rsqrtf((float)r2);
+  const double yd = (double)y0;
+  const double r0 = r2 * yd;
+  const double r = fma(0.5 * yd, fma(-r0, r0, r2), r0);
+  const H01f h = hankel01_far32(fmax(f.omega * r, DP_HANKEL_ZA));
+  const float dxf = (float)dx, dyf = (float)dy;
+  const float wq = zero ? 0.0f : s.wf;
+  const float cq = zero ? 0.0f : Ck * s.spf;
+  const float A0 = fmaf(wq, h.h0.im, cq * h.h0.re);
+  const float Sr = wq * h.h0.re;
+  if constexpr (OP == OP_S) {
+    K[0] = {-f.sc0 * A0, f.sc0 * Sr};
+    return;
+  }
+  const float B1 = fmaf(wq, h.h1.im, cq * h.h1.re);
+  const float T1 = wq * h.h1.re;
+  if constexpr (OP == OP_SOFT || OP == OP_D) {
+    const float on = fmaf(s.nxf, dxf, s.nyf * dyf) * y0 * f.om_sc0;  // omega nu_j.rhat sc0
+    if constexpr (OP == OP_SOFT) K[0] = {fmaf(f.eta_sc0, Sr, -on * B1), fmaf(f.eta_sc0, A0, on * T1)};
+    else K[0] = {-on * B1, on * T1};
+  } else if constexpr (OP == OP_DP) {
+    const float on = fmaf(tnx, dxf, tny * dyf) * y0 * f.om_sc0;      // omega nu_i.rhat sc0
+    K[0] = {on * B1, -on * T1};
+  } else {  // OP_HARD: S and G = -i (omega^2/eta)(nu_i.nu_j) S - D'
+    const float on = fmaf(tnx, dxf, tny * dyf) * y0 * f.om_sc1;
+    const float g = fmaf(tnx, s.nxf, tny * s.nyf) * f.g_sc1;
+    K[0] = {-f.sc0 * A0, f.sc0 * Sr};
+    K[1] = {fmaf(g, Sr, -on * B1), fmaf(g, A0, on * T1)};
+  }
 }
 
 // ------------------------------------------------------------ epilogue

@@ -7,6 +7,10 @@
 // The sweep uses A_ij = (2 pi/n)|x'_j| K + C_{(i-j) mod n} |x'_j| K1 off the
 // diagonal, which equals R_{|i-j|} K1 + (pi/N) K2 with K2 = K - K1 log(...)
 // without forming the cancelling difference.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "dp_internal.hpp"
 
 namespace dp {
@@ -65,7 +69,15 @@ int build_tables(dp_problem* p) {
   trig_tables<<<(n + 255) / 256, 256, 0, st>>>(ct.as<double>(), tw, n);
   kress_table<<<n, 256, 0, st>>>(ct.as<double>(), p->C.as<double>(), n);
   DP_HIP(hipGetLastError());
-  DP_HIP(hipMemcpyAsync(&p->R0, p->C.as<double>(), sizeof(double), hipMemcpyDeviceToHost, st));
+  std::vector<double> hc(n);
+  DP_HIP(hipMemcpyAsync(hc.data(), p->C.as<double>(), n * sizeof(double), hipMemcpyDeviceToHost, st));
+  DP_HIP(hipStreamSynchronize(st));
+  p->R0 = hc[0];
+  p->cmax = 0;
+  for (int k = 1; k < n; ++k) p->cmax = std::max(p->cmax, std::fabs(hc[k]));
+  std::vector<float> hc32(hc.begin(), hc.end());
+  DP_TRY(p->C32.reserve(n * sizeof(float)));
+  DP_HIP(hipMemcpyAsync(p->C32.p, hc32.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
   DP_HIP(hipStreamSynchronize(st));
   ct.release();
   return DP_OK;
