@@ -155,6 +155,7 @@ int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nr
   }
   if (rc == DP_OK) rc = build_tables(p);
   if (rc == DP_OK && !kappa) rc = curvature_spectral(p, p->hkap.data());
+  if (rc == DP_OK) rc = build_diag(p);
   if (rc == DP_OK) rc = near_build(p);
   if (rc != DP_OK) {
     dp_problem_destroy(p);
@@ -178,6 +179,7 @@ void dp_problem_destroy(dp_problem* p) {
   p->partial.release();
   p->dens16.release();
   p->C32.release();
+  p->diag.release();
   p->sc16.release();
   p->near_ptr.release();
   p->near_col.release();

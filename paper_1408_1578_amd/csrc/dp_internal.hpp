@@ -105,6 +105,7 @@ struct dp_problem {
   dp::DevBuf src;       // SrcRec[n]
   dp::DevBuf C;         // double[n]
   dp::DevBuf C32;       // float[n], FP32 copy of C
+  dp::DevBuf diag;      // double4[n]: S_ii (re, im), D_ii
   dp::DevBuf twiddle;   // cplx[n]   (e^{-2 pi i l/n})
   dp::DevBuf dens;      // sweep operands
   dp::DevBuf partial;   // sweep partial sums
@@ -152,6 +153,8 @@ int spectral_derivative(dp_problem* p, int nrhs, const cplx* in, cplx* out);
 // Curvature from the spectral t-derivatives of the node positions (power-of-two
 // n, twiddles built): written into the source records and into hkap (host, n).
 int curvature_spectral(dp_problem* p, double* hkap);
+// Per-node diagonal table (after the curvature and C_k are in place).
+int build_diag(dp_problem* p);
 // rhs
 int rhs_plane_wave(dp_problem* p, int nrhs, const double* angles_dev, cplx* f);
 // hankel test hook

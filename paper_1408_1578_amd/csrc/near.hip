@@ -162,8 +162,83 @@ void launch_values(int op, const NearParams& np, cplx* kv, hipStream_t st) {
   }
 }
 
+// All 64 columns: one lane per column, so a row's entries are the same for
+// the whole wave (scalar loads of the column index and kernel values, four
+// entries in flight).  A block covers 16 consecutive rows, 4 per wave, and
+// stages the sums in LDS (row stride padded to 17) so that each (density,
+// column) is written as one 16-row run.  Row blocks are spread over the XCDs
+// as in near_apply.
+template <int OP, class DT>
+__global__ __launch_bounds__(256) void near_apply64(NearParams p) {
+  constexpr int ND = Nd<OP>::v;
+  __shared__ cplx tile[ND * 64 * 17];  // [d][c][row]
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nb = gridDim.x;
+  const int x = blockIdx.x & 7, q8 = nb >> 3, r8 = nb & 7;
+  const int i0 = (x * q8 + min(x, r8) + (int)(blockIdx.x >> 3)) * 16;
+  const DT* dens = static_cast<const DT*>(p.dens);
+  for (int rr = 0; rr < 4; ++rr) {
+    const int rl = wv * 4 + rr;
+    const int i = i0 + rl;
+    cplx acc[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) acc[d] = {0.0, 0.0};
+    if (i < p.n) {
+      const int e0 = p.ptr[i], e1 = p.ptr[i + 1];
+      int q = e0;
+      for (; q + 4 <= e1; q += 4) {
+        int j[4];
+        cplx K[4][ND];
+        DT v[4][ND];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          j[u] = p.col[q + u];
+#pragma unroll
+          for (int d = 0; d < ND; ++d) K[u][d] = p.kv[(size_t)(q + u) * ND + d];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int d = 0; d < ND; ++d) v[u][d] = dens[((size_t)j[u] * ND + d) * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int d = 0; d < ND; ++d) cfma(acc[d], K[u][d], cplx{(double)v[u][d].re, (double)v[u][d].im});
+      }
+      for (; q < e1; ++q) {
+        const int j = p.col[q];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          const DT v = dens[((size_t)j * ND + d) * 64 + lane];
+          cfma(acc[d], p.kv[(size_t)q * ND + d], cplx{(double)v.re, (double)v.im});
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) tile[(d * 64 + lane) * 17 + rl] = acc[d];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ND * 64 * 16; t += 256) {
+    const int rl = t & 15, dc = t >> 4;  // dc = d * 64 + column
+    const int i = i0 + rl;
+    if (i < p.n) p.out[(size_t)dc * p.n + i] = tile[dc * 17 + rl];
+  }
+}
+
 template <class DT>
 void launch_near(int op, const NearParams& np, hipStream_t st) {
+  if (np.nrp == 64) {
+    const int grid = (np.n + 15) / 16;
+    switch (op) {
+      case OP_SOFT: near_apply64<OP_SOFT, DT><<<grid, 256, 0, st>>>(np); break;
+      case OP_HARD: near_apply64<OP_HARD, DT><<<grid, 256, 0, st>>>(np); break;
+      case OP_S: near_apply64<OP_S, DT><<<grid, 256, 0, st>>>(np); break;
+      case OP_D: near_apply64<OP_D, DT><<<grid, 256, 0, st>>>(np); break;
+      default: near_apply64<OP_DP, DT><<<grid, 256, 0, st>>>(np); break;
+    }
+    return;
+  }
   const int grid = (np.n + 3) / 4;
   switch (op) {
     case OP_SOFT: near_apply<OP_SOFT, DT><<<grid, 256, 0, st>>>(np); break;

@@ -59,10 +59,10 @@ struct Precond {
   SparseLU lu;
   DevBuf Lp, Lj, Lx, Up, Uj, Ux, Ud, lvlL, lvlLr, lvlU, lvlUr, pin, pout;
   int nlevL = 0, nlevU = 0;
-  // level-ordered copies for the LDS-resident solve
-  DevBuf itL, itU, jL2, vL2, jU2, vU2, uinv;
-  DevBuf vL2_32, vU2_32, uinv32;  // single-precision copies
-  bool lds_solve = false;
+  // step streams of the single-wave LDS-resident solve (L then U), FP64 and FP32
+  DevBuf slots, slots32;
+  int nsteps = 0;
+  bool lds_solve = false, lds_solve32 = false;
   // dense device LU of floor(W) (when the sparse factors would fill in)
   bool dense_w = false;
   DenseLU dlu;
@@ -604,68 +604,176 @@ __global__ __launch_bounds__(1024) void level_solve(cplx* x, const int* __restri
   }
 }
 
-// Whole floor(W)^{-1} z for one column per block with the column held in LDS:
+// Whole floor(W)^{-1} z for one column per wave, the column held in LDS:
 // gather zp[k] = z[perm_in[k]], forward solve with L (unit diagonal),
-// backward solve with U, scatter u[perm_out[b]] = u'[b].  Rows of one
-// dependency level are independent; each row is an item (row, first entry,
-// entry count) in level order, with its entries stored contiguously, so the
-// only accesses that depend on the previous level are LDS reads.
+// backward solve with U, scatter u[perm_out[b]] = u'[b].  Both solves are
+// one stream of steps of 64 slot records (col, row, value): a lane group of
+// 4, 16 or 64 lanes (chosen per level, coded in the top bits of col) works
+// through rows of a dependency level one after another, one entry per lane
+// per step, and the step that ends a row (row >= 0) writes x[row] = sum of
+// value * x[col] over the row's slots.  A row's slots
+// hold its own diagonal term (x[row] times 1 or 1/U_rr) and the negated,
+// scaled off-diagonal entries, so every row is a plain dot product; rows of
+// one level are independent, and a level's steps come after all steps of the
+// levels it depends on.  One wave executes its LDS accesses in program order,
+// so no barrier is needed, and the slot loads run 32 steps ahead.
+constexpr int kSlotAhead = 32;  // steps the slot loads run ahead (one wave per CU: registers to spare)
+
+// Value of the lane given by a DPP control: quad permutations 0xB1 (l ^ 1)
+// and 0x4E (l ^ 2), rotations within a row of 16 lanes 0x124 (by 4) and
+// 0x128 (by 8).
+template <int CTRL>
+__device__ __forceinline__ float dpp_sum(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_sum(double v) {
+  const int2 h = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, int2{__builtin_amdgcn_update_dpp(0, h.x, CTRL, 0xF, 0xF, false),
+                                         __builtin_amdgcn_update_dpp(0, h.y, CTRL, 0xF, 0xF, false)});
+}
+
 template <class C>
-__global__ __launch_bounds__(256) void tri_solve_lds(const C* __restrict__ z, C* __restrict__ u, int NW,
+struct Slot {
+  int col, row;
+  decltype(C{}.re) re, im;
+};
+
+template <class C>
+__global__ __launch_bounds__(64) void tri_solve_wave(const C* __restrict__ z, C* __restrict__ u, int NW,
                                                      const int* __restrict__ pin, const int* __restrict__ pout,
-                                                     const int4* __restrict__ itL, const int* __restrict__ lvL,
-                                                     int nlevL, const int* __restrict__ jL,
-                                                     const C* __restrict__ vL, const int4* __restrict__ itU,
-                                                     const int* __restrict__ lvU, int nlevU,
-                                                     const int* __restrict__ jU, const C* __restrict__ vU,
-                                                     const C* __restrict__ uinv) {
+                                                     const Slot<C>* __restrict__ slots, int nsteps) {
   extern __shared__ unsigned char lds_raw[];
-  C* xs = reinterpret_cast<C*>(lds_raw);
+  C* xs = reinterpret_cast<C*>(lds_raw);  // NW + 1 elements
   const size_t c = blockIdx.x;
-  for (int k = threadIdx.x; k < NW; k += blockDim.x) xs[k] = z[c * NW + pin[k]];
-  __syncthreads();
-  // each row is handled by RL consecutive lanes (strided over its entries,
-  // then a shuffle reduction): long rows do not serialise a level
-  constexpr int RL = 8;
-  const int g = threadIdx.x / RL, lr = threadIdx.x % RL;
-  const int G = blockDim.x / RL;
-  for (int pass = 0; pass < 2; ++pass) {
-    const int4* it_ = pass ? itU : itL;
-    const int* lv = pass ? lvU : lvL;
-    const int* jj = pass ? jU : jL;
-    const C* vv = pass ? vU : vL;
-    const int nlev = pass ? nlevU : nlevL;
-    for (int l = 0; l < nlev; ++l) {
-      const int b = lv[l], e = lv[l + 1];
-      for (int t0 = b; t0 < e; t0 += G) {
-        const int t = t0 + g;
-        const bool act = t < e;
-        const int4 it = act ? it_[t] : int4{0, 0, 0, 0};
-        C acc = {0, 0};
-        for (int q = it.y + lr; q < it.y + it.z; q += RL) {
-          const C a = vv[q], xv = xs[jj[q]];
-          acc.re += a.re * xv.re - a.im * xv.im;
-          acc.im += a.re * xv.im + a.im * xv.re;
-        }
+  const int lane = threadIdx.x;
+#pragma unroll 32
+  for (int k = lane; k < NW; k += 64) xs[k] = z[c * NW + pin[k]];
+  // nsteps is a multiple of D and the stream holds D more padding steps
+  constexpr int D = kSlotAhead;
+  Slot<C> ring[D];
 #pragma unroll
-        for (int off = RL / 2; off > 0; off >>= 1) {
-          acc.re += __shfl_xor(acc.re, off, RL);
-          acc.im += __shfl_xor(acc.im, off, RL);
-        }
-        if (act && lr == 0) {
-          const C x0 = xs[it.x];
-          C r = {x0.re - acc.re, x0.im - acc.im};
-          if (pass) {
-            const C w = uinv[it.x];
-            r = {r.re * w.re - r.im * w.im, r.re * w.im + r.im * w.re};
-          }
-          xs[it.x] = r;
+  for (int q = 0; q < D; ++q) ring[q] = slots[(size_t)q * 64 + lane];
+  C acc = {0, 0};
+  for (int s0 = 0; s0 < nsteps; s0 += D) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const Slot<C> r = ring[q];
+      ring[q] = slots[(size_t)(s0 + q + D) * 64 + lane];
+      const C xv = xs[r.col & 0x3fffffff];
+      acc.re = fma(r.re, xv.re, fma(-r.im, xv.im, acc.re));
+      acc.im = fma(r.re, xv.im, fma(r.im, xv.re, acc.im));
+      // the step's lanes per row (4, 16 or 64) are in bits 30..31 of col
+      const int wcode = __builtin_amdgcn_readfirstlane((int)((unsigned)r.col >> 30));
+      C tot = acc;
+      tot.re += dpp_sum<0xB1>(tot.re);  // lanes 4g + (l ^ 1)
+      tot.im += dpp_sum<0xB1>(tot.im);
+      tot.re += dpp_sum<0x4E>(tot.re);  // lanes 4g + (l ^ 2)
+      tot.im += dpp_sum<0x4E>(tot.im);
+      if (wcode) {                        // 16 lanes: rotations by 4 and 8 within the row
+        tot.re += dpp_sum<0x124>(tot.re);
+        tot.im += dpp_sum<0x124>(tot.im);
+        tot.re += dpp_sum<0x128>(tot.re);
+        tot.im += dpp_sum<0x128>(tot.im);
+        if (wcode > 1) {                  // 64 lanes
+          tot.re += __shfl_xor(tot.re, 16);
+          tot.im += __shfl_xor(tot.im, 16);
+          tot.re += __shfl_xor(tot.re, 32);
+          tot.im += __shfl_xor(tot.im, 32);
         }
       }
-      __syncthreads();
+      const int wmask = wcode == 0 ? 3 : (wcode == 1 ? 15 : 63);
+      // branch-free: lanes that do not finish a row write the spare element xs[NW]
+      const bool fin = r.row >= 0;
+      xs[fin && (lane & wmask) == 0 ? r.row : NW] = tot;
+      acc.re = fin ? 0 : acc.re;
+      acc.im = fin ? 0 : acc.im;
     }
   }
-  for (int k = threadIdx.x; k < NW; k += blockDim.x) u[c * NW + pout[k]] = xs[k];
+#pragma unroll 32
+  for (int k = lane; k < NW; k += 64) u[c * NW + pout[k]] = xs[k];
+}
+
+// Step stream of the forward (L) then backward (U) solve: within each level,
+// rows sorted by slot count are dealt longest first to the least-loaded lane
+// group, with 4, 16 or 64 lanes per row, whichever takes the fewest steps
+// (long rows alone in a level use the whole wave); padding slots have column
+// 0, value 0 and row -1.
+template <class C>
+static int build_slots(const SparseLU& lu, std::vector<Slot<C>>& out) {
+  using R = decltype(C{}.re);
+  const int NW = lu.n;
+  out.clear();
+  int steps = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const std::vector<int>& lptr = pass ? lu.lvlU_ptr : lu.lvlL_ptr;
+    const std::vector<int>& lrows = pass ? lu.lvlU_rows : lu.lvlL_rows;
+    const std::vector<int>& Pp = pass ? lu.Up : lu.Lp;
+    const std::vector<int>& Jj = pass ? lu.Uj : lu.Lj;
+    const auto& Vv = pass ? lu.Ux : lu.Lx;
+    const int nlev = (int)lptr.size() - 1;
+    for (int l = 0; l < nlev; ++l) {
+      std::vector<std::pair<int, int>> rows;  // (slot count, row)
+      for (int q = lptr[l]; q < lptr[l + 1]; ++q) {
+        const int r = lrows[q];
+        rows.push_back({Pp[r + 1] - Pp[r] + 1, r});
+      }
+      std::sort(rows.begin(), rows.end(), [](const auto& a, const auto& b) {
+        return a.first != b.first ? a.first > b.first : a.second < b.second;
+      });
+      // lanes per row W in {4, 16, 64}: the one with the fewest steps
+      int best_w = 4, best_st = INT32_MAX;
+      std::vector<std::vector<int>> best_grp;
+      for (int W : {4, 16, 64}) {
+        const int ng = 64 / W;
+        std::vector<std::vector<int>> grp(ng);
+        std::vector<int> load(ng, 0);
+        for (const auto& [cnt, r] : rows) {
+          const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+          grp[g].push_back(r);
+          load[g] += (cnt + W - 1) / W;
+        }
+        const int nst = *std::max_element(load.begin(), load.end());
+        if (nst < best_st) {
+          best_st = nst;
+          best_w = W;
+          best_grp = std::move(grp);
+        }
+      }
+      const int W = best_w, nst = best_st;
+      const int wcode = W == 4 ? 0 : (W == 16 ? 1 : 2);
+      const size_t base = out.size();
+      out.resize(base + (size_t)nst * 64, Slot<C>{wcode << 30, -1, 0, 0});
+      for (int g = 0; g < 64 / W; ++g) {
+        int st = 0;
+        for (int r : best_grp[g]) {
+          const std::complex<double> d = pass ? 1.0 / lu.Ud[r] : std::complex<double>(1.0, 0.0);
+          std::vector<std::pair<int, std::complex<double>>> ent;
+          ent.push_back({r, d});
+          for (int q = Pp[r]; q < Pp[r + 1]; ++q) ent.push_back({Jj[q], -d * Vv[q]});
+          const int rs = ((int)ent.size() + W - 1) / W;
+          for (int k = 0; k < rs; ++k)
+            for (int lr = 0; lr < W; ++lr) {
+              Slot<C>& sl = out[base + (size_t)(st + k) * 64 + W * g + lr];
+              const int e = W * k + lr;
+              if (e < (int)ent.size()) {
+                sl.col = ent[e].first | (wcode << 30);
+                sl.re = (R)ent[e].second.real();
+                sl.im = (R)ent[e].second.imag();
+              }
+              sl.row = (k == rs - 1) ? r : -1;
+            }
+          st += rs;
+        }
+      }
+      steps += nst;
+    }
+  }
+  // round up to whole prefetch rounds, plus one round that is only loaded
+  const int total = (steps + kSlotAhead - 1) / kSlotAhead * kSlotAhead;
+  out.resize((size_t)(total + kSlotAhead) * 64, Slot<C>{0, -1, 0, 0});  // width code 0
+  (void)NW;
+  return total;
 }
 
 // ------------------------------------------------------------------ host: setup
@@ -940,46 +1048,21 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     P->nlevL = (int)lu.lvlL_ptr.size() - 1;
     P->nlevU = (int)lu.lvlU_ptr.size() - 1;
     {
-      // level-ordered items (row, first entry, count) and entries
-      auto order = [&](const std::vector<int>& rows, const std::vector<int>& Pp, const std::vector<int>& Jj,
-                       const std::vector<zc>& Vv, std::vector<int4>& items, std::vector<int>& j2,
-                       std::vector<cplx>& v2) {
-        for (int r : rows) {
-          items.push_back(int4{r, (int)j2.size(), Pp[r + 1] - Pp[r], 0});
-          for (int q = Pp[r]; q < Pp[r + 1]; ++q) {
-            j2.push_back(Jj[q]);
-            v2.push_back({Vv[q].real(), Vv[q].imag()});
-          }
-        }
-      };
-      std::vector<int4> itl, itu;
-      std::vector<int> jl, ju;
-      std::vector<cplx> vl, vu, ui(NW);
-      order(lu.lvlL_rows, lu.Lp, lu.Lj, lu.Lx, itl, jl, vl);
-      order(lu.lvlU_rows, lu.Up, lu.Uj, lu.Ux, itu, ju, vu);
-      for (int r = 0; r < NW; ++r) {
-        const zc inv = 1.0 / lu.Ud[r];
-        ui[r] = {inv.real(), inv.imag()};
-      }
-      auto single = [](const std::vector<cplx>& a) {
-        std::vector<cplxf> r(a.size());
-        for (size_t q = 0; q < a.size(); ++q) r[q] = {(float)a[q].re, (float)a[q].im};
-        return r;
-      };
-      if ((rc = upload(P->itL, itl, st)) || (rc = upload(P->itU, itu, st)) || (rc = upload(P->jL2, jl, st)) ||
-          (rc = upload(P->vL2, vl, st)) || (rc = upload(P->jU2, ju, st)) || (rc = upload(P->vU2, vu, st)) ||
-          (rc = upload(P->uinv, ui, st)) || (rc = upload(P->vL2_32, single(vl), st)) ||
-          (rc = upload(P->vU2_32, single(vu), st)) || (rc = upload(P->uinv32, single(ui), st)))
-        return fail(rc);
+      std::vector<Slot<cplx>> sl;
+      std::vector<Slot<cplxf>> sl32;
+      P->nsteps = build_slots(lu, sl);
+      (void)build_slots(lu, sl32);
+      if ((rc = upload(P->slots, sl, st)) || (rc = upload(P->slots32, sl32, st))) return fail(rc);
       int maxlds = 0;
       DP_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->ctx->device));
-      P->lds_solve = (size_t)NW * sizeof(cplx) <= (size_t)maxlds;
-      if (P->lds_solve) {
-        DP_HIP(hipFuncSetAttribute((const void*)tri_solve_lds<cplx>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)(NW * sizeof(cplx))));
-        DP_HIP(hipFuncSetAttribute((const void*)tri_solve_lds<cplxf>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)(NW * sizeof(cplxf))));
-      }
+      P->lds_solve = (size_t)(NW + 1) * sizeof(cplx) <= (size_t)maxlds;
+      P->lds_solve32 = (size_t)(NW + 1) * sizeof(cplxf) <= (size_t)maxlds;
+      if (P->lds_solve)
+        DP_HIP(hipFuncSetAttribute((const void*)tri_solve_wave<cplx>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)((NW + 1) * sizeof(cplx))));
+      if (P->lds_solve32)
+        DP_HIP(hipFuncSetAttribute((const void*)tri_solve_wave<cplxf>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)((NW + 1) * sizeof(cplxf))));
     }
   }
 
@@ -1076,10 +1159,8 @@ static int w_solve(dp_problem* p, int nrhs, const cplx* z, cplx* u) {
   const int NW = P->NW;
   if (P->dense_w) return P->dlu.solve(st, z, u, nrhs);
   if (P->lds_solve) {
-    tri_solve_lds<cplx><<<nrhs, 256, (size_t)NW * sizeof(cplx), st>>>(
-        z, u, NW, P->pin.as<int>(), P->pout.as<int>(), P->itL.as<int4>(), P->lvlL.as<int>(), P->nlevL,
-        P->jL2.as<int>(), P->vL2.as<cplx>(), P->itU.as<int4>(), P->lvlU.as<int>(), P->nlevU, P->jU2.as<int>(),
-        P->vU2.as<cplx>(), P->uinv.as<cplx>());
+    tri_solve_wave<cplx><<<nrhs, 64, (size_t)(NW + 1) * sizeof(cplx), st>>>(
+        z, u, NW, P->pin.as<int>(), P->pout.as<int>(), P->slots.as<Slot<cplx>>(), P->nsteps);
     return DP_OK;
   }
   cplx* t = P->wt.as<cplx>();
@@ -1135,11 +1216,9 @@ static int apply_core32(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
   DP_TRY(run_seg_gemm<cplxf>(p, BINV, 0, 0, 0, 0, sv, n, nullptr, y, n, nrhs));
   DP_TRY(run_seg_gemm<cplxf>(p, UT, 1, 0, 1, 0, y, n, nullptr, g, NW, nrhs));
   DP_TRY(run_seg_gemm<cplxf>(p, TT, 1, 1, 1, 0, g, NW, nullptr, z, NW, nrhs));
-  if (!P->dense_w && P->lds_solve) {
-    tri_solve_lds<cplxf><<<nrhs, 256, (size_t)NW * sizeof(cplxf), st>>>(
-        z, u, NW, P->pin.as<int>(), P->pout.as<int>(), P->itL.as<int4>(), P->lvlL.as<int>(), P->nlevL,
-        P->jL2.as<int>(), P->vL2_32.as<cplxf>(), P->itU.as<int4>(), P->lvlU.as<int>(), P->nlevU, P->jU2.as<int>(),
-        P->vU2_32.as<cplxf>(), P->uinv32.as<cplxf>());
+  if (!P->dense_w && P->lds_solve32) {
+    tri_solve_wave<cplxf><<<nrhs, 64, (size_t)(NW + 1) * sizeof(cplxf), st>>>(
+        z, u, NW, P->pin.as<int>(), P->pout.as<int>(), P->slots32.as<Slot<cplxf>>(), P->nsteps);
   } else {
     to_double<<<grid1(nw), 256, 0, st>>>(z, P->wz.as<cplx>(), nw);
     DP_TRY(w_solve(p, nrhs, P->wz.as<cplx>(), P->wu.as<cplx>()));
@@ -1246,7 +1325,7 @@ void precond_destroy(Precond* P) {
   }
   for (DevBuf* b : {&P->d_segs, &P->d_ptrs, &P->d_dims, &P->Lp, &P->Lj, &P->Lx, &P->Up, &P->Uj, &P->Ux, &P->Ud,
                     &P->lvlL, &P->lvlLr, &P->lvlU, &P->lvlUr, &P->pin, &P->pout, &P->wy, &P->wg, &P->wz, &P->wu,
-                    &P->wt, &P->wn, &P->itL, &P->itU, &P->jL2, &P->vL2, &P->jU2, &P->vU2, &P->uinv})
+                    &P->wt, &P->wn, &P->slots, &P->slots32})
     b->release();
   P->dlu.release();
   if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
@@ -1257,7 +1336,7 @@ void precond_destroy(Precond* P) {
     c.Ut32.release();
     c.Tt32.release();
   }
-  for (DevBuf* b : {&P->d_ptrs32, &P->vL2_32, &P->vU2_32, &P->uinv32, &P->sy, &P->sg, &P->sz, &P->su, &P->sn,
+  for (DevBuf* b : {&P->d_ptrs32, &P->sy, &P->sg, &P->sz, &P->su, &P->sn,
                     &P->sv, &P->sq})
     b->release();
   P->win.release();

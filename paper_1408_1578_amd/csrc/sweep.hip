@@ -815,6 +815,7 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   DP_TRY(near_apply_group(p, op, nrp, p->dens.p, part32));
   EpiParams e;
   e.src = sp.src;
+  e.diag = p->diag.as<double4>();
   e.partial = sp.partial;
   e.nearp = p->near_nnz > 0 ? p->near_out.as<cplx>() : nullptr;
   e.q = op == OP_HARD ? b : a;
@@ -945,6 +946,28 @@ void SweepClock::destroy() {
   for (auto e : ev) (void)hipEventDestroy(e);
   ev.clear();
   used = 0;
+}
+
+// Diagonal (Kress limits) of S and of D = D' at every node:
+//   S_ii = R0 (-sp/(4 pi)) + dt sp (i/4 - gamma/(2 pi) - log(omega sp/2)/(2 pi)),
+//   D_ii = -dt kappa sp/(4 pi).
+__global__ void diag_table(const SrcRec* __restrict__ src, double4* __restrict__ diag, int n, double R0, double dt,
+                           double omega) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const SrcRec s = src[i];
+    const double sp = s.sp;
+    diag[i] = double4{R0 * (-sp * kInv4Pi) + dt * sp * (-kEulerGamma - log(0.5 * omega * sp)) * (2.0 * kInv4Pi),
+                      0.25 * dt * sp, -dt * s.kappa * sp * kInv4Pi, 0.0};
+  }
+}
+
+int build_diag(dp_problem* p) {
+  const int n = (int)p->n;
+  DP_TRY(p->diag.reserve((size_t)n * sizeof(double4)));
+  diag_table<<<grid1d(n), 256, 0, p->ctx->stream>>>(p->src.as<SrcRec>(), p->diag.as<double4>(), n, p->R0,
+                                                    2.0 * kPi / n, p->omega);
+  DP_HIP(hipGetLastError());
+  return DP_OK;
 }
 
 int sweep_apply(dp_problem* p, int op, int nrhs, const cplx* q, cplx* y, int prec) {

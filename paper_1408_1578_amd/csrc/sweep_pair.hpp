@@ -179,6 +179,7 @@ __device__ __forceinline__ void pair_kernel_far32(const Tgt& t, float tnx, float
 // ------------------------------------------------------------ epilogue
 struct EpiParams {
   const SrcRec* src;
+  const double4* diag;  // per node: S_ii (re, im), D_ii
   const void* partial;
   const cplx* nearp;   // near-field sums [nd][nrp][n] (FP64) or null
   const cplx* q;       // density (n x nrhs), for diagonal and identity terms
@@ -190,32 +191,43 @@ struct EpiParams {
 };
 
 // Sum the near-field sums and the chunk partials (FP64 or FP32), add the
-// diagonal (Kress limits) and the identity terms, in FP64.
+// diagonal (Kress limits, per-row table) and the identity terms, in FP64.
+// The partials of four chunks are requested together.
 template <class PT>
 __global__ void sweep_epilogue(EpiParams e) {
   const size_t tot = (size_t)e.n * e.nrhs;
   const int nd = e.op == OP_HARD ? 2 : 1;
   const PT* part = static_cast<const PT*>(e.partial);
+  const size_t cs = (size_t)nd * e.nrp * e.n;  // elements between chunks
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
        idx += (size_t)gridDim.x * blockDim.x) {
     const int i = idx % e.n;
     const int c = idx / e.n;
-    const SrcRec s = e.src[i];
-    const double sp = s.sp;
-    // S_ii = R0 (-sp/(4 pi)) + dt sp (i/4 - gamma/(2 pi) - log(omega sp/2)/(2 pi))
-    const cplx Sii = {e.R0 * (-sp * kInv4Pi) +
-                          e.dt * sp * (-kEulerGamma - log(0.5 * e.omega * sp)) * (2.0 * kInv4Pi),
-                      0.25 * e.dt * sp};
-    const double Dii = -e.dt * s.kappa * sp * kInv4Pi;  // D_ii = D'_ii
+    const double4 dg = e.diag[i];  // S_ii (re, im), D_ii = D'_ii
+    const cplx Sii = {dg.x, dg.y};
+    const double Dii = dg.z;
     cplx sum[2] = {{0.0, 0.0}, {0.0, 0.0}};
     if (e.nearp)
       for (int d = 0; d < nd; ++d) sum[d] = e.nearp[((size_t)d * e.nrp + c) * e.n + i];
-    for (int ch = 0; ch < e.nchunks; ++ch)
-      for (int d = 0; d < nd; ++d) {
-        const PT v = part[(((size_t)ch * nd + d) * e.nrp + c) * e.n + i];
+    for (int d = 0; d < nd; ++d) {
+      const PT* pd = part + ((size_t)d * e.nrp + c) * e.n + i;
+      int ch = 0;
+      for (; ch + 4 <= e.nchunks; ch += 4) {
+        PT v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = pd[(ch + u) * cs];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          sum[d].re += (double)v[u].re;
+          sum[d].im += (double)v[u].im;
+        }
+      }
+      for (; ch < e.nchunks; ++ch) {
+        const PT v = pd[ch * cs];
         sum[d].re += (double)v.re;
         sum[d].im += (double)v.im;
       }
+    }
     const cplx qi = e.q[(size_t)(e.col0 + c) * e.n + i];
     const size_t o = (size_t)(e.col0 + c) * e.n + i;
     if (e.op == OP_SOFT) {
