@@ -184,31 +184,34 @@ DP_HD float dp_rsqrtf(float z) {
 // Asymptotic branch for z >= DP_HANKEL_ZA with FP32 arithmetic: the phase z
 // is reduced modulo pi/2 in FP64 (|z| up to 1e6 keeps ~1e-16 absolute phase
 // error), everything after the reduction is FP32 with the FP32-economized
-// polynomials (approximation error < 4e-9).  Relative accuracy ~3e-7.
-DP_HD H01f hankel01_far32(double z) {
+// polynomials (approximation error < 4e-9).  Relative accuracy ~3e-7.  Both
+// values come out multiplied by `scale` (a power of two, or 1).
+// With z = q pi/2 + r, e^{i(z - pi/4)} sqrt(2) = (c + s) + i (s - c) for
+// c = cos z, s = sin z; in terms of P = cos r + sin r and M = cos r - sin r
+// that pair is (P, -M), (M, P), (-P, M), (-M, -P) for q = 0, 1, 2, 3 mod 4.
+DP_HD H01f hankel01_far32(double z, float scale = 1.0f) {
   const double kq = rint(z * kTwoOverPi);
   double rr = fma(-kq, kPio2Hi, z);
   rr = fma(-kq, kPio2Lo, rr);
   const float r = (float)rr, v = r * r;
   const float sr = fmaf(r * v, horner(kSinS32, v), r);
   const float cr = fmaf(v, horner(kCosC32, v), 1.0f);
-  const int q = (int)kq & 3;  // kq < 2^31 for z < 3e9
-  const float s1 = (q & 1) ? cr : sr;
-  const float c1 = (q & 1) ? sr : cr;
-  const float s = (q & 2) ? -s1 : s1;
-  const float c = ((q + 1) & 2) ? -c1 : c1;
+  const int q = (int)kq;  // kq < 2^31 for z < 3e9
+  const float P = cr + sr, M = cr - sr;
+  const float a = (q & 1) ? M : P;
+  const float b = (q & 1) ? P : -M;
   const float zf = (float)z;
   const float y = dp_rsqrtf(zf);
   const float t = y * y;
   const float u = t * t;
   const float p0 = horner(kHankP032, u), p1 = horner(kHankP132, u);
   const float q0 = horner(kHankQ032, u) * t, q1 = horner(kHankQ132, u) * t;
-  const float m = (float)(kSqrt2OverPi * kInvSqrt2) * y;
-  const cplxf e0 = {(c + s) * m, (s - c) * m};
-  const cplxf e1 = {(s - c) * m, -(s + c) * m};
+  const float m0 = (float)(kSqrt2OverPi * kInvSqrt2) * scale * y;
+  const float m = (q & 2) ? -m0 : m0;
+  const cplxf e0 = {a * m, b * m};  // e1 = -i e0
   H01f h;
   h.h0 = {e0.re * p0 - e0.im * q0, e0.re * q0 + e0.im * p0};
-  h.h1 = {e1.re * p1 - e1.im * q1, e1.re * q1 + e1.im * p1};
+  h.h1 = {e0.im * p1 + e0.re * q1, e0.im * q1 - e0.re * p1};
   return h;
 }
 

@@ -19,13 +19,14 @@ __device__ __forceinline__ unsigned bitrev(unsigned v, int bits) { return __brev
 // In-LDS radix-2 DIT transform of `lines` lines of length Lf stored as
 // buf[e * lines + l] (element-major, so that loads over lines coalesce).
 // Input must be in bit-reversed element order.  dir = -1 forward, +1 inverse.
-__device__ void lds_fft(cplx* buf, int Lf, int lines, int logL, const cplx* tw, int ntw, int dir) {
+// Lf, lines and ntw are powers of two (loglines = log2 lines).
+__device__ void lds_fft(cplx* buf, int Lf, int lines, int loglines, const cplx* tw, int ntw, int dir) {
   for (int half = 1; half < Lf; half <<= 1) {
     const int nb = (Lf >> 1) * lines;
     const int stride = ntw / (2 * half);
     for (int t = threadIdx.x; t < nb; t += blockDim.x) {
-      const int l = t % lines;
-      const int b = t / lines;
+      const int l = t & (lines - 1);
+      const int b = t >> loglines;
       const int pos = b & (half - 1);
       const int i0 = ((b - pos) << 1) + pos;
       const int i1 = i0 + half;
@@ -38,7 +39,6 @@ __device__ void lds_fft(cplx* buf, int Lf, int lines, int logL, const cplx* tw, 
     }
     __syncthreads();
   }
-  (void)logL;
 }
 
 // Column pass: for each column b and each j2 in [0, n2): line over j1 (stride
@@ -49,23 +49,24 @@ __global__ void fft_col_pass(cplx* data, int n, int n1, int n2, int logn1, int l
   extern __shared__ cplx sbuf[];
   const int b = blockIdx.y;
   const int j2_0 = blockIdx.x * lines;
+  const int loglines = __builtin_ctz(lines);
   cplx* base = data + (size_t)b * n;
   for (int t = threadIdx.x; t < n1 * lines; t += blockDim.x) {
-    const int l = t % lines, j1 = t / lines;
+    const int l = t & (lines - 1), j1 = t >> loglines;
     cplx v = base[(size_t)n2 * j1 + j2_0 + l];
     if (twiddle && dir > 0) {  // inverse: pre-twiddle e^{+2 pi i j2 k1/n} (k1 = j1 here)
-      cplx w = tw[((size_t)(j2_0 + l) * j1) % n];
+      cplx w = tw[((j2_0 + l) * j1) & (n - 1)];
       w.im = -w.im;
       v = cmul(v, w);
     }
     sbuf[bitrev(j1, logn1) * lines + l] = v;
   }
   __syncthreads();
-  lds_fft(sbuf, n1, lines, logn1, tw, n, dir);
+  lds_fft(sbuf, n1, lines, loglines, tw, n, dir);
   for (int t = threadIdx.x; t < n1 * lines; t += blockDim.x) {
-    const int l = t % lines, k1 = t / lines;
+    const int l = t & (lines - 1), k1 = t >> loglines;
     cplx v = sbuf[k1 * lines + l];
-    if (twiddle && dir < 0) v = cmul(v, tw[((size_t)(j2_0 + l) * k1) % n]);
+    if (twiddle && dir < 0) v = cmul(v, tw[((j2_0 + l) * k1) & (n - 1)]);
     base[(size_t)n2 * k1 + j2_0 + l] = v;
   }
 }
@@ -78,13 +79,13 @@ __global__ void fft_row_pass(cplx* data, int n, int n2, int logn2, int lines, co
   const int k1_0 = blockIdx.x * lines;
   cplx* base = data + (size_t)b * n + (size_t)k1_0 * n2;
   for (int t = threadIdx.x; t < n2 * lines; t += blockDim.x) {
-    const int e = t % n2, l = t / n2;
+    const int e = t & (n2 - 1), l = t >> logn2;
     sbuf[bitrev(e, logn2) * lines + l] = base[(size_t)l * n2 + e];
   }
   __syncthreads();
-  lds_fft(sbuf, n2, lines, logn2, tw, n, dir);
+  lds_fft(sbuf, n2, lines, __builtin_ctz(lines), tw, n, dir);
   for (int t = threadIdx.x; t < n2 * lines; t += blockDim.x) {
-    const int e = t % n2, l = t / n2;
+    const int e = t & (n2 - 1), l = t >> logn2;
     base[(size_t)l * n2 + e] = sbuf[e * lines + l];
   }
 }
@@ -95,8 +96,8 @@ __global__ void deriv_scale(cplx* data, int n, int n1, int n2, int nb) {
   const size_t tot = (size_t)n * nb;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
        idx += (size_t)gridDim.x * blockDim.x) {
-    const int p = idx % n;
-    const int k1 = p / n2, k2 = p % n2;
+    const int p = (int)(idx & (size_t)(n - 1));  // n, n2 powers of two
+    const int k1 = p / n2, k2 = p & (n2 - 1);
     const int k = k1 + n1 * k2;
     const int m = (k < n / 2) ? k : ((k == n / 2) ? 0 : k - n);
     const cplx v = data[idx];
@@ -111,7 +112,7 @@ __global__ void copy_div_speed(const cplx* __restrict__ in, cplx* __restrict__ o
        idx += (size_t)gridDim.x * blockDim.x) {
     cplx v = in[idx];
     if (divide) {
-      const double s = 1.0 / src[idx % n].sp;
+      const double s = 1.0 / src[idx & (size_t)(n - 1)].sp;  // n a power of two
       v = {v.re * s, v.im * s};
     }
     out[idx] = v;

@@ -159,78 +159,6 @@ __global__ void toeplitz_aug(const cplx* __restrict__ row, cplx* A, int s) {
   }
 }
 
-// ------------------------------------------------------------------ Gauss-Jordan
-// Step k on the augmented row-major s x 2s matrix: choose the pivot row (max
-// modulus in column k among rows >= k), swap it into row k, scale row k by the
-// inverse pivot, and save the multipliers A[i][k] of every row.
-__global__ __launch_bounds__(256) void gj_pivot(cplx* A, int s, int k, cplx* mult, int* status) {
-  __shared__ double bv[256];
-  __shared__ int bi[256];
-  const int w = 2 * s;
-  double best = -1.0;
-  int bidx = k;
-  for (int i = k + threadIdx.x; i < s; i += 256) {
-    const cplx a = A[(size_t)i * w + k];
-    const double m = a.re * a.re + a.im * a.im;
-    if (m > best) {
-      best = m;
-      bidx = i;
-    }
-  }
-  bv[threadIdx.x] = best;
-  bi[threadIdx.x] = bidx;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      const double o = bv[threadIdx.x + st];
-      const int oi = bi[threadIdx.x + st];
-      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
-        bv[threadIdx.x] = o;
-        bi[threadIdx.x] = oi;
-      }
-    }
-    __syncthreads();
-  }
-  const int p = bi[0];
-  if (!(bv[0] > 0.0)) {
-    if (threadIdx.x == 0) status[0] = 1;
-    return;
-  }
-  if (p != k) {
-    for (int c = threadIdx.x; c < w; c += 256) {
-      const cplx t = A[(size_t)k * w + c];
-      A[(size_t)k * w + c] = A[(size_t)p * w + c];
-      A[(size_t)p * w + c] = t;
-    }
-  }
-  __syncthreads();
-  const cplx pv = A[(size_t)k * w + k];
-  const double den = pv.re * pv.re + pv.im * pv.im;
-  const cplx inv = {pv.re / den, -pv.im / den};
-  __syncthreads();
-  for (int c = threadIdx.x; c < w; c += 256) A[(size_t)k * w + c] = cmul(A[(size_t)k * w + c], inv);
-  for (int i = threadIdx.x; i < s; i += 256) mult[i] = (i == k) ? cplx{0.0, 0.0} : A[(size_t)i * w + k];
-}
-
-// Row i -= mult[i] * row k (all rows but k, columns k..2s-1).
-__global__ void gj_update(cplx* A, int s, int k, const cplx* __restrict__ mult, const int* __restrict__ status) {
-  if (status[0]) return;
-  const int w = 2 * s;
-  const int cols = w - k;
-  const size_t tot = (size_t)s * cols;
-  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int i = idx / cols;
-    const int c = k + (int)(idx % cols);
-    if (i == k) continue;
-    const cplx m = mult[i];
-    const cplx a = A[(size_t)k * w + c];
-    cplx& t = A[(size_t)i * w + c];
-    t.re -= m.re * a.re - m.im * a.im;
-    t.im -= m.re * a.im + m.im * a.re;
-  }
-}
-
 __global__ void copy_right_half(const cplx* __restrict__ A, cplx* out, int s) {
   const size_t tot = (size_t)s * s;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
@@ -240,29 +168,147 @@ __global__ void copy_right_half(const cplx* __restrict__ A, cplx* out, int s) {
   }
 }
 
-// inverse of a row-major s x s matrix (given in the left half of Aug)
-static int gj_inverse(hipStream_t st, DevBuf& aug, int s, cplx* out, DevBuf& scratch) {
-  DP_TRY(scratch.reserve(s * sizeof(cplx) + 64));
-  cplx* mult = scratch.as<cplx>();
-  int* status = reinterpret_cast<int*>(mult + s);
-  DP_HIP(hipMemsetAsync(status, 0, sizeof(int), st));
-  cplx* A = aug.as<cplx>();
-  for (int k = 0; k < s; ++k) {
-    gj_pivot<<<1, 256, 0, st>>>(A, s, k, mult, status);
-    gj_update<<<grid1((size_t)s * (2 * s - k)), 256, 0, st>>>(A, s, k, mult, status);
+// ------------------------------------------------------------ batched Gauss-Jordan
+// Several augmented row-major s x 2s matrices [M | I] inverted together, one
+// launch per elimination step k for all of them.  Step k reads buffer k % 2
+// and writes buffer (k + 1) % 2, so no block sees another's partial update:
+// the pivot row p (largest |A[i][k]| over rows i >= k, lowest index on ties,
+// found by every block alike) becomes row k scaled by 1/A[p][k], the old row
+// k moves to row p, and every other row loses its column-k multiple of the
+// new row k.  Column k itself is not written (no later step reads it); the
+// new column k + 1 is also kept contiguously for the next pivot search and
+// multipliers.  After s steps the right half of buffer s % 2 is M^{-1}.  A zero pivot column sets
+// status[matrix].
+struct GJMat {
+  cplx* a[2];
+  cplx* col[2];  // contiguous copies of the pivot column of buffer k % 2 (column k)
+  int s;
+};
+struct GJBatch {
+  GJMat m[8];
+  int* status;
+};
+
+__global__ __launch_bounds__(256) void gj_step(GJBatch b, int k) {
+  const GJMat M = b.m[blockIdx.y];
+  const int s = M.s;
+  const int i = blockIdx.x;  // this block's row
+  if (k >= s || i >= s) return;
+  const int w = 2 * s;
+  const cplx* A = M.a[k & 1];
+  cplx* O = M.a[(k + 1) & 1];
+  const cplx* colk = M.col[k & 1];
+  cplx* coln = M.col[(k + 1) & 1];
+  // pivot: wave-level argmax (ties to the lower row), then across the 4 waves
+  __shared__ double bv[4];
+  __shared__ int bi[4];
+  double best = -1.0;
+  int bidx = s;
+  for (int i = k + threadIdx.x; i < s; i += 256) {
+    const cplx a = colk[i];
+    const double m = a.re * a.re + a.im * a.im;
+    if (m > best) {
+      best = m;
+      bidx = i;
+    }
   }
-  copy_right_half<<<grid1((size_t)s * s), 256, 0, st>>>(A, out, s);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(best, off);
+    const int oi = __shfl_xor(bidx, off);
+    if (o > best || (o == best && oi < bidx)) {
+      best = o;
+      bidx = oi;
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    bv[threadIdx.x >> 6] = best;
+    bi[threadIdx.x >> 6] = bidx;
+  }
+  __syncthreads();
+  best = bv[0];
+  int p = bi[0];
+#pragma unroll
+  for (int q = 1; q < 4; ++q)
+    if (bv[q] > best || (bv[q] == best && bi[q] < p)) {
+      best = bv[q];
+      p = bi[q];
+    }
+  if (!(best > 0.0)) {
+    if (i == 0 && threadIdx.x == 0) b.status[blockIdx.y] = 1;
+    return;
+  }
+  const cplx pv = colk[p];
+  const double den = pv.re * pv.re + pv.im * pv.im;
+  const cplx inv = {pv.re / den, -pv.im / den};
+  // row i, columns k + 1 .. 2s - 1, four per thread in flight
+  const int src = (i == p) ? k : i;
+  const cplx m = colk[src];
+  const cplx* prow = A + (size_t)p * w;
+  const cplx* srow = A + (size_t)src * w;
+  cplx* orow = O + (size_t)i * w;
+  for (int c0 = k + 1 + threadIdx.x; c0 < w; c0 += 1024) {
+    cplx pa[4], sa[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = min(c0 + 256 * u, w - 1);
+      pa[u] = prow[c];
+      sa[u] = srow[c];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + 256 * u;
+      if (c < w) {
+        const cplx pr = cmul(pa[u], inv);
+        cplx v = pr;
+        if (i != k)
+          v = {sa[u].re - (m.re * pr.re - m.im * pr.im), sa[u].im - (m.re * pr.im + m.im * pr.re)};
+        orow[c] = v;
+        if (c == k + 1) coln[i] = v;
+      }
+    }
+  }
+}
+
+// col[i] = A[i][0] of a row-major matrix with w columns
+__global__ void copy_column(const cplx* __restrict__ A, cplx* col, int rows, int w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < rows) col[i] = A[(size_t)i * w];
+}
+
+// [S | I] from a row-major K x K matrix S
+__global__ void augment_identity(const cplx* __restrict__ S, cplx* A, int K) {
+  const size_t tot = (size_t)K * 2 * K;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int r = idx / (2 * K), c = idx % (2 * K);
+    A[idx] = c < K ? S[(size_t)r * K + c] : cplx{(c - K == r) ? 1.0 : 0.0, 0.0};
+  }
+}
+
+// Inverts the batch (at most 8 matrices): one launch per step of the largest.
+static int gj_batch(hipStream_t st, GJBatch& b, int count, DevBuf& status) {
+  DP_TRY(status.reserve(8 * sizeof(int)));
+  b.status = status.as<int>();
+  DP_HIP(hipMemsetAsync(b.status, 0, 8 * sizeof(int), st));
+  int smax = 0;
+  for (int q = 0; q < count; ++q) smax = std::max(smax, b.m[q].s);
+  for (int q = 0; q < count; ++q)  // pivot column of step 0
+    copy_column<<<(b.m[q].s + 255) / 256, 256, 0, st>>>(b.m[q].a[0], b.m[q].col[0], b.m[q].s, 2 * b.m[q].s);
+  for (int k = 0; k < smax; ++k) gj_step<<<dim3(smax, count), 256, 0, st>>>(b, k);
   DP_HIP(hipGetLastError());
-  int h = 0;
-  DP_HIP(hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, st));
+  int h[8] = {0};
+  DP_HIP(hipMemcpyAsync(h, b.status, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
   DP_HIP(hipStreamSynchronize(st));
-  if (h) {
-    set_error("singular dense block in the preconditioner setup (size %d)", s);
-    return DP_ESINGULAR;
-  }
+  for (int q = 0; q < count; ++q)
+    if (h[q]) {
+      set_error("singular dense block in the preconditioner setup (size %d)", b.m[q].s);
+      return DP_ESINGULAR;
+    }
   return DP_OK;
 }
 
+// inverse of a row-major s x s matrix (given in the left half of Aug)
 // ------------------------------------------------------------------ dense products
 // C (M x N) = A (M x Kd) * B (Kd x N), all row-major (setup products).
 __global__ void dense_gemm(const cplx* __restrict__ A, const cplx* __restrict__ B, cplx* C, int M, int N, int Kd) {
@@ -297,22 +343,32 @@ __global__ void partial_fourier(cplx* U, cplx* Ut, int s, int J) {
 
 // alpha_s(b) = (1/s) sum_a l_b(xi_a), xi_a = (a - (s-1)/2)/(s/2), Lagrange basis
 // on first-kind Chebyshev points x_b = cos((2b+1) pi/(2 m_c)).
-__global__ void lagrange_mean(double* alpha, int s, int mc) {
-  const int b = threadIdx.x;
-  if (b >= mc) return;
-  const double xb = cospi((2.0 * b + 1.0) / (2.0 * mc));
+// One block per basis function b (256 threads over the s points).
+__global__ __launch_bounds__(256) void lagrange_mean(double* alpha, int s, int mc) {
+  __shared__ double xs[64];
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  if (threadIdx.x < mc) xs[threadIdx.x] = cospi((2.0 * threadIdx.x + 1.0) / (2.0 * mc));
+  __syncthreads();
+  const double xb = xs[b];
   double acc = 0.0;
-  for (int a = 0; a < s; ++a) {
+  for (int a = threadIdx.x; a < s; a += 256) {
     const double xa = (a - 0.5 * (s - 1)) / (0.5 * s);
-    double l = 1.0;
+    double num = 1.0, den = 1.0;
     for (int c = 0; c < mc; ++c) {
       if (c == b) continue;
-      const double xc = cospi((2.0 * c + 1.0) / (2.0 * mc));
-      l *= (xa - xc) / (xb - xc);
+      num *= xa - xs[c];
+      den *= xb - xs[c];
     }
-    acc += l;
+    acc += num / den;
   }
-  alpha[b] = acc / s;
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) alpha[b] = red[0] / s;
 }
 
 // ------------------------------------------------------------------ geometry
@@ -704,6 +760,8 @@ static int build_slots(const SparseLU& lu, std::vector<Slot<C>>& out) {
   using R = decltype(C{}.re);
   const int NW = lu.n;
   out.clear();
+  out.reserve((size_t)(lu.Lx.size() + lu.Ux.size() + 2 * NW) / 8 * 64);
+  std::vector<std::pair<int, std::complex<double>>> ent;
   int steps = 0;
   for (int pass = 0; pass < 2; ++pass) {
     const std::vector<int>& lptr = pass ? lu.lvlU_ptr : lu.lvlL_ptr;
@@ -748,7 +806,7 @@ static int build_slots(const SparseLU& lu, std::vector<Slot<C>>& out) {
         int st = 0;
         for (int r : best_grp[g]) {
           const std::complex<double> d = pass ? 1.0 / lu.Ud[r] : std::complex<double>(1.0, 0.0);
-          std::vector<std::pair<int, std::complex<double>>> ent;
+          ent.clear();
           ent.push_back({r, d});
           for (int q = Pp[r]; q < Pp[r + 1]; ++q) ent.push_back({Jj[q], -d * Vv[q]});
           const int rs = ((int)ent.size() + W - 1) / W;
@@ -864,48 +922,88 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
   P->NW = P->offK[m];
   const int mc = o->m_c;
 
-  // ---- size classes: B^{-1}, U, S, T, floor(T), alpha
-  DevBuf row, aug, scratch, X, S;
-  std::vector<double> alpha_all;
+  // ---- size classes: B^{-1}, U, S, T, floor(T), alpha (batched over classes)
+  const int ncls = (int)P->classes.size();
+  if (ncls > 8) {
+    set_error("dp_precond_build: more than 8 segment size classes");
+    return fail(DP_EINVAL);
+  }
+  std::vector<DevBuf> augB(2 * ncls), augS(2 * ncls), colB(2 * ncls), colS(2 * ncls);
+  DevBuf row, X, S, gstat;
   DevBuf d_alpha;
-  DP_TRY(d_alpha.reserve(P->classes.size() * mc * sizeof(double)));
-  for (size_t ci = 0; ci < P->classes.size(); ++ci) {
+  struct Release {  // the setup's own buffers, on every return path
+    std::vector<DevBuf*> bufs;
+    std::vector<DevBuf>* vecs[4];
+    ~Release() {
+      for (DevBuf* q : bufs) q->release();
+      for (auto* v : vecs)
+        for (DevBuf& q : *v) q.release();
+    }
+  } release_locals{{&row, &X, &S, &gstat, &d_alpha}, {&augB, &augS, &colB, &colS}};
+  DP_TRY(d_alpha.reserve(ncls * mc * sizeof(double)));
+  GJBatch gb{};
+  for (int ci = 0; ci < ncls; ++ci) {
     SizeClass& c = P->classes[ci];
     const int s = c.s, K = c.K;
     int rc;
-    if ((rc = row.reserve(s * sizeof(cplx))) || (rc = aug.reserve((size_t)s * 2 * s * sizeof(cplx))) ||
+    if ((rc = row.reserve(s * sizeof(cplx))) || (rc = augB[2 * ci].reserve((size_t)s * 2 * s * sizeof(cplx))) ||
+        (rc = augB[2 * ci + 1].reserve((size_t)s * 2 * s * sizeof(cplx))) ||
+        (rc = colB[2 * ci].reserve((size_t)s * sizeof(cplx))) || (rc = colB[2 * ci + 1].reserve((size_t)s * sizeof(cplx))) ||
         (rc = c.Binv.reserve((size_t)s * s * sizeof(cplx))) || (rc = c.U.reserve((size_t)s * K * sizeof(cplx))) ||
-        (rc = c.Ut.reserve((size_t)s * K * sizeof(cplx))) || (rc = c.Tt.reserve((size_t)K * K * sizeof(cplx))) ||
-        (rc = X.reserve((size_t)s * K * sizeof(cplx))) || (rc = S.reserve((size_t)K * 2 * K * sizeof(cplx))))
+        (rc = c.Ut.reserve((size_t)s * K * sizeof(cplx))) || (rc = c.Tt.reserve((size_t)K * K * sizeof(cplx))))
       return fail(rc);
     flat_row<<<(s + 255) / 256, 256, 0, st>>>(p->C.as<double>(), row.as<cplx>(), s, n, L, omega, p->eta, p->kind);
-    toeplitz_aug<<<grid1((size_t)s * 2 * s), 256, 0, st>>>(row.as<cplx>(), aug.as<cplx>(), s);
-    if ((rc = gj_inverse(st, aug, s, c.Binv.as<cplx>(), scratch))) return fail(rc);
+    toeplitz_aug<<<grid1((size_t)s * 2 * s), 256, 0, st>>>(row.as<cplx>(), augB[2 * ci].as<cplx>(), s);
+    gb.m[ci] = GJMat{{augB[2 * ci].as<cplx>(), augB[2 * ci + 1].as<cplx>()},
+                     {colB[2 * ci].as<cplx>(), colB[2 * ci + 1].as<cplx>()}, s};
+    // the next class's flat row must not overwrite this one before it is read
+    DP_HIP(hipStreamSynchronize(st));
+  }
+  {
+    int rc;
+    if ((rc = gj_batch(st, gb, ncls, gstat))) return fail(rc);
+  }
+  GJBatch gs{};
+  for (int ci = 0; ci < ncls; ++ci) {
+    SizeClass& c = P->classes[ci];
+    const int s = c.s, K = c.K;
+    copy_right_half<<<grid1((size_t)s * s), 256, 0, st>>>(augB[2 * ci + (s & 1)].as<cplx>(), c.Binv.as<cplx>(), s);
+    augB[2 * ci].release();
+    augB[2 * ci + 1].release();
+    int rc;
+    if ((rc = X.reserve((size_t)s * K * sizeof(cplx))) || (rc = S.reserve((size_t)K * K * sizeof(cplx))) ||
+        (rc = augS[2 * ci].reserve((size_t)K * 2 * K * sizeof(cplx))) ||
+        (rc = augS[2 * ci + 1].reserve((size_t)K * 2 * K * sizeof(cplx))) ||
+        (rc = colS[2 * ci].reserve((size_t)K * sizeof(cplx))) || (rc = colS[2 * ci + 1].reserve((size_t)K * sizeof(cplx))))
+      return fail(rc);
     partial_fourier<<<grid1((size_t)s * K), 256, 0, st>>>(c.U.as<cplx>(), c.Ut.as<cplx>(), s, c.J);
     dense_gemm<<<grid1((size_t)s * K), 256, 0, st>>>(c.Binv.as<cplx>(), c.U.as<cplx>(), X.as<cplx>(), s, K, s);
-    // S = U^t X, written as the left half of an augmented K x 2K matrix
-    dense_gemm<<<grid1((size_t)K * K), 256, 0, st>>>(c.Ut.as<cplx>(), X.as<cplx>(), c.Tt.as<cplx>(), K, K, s);
-    {
-      // build [S | I]
-      std::vector<cplx> Sh((size_t)K * K);
-      DP_HIP(hipMemcpyAsync(Sh.data(), c.Tt.p, Sh.size() * sizeof(cplx), hipMemcpyDeviceToHost, st));
-      DP_HIP(hipStreamSynchronize(st));
-      std::vector<cplx> Ah((size_t)K * 2 * K, cplx{0.0, 0.0});
-      for (int r = 0; r < K; ++r) {
-        for (int q = 0; q < K; ++q) Ah[(size_t)r * 2 * K + q] = Sh[(size_t)r * K + q];
-        Ah[(size_t)r * 2 * K + K + r] = {1.0, 0.0};
-      }
-      DP_HIP(hipMemcpyAsync(S.p, Ah.data(), Ah.size() * sizeof(cplx), hipMemcpyHostToDevice, st));
-      DP_HIP(hipStreamSynchronize(st));
-    }
-    if ((rc = gj_inverse(st, S, K, c.Tt.as<cplx>(), scratch))) return fail(rc);
+    // S = U^t X, then [S | I]
+    dense_gemm<<<grid1((size_t)K * K), 256, 0, st>>>(c.Ut.as<cplx>(), X.as<cplx>(), S.as<cplx>(), K, K, s);
+    augment_identity<<<grid1((size_t)K * 2 * K), 256, 0, st>>>(S.as<cplx>(), augS[2 * ci].as<cplx>(), K);
+    gs.m[ci] = GJMat{{augS[2 * ci].as<cplx>(), augS[2 * ci + 1].as<cplx>()},
+                     {colS[2 * ci].as<cplx>(), colS[2 * ci + 1].as<cplx>()}, K};
+    // X and S are reused by the next class
+    DP_HIP(hipStreamSynchronize(st));
+  }
+  {
+    int rc;
+    if ((rc = gj_batch(st, gs, ncls, gstat))) return fail(rc);
+  }
+  for (int ci = 0; ci < ncls; ++ci) {
+    SizeClass& c = P->classes[ci];
+    const int s = c.s, K = c.K;
+    copy_right_half<<<grid1((size_t)K * K), 256, 0, st>>>(augS[2 * ci + (K & 1)].as<cplx>(), c.Tt.as<cplx>(), K);
     c.T.resize((size_t)K * K);
     DP_HIP(hipMemcpyAsync(c.T.data(), c.Tt.p, c.T.size() * sizeof(cplx), hipMemcpyDeviceToHost, st));
     DP_HIP(hipStreamSynchronize(st));
+    augS[2 * ci].release();
+    augS[2 * ci + 1].release();
     std::vector<cplx> Tt;
     threshold_T(c.T, K, o->t_keep, Tt);
     DP_HIP(hipMemcpyAsync(c.Tt.p, Tt.data(), Tt.size() * sizeof(cplx), hipMemcpyHostToDevice, st));
-    lagrange_mean<<<1, 64, 0, st>>>(d_alpha.as<double>() + ci * mc, s, mc);
+    DP_HIP(hipStreamSynchronize(st));
+    lagrange_mean<<<mc, 256, 0, st>>>(d_alpha.as<double>() + ci * mc, s, mc);
   }
   DP_HIP(hipGetLastError());
 
@@ -1049,9 +1147,9 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     P->nlevU = (int)lu.lvlU_ptr.size() - 1;
     {
       std::vector<Slot<cplx>> sl;
-      std::vector<Slot<cplxf>> sl32;
       P->nsteps = build_slots(lu, sl);
-      (void)build_slots(lu, sl32);
+      std::vector<Slot<cplxf>> sl32(sl.size());
+      for (size_t q = 0; q < sl.size(); ++q) sl32[q] = {sl[q].col, sl[q].row, (float)sl[q].re, (float)sl[q].im};
       if ((rc = upload(P->slots, sl, st)) || (rc = upload(P->slots32, sl32, st))) return fail(rc);
       int maxlds = 0;
       DP_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->ctx->device));
@@ -1108,8 +1206,7 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
   }
   DP_HIP(hipStreamSynchronize(st));
   row.release();
-  aug.release();
-  scratch.release();
+  gstat.release();
   X.release();
   S.release();
   d_alpha.release();

@@ -44,8 +44,8 @@ __global__ __launch_bounds__(256) void sweep_private(SweepParams p) {
   const int ii = i < n ? i : n - 1;
   const SrcRec tr = p.src[ii];
   const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
-  const float tnx = (float)tr.nx, tny = (float)tr.ny;
   const Far32 f = far32_consts(p.omega, p.eta, p.r2near, 1.0f, 1.0f);
+  const Tgt32 tf = tgt32<OP>(tr.nx, tr.ny, f);
   const int j0 = blockIdx.y * p.chunk_len;
   const int j1 = min(n, j0 + p.chunk_len);
   cplx acc[ND][NR];
@@ -323,8 +323,8 @@ __global__ __launch_bounds__(256) void sweep_private32(SweepParams p) {
   const int ii = i < n ? i : n - 1;
   const SrcRec tr = p.src[ii];
   const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
-  const float tnx = (float)tr.nx, tny = (float)tr.ny;
   const Far32 f = far32_consts(p.omega, p.eta, p.r2near, 1.0f, 1.0f);
+  const Tgt32 tf = tgt32<OP>(tr.nx, tr.ny, f);
   const int j0 = blockIdx.y * p.chunk_len;
   const int j1 = min(n, j0 + p.chunk_len);
   cplx acc[ND][NR];
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(256) void sweep_private32(SweepParams p) {
   for (int j = j0; j < j1; ++j) {
     const SrcRec s = p.src[j];
     cplxf K[ND];
-    pair_kernel_far32<OP>(t, tnx, tny, s, (float)p.C[k], ii == j, f, K);
+    pair_kernel_far32<OP>(t, tf, s, (float)p.C[k], ii == j, f, K);
     const cplx* dj = p.dens + (size_t)j * ND * NR;
 #pragma unroll
     for (int d = 0; d < ND; ++d)
@@ -432,8 +432,8 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
   const int ii = i < n ? i : n - 1;
   const SrcRec tr = p.src[ii];
   const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
-  const float tnx = (float)tr.nx, tny = (float)tr.ny;
   const Far32 f = far32_consts(p.omega, p.eta, p.r2near, p.ksc[0], p.ksc[1]);
+  const Tgt32 tf = tgt32<OP>(tr.nx, tr.ny, f);
   const int j0 = blockIdx.y * p.chunk_len;  // multiple of 32
   const int j1 = min(n, j0 + p.chunk_len);
   const int nsteps = (j1 - j0 + 31) / 32;
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
       for (int h = 0; h < 2; ++h) {
         const int jj = 8 * lk + 2 * e2 + h;
         const int j = jb + jj;
-        pair_kernel_far32<OP>(t, tnx, tny, ss[jj], Cs[31 + ti - jj], ii == j || j >= j1, f, K[h]);
+        pair_kernel_far32<OP>(t, tf, ss[jj], Cs[31 + ti - jj], ii == j || j >= j1, f, K[h]);
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
@@ -496,28 +496,39 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
         nih[e] = aih[d][e] ^ 0x80008000u;
         nil[e] = ail[d][e] ^ 0x80008000u;
       }
+      // two column blocks at a time: four independent accumulation chains
+      constexpr int CP = NCB >= 2 ? 2 : 1;
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        const int row = d * 4 * NC + cb * 16 + li;
-        const uint4 brh = Bt[row * 4 + gsw];
-        const uint4 brl = Bt[(row + NC) * 4 + gsw];
-        const uint4 bih = Bt[(row + 2 * NC) * 4 + gsw];
-        const uint4 bil = Bt[(row + 3 * NC) * 4 + gsw];
-        flt4 r = Re[d][cb], m = Im[d][cb];
-        r = mma16(arh[d], brh, r);
-        m = mma16(arh[d], bih, m);
-        r = mma16(arh[d], brl, r);
-        m = mma16(arh[d], bil, m);
-        r = mma16(arl[d], brh, r);
-        m = mma16(arl[d], bih, m);
-        r = mma16(nih, bih, r);
-        m = mma16(aih[d], brh, m);
-        r = mma16(nih, bil, r);
-        m = mma16(aih[d], brl, m);
-        r = mma16(nil, bih, r);
-        m = mma16(ail[d], brh, m);
-        Re[d][cb] = r;
-        Im[d][cb] = m;
+      for (int cb0 = 0; cb0 < NCB; cb0 += CP) {
+        uint4 brh[CP], brl[CP], bih[CP], bil[CP];
+        flt4 r[CP], m[CP];
+#pragma unroll
+        for (int u = 0; u < CP; ++u) {
+          const int row = d * 4 * NC + (cb0 + u) * 16 + li;
+          brh[u] = Bt[row * 4 + gsw];
+          brl[u] = Bt[(row + NC) * 4 + gsw];
+          bih[u] = Bt[(row + 2 * NC) * 4 + gsw];
+          bil[u] = Bt[(row + 3 * NC) * 4 + gsw];
+          r[u] = Re[d][cb0 + u];
+          m[u] = Im[d][cb0 + u];
+        }
+#define DP_MMA2(AR, BR, AI, BI)                  \
+  _Pragma("unroll") for (int u = 0; u < CP; ++u) { \
+    r[u] = mma16(AR, BR[u], r[u]);               \
+    m[u] = mma16(AI, BI[u], m[u]);               \
+  }
+        DP_MMA2(arh[d], brh, arh[d], bih)
+        DP_MMA2(arh[d], brl, arh[d], bil)
+        DP_MMA2(arl[d], brh, arl[d], bih)
+        DP_MMA2(nih, bih, aih[d], brh)
+        DP_MMA2(nih, bil, aih[d], brl)
+        DP_MMA2(nil, bih, ail[d], brh)
+#undef DP_MMA2
+#pragma unroll
+        for (int u = 0; u < CP; ++u) {
+          Re[d][cb0 + u] = r[u];
+          Im[d][cb0 + u] = m[u];
+        }
       }
     }
     // the next step's loads are complete and this step's reads are done

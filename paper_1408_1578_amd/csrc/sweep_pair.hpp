@@ -105,15 +105,16 @@ struct Nd32 {
   static constexpr int v = Nd<OP>::v;
 };
 
-// Per-launch constants of the FP32 kernel values, with power-of-two output
-// scales sc[d] (1 when unscaled) folded in.
+// Per-launch constants of the FP32 kernel values.  Output scales sc[d] are
+// powers of two (1 when unscaled): sc0 multiplies the Hankel values, and the
+// hard operator's second density takes the ratio sc1/sc0 in its factors.
 struct Far32 {
   double omega, r2near;
-  float sc0;      // scale of density 0
-  float om_sc0;   // omega sc0
-  float om_sc1;   // omega sc1
-  float eta_sc0;  // eta sc0 (soft)
-  float g_sc1;    // (omega^2/eta) sc1 (hard)
+  float sc0;   // scale of density 0 (applied to H0, H1)
+  float om;    // omega
+  float eta;   // eta
+  float om_r;  // omega sc1/sc0 (hard)
+  float g_r;   // (omega^2/eta) sc1/sc0 (hard)
 };
 
 __host__ __device__ inline Far32 far32_consts(double omega, double eta, double r2near, float sc0, float sc1) {
@@ -121,11 +122,24 @@ __host__ __device__ inline Far32 far32_consts(double omega, double eta, double r
   f.omega = omega;
   f.r2near = r2near;
   f.sc0 = sc0;
-  f.om_sc0 = (float)(omega * sc0);
-  f.om_sc1 = (float)(omega * sc1);
-  f.eta_sc0 = (float)(eta * sc0);
-  f.g_sc1 = (float)(omega * omega / eta * sc1);
+  f.om = (float)omega;
+  f.eta = (float)eta;
+  f.om_r = (float)(omega * (double)sc1 / (double)sc0);
+  f.g_r = (float)(omega * omega / eta * (double)sc1 / (double)sc0);
   return f;
+}
+
+// Target factors of the FP32 kernel values, once per target: its normal
+// times the D'-type factor (omega, or omega sc1/sc0 for the hard operator)
+// and times (omega^2/eta) sc1/sc0 (hard).
+struct Tgt32 {
+  float nxo, nyo, nxg, nyg;
+};
+
+template <int OP>
+__host__ __device__ inline Tgt32 tgt32(double nx, double ny, const Far32& f) {
+  const float o = OP == OP_HARD ? f.om_r : f.om;
+  return Tgt32{(float)nx * o, (float)ny * o, (float)nx * f.g_r, (float)ny * f.g_r};
 }
 
 // Far-field pair with FP32 kernel values.  r comes from the FP32 reciprocal
@@ -139,7 +153,7 @@ __host__ __device__ inline Far32 far32_consts(double omega, double eta, double r
 // zero set (self, near field, outside the caller's range) get wf = cq = 0
 // and hence K = 0; their distance is replaced by 1 so every value is finite.
 template <int OP>
-__device__ __forceinline__ void pair_kernel_far32(const Tgt& t, float tnx, float tny, const SrcRec& s, float Ck,
+__device__ __forceinline__ void pair_kernel_far32(const Tgt& t, const Tgt32& tf, const SrcRec& s, float Ck,
                                                   bool zero, const Far32& f, cplxf* K) {
   const double dx = t.x - s.x, dy = t.y - s.y;
   double r2 = pair_r2(t.x, t.y, s.x, s.y);
@@ -149,29 +163,29 @@ __device__ __forceinline__ void pair_kernel_far32(const Tgt& t, float tnx, float
   const double yd = (double)y0;
   const double r0 = r2 * yd;
   const double r = fma(0.5 * yd, fma(-r0, r0, r2), r0);
-  const H01f h = hankel01_far32(fmax(f.omega * r, DP_HANKEL_ZA));
+  const H01f h = hankel01_far32(fmax(f.omega * r, DP_HANKEL_ZA), f.sc0);
   const float dxf = (float)dx, dyf = (float)dy;
   const float wq = zero ? 0.0f : s.wf;
   const float cq = zero ? 0.0f : Ck * s.spf;
   const float A0 = fmaf(wq, h.h0.im, cq * h.h0.re);
   const float Sr = wq * h.h0.re;
   if constexpr (OP == OP_S) {
-    K[0] = {-f.sc0 * A0, f.sc0 * Sr};
+    K[0] = {-A0, Sr};
     return;
   }
   const float B1 = fmaf(wq, h.h1.im, cq * h.h1.re);
   const float T1 = wq * h.h1.re;
   if constexpr (OP == OP_SOFT || OP == OP_D) {
-    const float on = fmaf(s.nxf, dxf, s.nyf * dyf) * y0 * f.om_sc0;  // omega nu_j.rhat sc0
-    if constexpr (OP == OP_SOFT) K[0] = {fmaf(f.eta_sc0, Sr, -on * B1), fmaf(f.eta_sc0, A0, on * T1)};
+    const float on = fmaf(s.nxf, dxf, s.nyf * dyf) * (y0 * f.om);  // omega nu_j.rhat
+    if constexpr (OP == OP_SOFT) K[0] = {fmaf(f.eta, Sr, -on * B1), fmaf(f.eta, A0, on * T1)};
     else K[0] = {-on * B1, on * T1};
   } else if constexpr (OP == OP_DP) {
-    const float on = fmaf(tnx, dxf, tny * dyf) * y0 * f.om_sc0;      // omega nu_i.rhat sc0
+    const float on = fmaf(tf.nxo, dxf, tf.nyo * dyf) * y0;           // omega nu_i.rhat
     K[0] = {on * B1, -on * T1};
   } else {  // OP_HARD: S and G = -i (omega^2/eta)(nu_i.nu_j) S - D'
-    const float on = fmaf(tnx, dxf, tny * dyf) * y0 * f.om_sc1;
-    const float g = fmaf(tnx, s.nxf, tny * s.nyf) * f.g_sc1;
-    K[0] = {-f.sc0 * A0, f.sc0 * Sr};
+    const float on = fmaf(tf.nxo, dxf, tf.nyo * dyf) * y0;           // omega nu_i.rhat sc1/sc0
+    const float g = fmaf(tf.nxg, s.nxf, tf.nyg * s.nyf);              // (omega^2/eta) nu_i.nu_j sc1/sc0
+    K[0] = {-A0, Sr};
     K[1] = {fmaf(g, Sr, -on * B1), fmaf(g, A0, on * T1)};
   }
 }
