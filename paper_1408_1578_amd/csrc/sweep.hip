@@ -401,10 +401,12 @@ __device__ __forceinline__ flt4 mma16(const uint32_t (&a)[4], const uint4& b, fl
 // Density tiles: for each block of 32 sources b, density d, part
 // (re hi, re lo, im hi, im lo) and column c, the 32 halves of the block's
 // sources, i.e. uint4 index (((b * nd + d) * 4 + part) * nrp + c) * 4 + g for
-// sources 32 b + 8 g .. + 7.  Sources past n and columns past nrhs are zero.
+// the 8 sources 32 b + 4 e + g, e = 0..7 (the contraction index 8 g + e
+// stands for source 4 e + g).  Sources past n and columns past nrhs are zero.
 // Block: 8 waves, each 16 targets x all nrp columns; per 32-source step
-// every lane evaluates 8 pairs (target lane % 16, sources 8 (lane / 16) + e),
-// which is exactly its A fragment.  The step's density tile, its 32 source
+// every lane evaluates 8 pairs (target lane % 16, sources 4 e + lane / 16),
+// which is exactly its A fragment; the four lane groups then read adjacent
+// source records, on distinct LDS banks.  The step's density tile, its 32 source
 // records and the C_k window of the block (FP32 copy of the table) reach LDS
 // by direct global-to-LDS loads issued one step ahead into the other of two
 // buffers; the steps alternate between two separate sets of LDS arrays so
@@ -478,7 +480,7 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
       cplxf K[2][ND];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int jj = 8 * lk + 2 * e2 + h;
+        const int jj = 4 * (2 * e2 + h) + lk;  // k-index 8 lk + e holds source 4 e + lk
         const int j = jb + jj;
         pair_kernel_far32<OP>(t, tf, ss[jj], Cs[31 + ti - jj], ii == j || j >= j1, f, K[h]);
       }
@@ -594,8 +596,8 @@ __global__ __launch_bounds__(256) void dens16_scales(const cplx* __restrict__ a,
   }
 }
 
-// Split-FP16 density tiles (layout in sweep_mfma16); one thread per 8
-// sources of one (block, density, column).
+// Split-FP16 density tiles (layout in sweep_mfma16); one thread per chunk
+// (8 sources) of one (block, density, column).
 __global__ void pack_dens16(const cplx* __restrict__ a, const cplx* __restrict__ b,
                             const double* __restrict__ bscale, uint4* __restrict__ out, int n, int nrhs,
                             int nrp, int nd, int col0, int nb) {
@@ -614,7 +616,7 @@ __global__ void pack_dens16(const cplx* __restrict__ a, const cplx* __restrict__
       float v[2][2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const size_t j = bi * 32 + 8 * g + 2 * e2 + h;
+        const size_t j = bi * 32 + 4 * (2 * e2 + h) + g;
         const cplx x = (c < nrhs && j < (size_t)n) ? src[j] : cplx{0.0, 0.0};
         v[h][0] = (float)(x.re * sc);
         v[h][1] = (float)(x.im * sc);
