@@ -598,6 +598,94 @@ __global__ __launch_bounds__(256) void seg_gemm(SegGemm<C> g) {
   }
 }
 
+// FP32 batched per-segment complex GEMM on the matrix cores
+// (v_mfma_f32_16x16x4f32, A[i][k] in lane i + 16k, B[k][c] in lane c + 16k,
+// D[i][c] in register r of lane c + 16 (i / 4), i = 4 (lane / 16) + r).
+// Grid (segment, row tile of 64, column tile of 64); 4 waves, each 16 rows x
+// 64 columns; the 64 x 16 A tile and the 16 x 64 X tile of each 16-deep
+// slice go through LDS.  Complex products take 4 real ones:
+// Re += Ar Xr + (-Ai) Xi, Im += Ar Xi + Ai Xr.
+typedef float flt4v __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void seg_gemm_mfma32(SegGemm<cplxf> g) {
+  __shared__ cplxf As[64][17];
+  __shared__ cplxf Xs[16][65];
+  const int sg = blockIdx.x;
+  const int off = g.segs[4 * sg], offK = g.segs[4 * sg + 2], cls = g.segs[4 * sg + 3];
+  const int s = g.dims[2 * cls], K = g.dims[2 * cls + 1];
+  const int M = g.mrows ? K : s;
+  const int Kd = g.kin ? K : s;
+  const int r0 = blockIdx.y * 64;
+  if (r0 >= M) return;
+  const int c0 = blockIdx.z * 64;
+  const cplxf* A = g.A[cls];
+  const int xo = g.kin ? offK : off;
+  const int yo = g.yoff ? offK : off;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  flt4v re[4], im[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    re[cb] = flt4v{0, 0, 0, 0};
+    im[cb] = flt4v{0, 0, 0, 0};
+  }
+  // each thread moves 4 A and 4 X elements per 16-deep slice; the next
+  // slice is requested before the current one's products
+  cplxf ra[4], rx[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      const int rr = t >> 4, kk = t & 15;
+      const int r = r0 + rr, k = k0 + kk;
+      ra[q] = (r < M && k < Kd) ? A[(size_t)r * Kd + k] : cplxf{0, 0};
+      const int c = c0 + rr;  // X: kk fastest, column rr
+      rx[q] = (k < Kd && c < g.nrhs) ? g.X[(size_t)c * g.ldx + xo + k] : cplxf{0, 0};
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < Kd; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      As[t >> 4][t & 15] = ra[q];
+      Xs[t & 15][t >> 4] = rx[q];
+    }
+    __syncthreads();
+    if (k0 + 16 < Kd) fetch(k0 + 16);
+#pragma unroll
+    for (int ks = 0; ks < 16; ks += 4) {
+      const cplxf a = As[16 * w + li][ks + lk];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const cplxf x = Xs[ks + lk][16 * cb + li];
+        re[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, x.re, re[cb], 0, 0, 0);
+        im[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, x.im, im[cb], 0, 0, 0);
+        re[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.im, x.im, re[cb], 0, 0, 0);
+        im[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.im, x.re, im[cb], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int c = c0 + 16 * cb + li;
+    if (c >= g.nrhs) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + 16 * w + 4 * lk + r;
+      if (row >= M) continue;
+      const size_t o = (size_t)c * g.ldy + yo + row;
+      if (g.mode == 1) {
+        const cplxf z = g.Z[o];
+        g.Y[o] = {z.re - re[cb][r], z.im - im[cb][r]};
+      } else {
+        g.Y[o] = {re[cb][r], im[cb][r]};
+      }
+    }
+  }
+}
+
 // precision conversions of n-element complex arrays
 __global__ void to_single(const cplx* __restrict__ a, cplxf* b, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -1242,6 +1330,14 @@ static int run_seg_gemm(dp_problem* p, int which, int mrows, int kin, int yoff, 
   g.kin = kin;
   g.yoff = yoff;
   g.mode = mode;
+  if constexpr (sizeof(C) == sizeof(cplxf)) {
+    if (nrhs >= 16) {
+      dim3 grid(P->m, (maxM + 63) / 64, (nrhs + 63) / 64);
+      seg_gemm_mfma32<<<grid, 256, 0, p->ctx->stream>>>(g);
+      DP_HIP(hipGetLastError());
+      return DP_OK;
+    }
+  }
   dim3 grid(P->m, (maxM + 63) / 64, (nrhs + 15) / 16);
   seg_gemm<C><<<grid, 256, 0, p->ctx->stream>>>(g);
   DP_HIP(hipGetLastError());
