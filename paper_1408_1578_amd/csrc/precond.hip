@@ -26,6 +26,7 @@
 #include <cmath>
 #include <complex>
 #include <map>
+#include <thread>
 #include <vector>
 
 #include "dp_internal.hpp"
@@ -1030,6 +1031,120 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
   } release_locals{{&row, &X, &S, &gstat, &d_alpha}, {&augB, &augS, &colB, &colS}};
   DP_TRY(d_alpha.reserve(ncls * mc * sizeof(double)));
   GJBatch gb{};
+  for (int ci = 0; ci < ncls; ++ci)
+    lagrange_mean<<<mc, 256, 0, st>>>(d_alpha.as<double>() + ci * mc, P->classes[ci].s, mc);
+  // ---- segment geometry: centre + m_c Chebyshev points, by trigonometric interpolation
+  const int npts = m * (1 + mc);
+  std::vector<double> uh(npts);
+  for (int i = 0; i < m; ++i) {
+    const double uc = P->off[i] + 0.5 * (P->len[i] - 1);
+    uh[(size_t)i * (1 + mc)] = uc;
+    for (int b = 0; b < mc; ++b) {
+      const double xi = std::cos((2.0 * b + 1.0) * kPi / (2.0 * mc));
+      double u = uc + xi * 0.5 * P->len[i];
+      if (u < 0) u += n;
+      if (u >= n) u -= n;
+      uh[(size_t)i * (1 + mc) + 1 + b] = u;
+    }
+  }
+  DevBuf d_u, d_geo, d_seg, d_e, d_kk;
+  std::vector<int> seg4(4 * m);
+  for (int i = 0; i < m; ++i) {
+    seg4[4 * i] = P->off[i];
+    seg4[4 * i + 1] = P->len[i];
+    seg4[4 * i + 2] = P->J[i];
+    seg4[4 * i + 3] = P->cls[i];
+  }
+  const size_t npair = (size_t)m * (m - 1);
+  int rc;
+  if ((rc = upload(d_u, uh, st)) || (rc = d_geo.reserve((size_t)npts * 4 * sizeof(double))) ||
+      (rc = upload(d_seg, seg4, st)) || (rc = d_e.reserve(npair * sizeof(cplx))) ||
+      (rc = d_kk.reserve(npair * 2 * sizeof(int))))
+    return fail(rc);
+  trig_interp<<<npts, 256, 0, st>>>(p->src.as<SrcRec>(), d_u.as<double>(), d_geo.as<double>(), n);
+  EArgs ea;
+  ea.geo = d_geo.as<double>();
+  ea.seg = d_seg.as<int>();
+  ea.alpha = d_alpha.as<double>();
+  ea.e = d_e.as<cplx>();
+  ea.kk = d_kk.as<int>();
+  ea.m = m;
+  ea.mc = mc;
+  ea.n = n;
+  ea.omega = omega;
+  ea.eta = p->eta;
+  ea.ds = ds;
+  ea.kind = p->kind;
+  e_entries<<<(unsigned)npair, 128, 0, st>>>(ea);
+  DP_HIP(hipGetLastError());
+  P->eval.resize(npair);
+  std::vector<int> kk(npair * 2);
+  DP_HIP(hipMemcpyAsync(P->eval.data(), d_e.p, npair * sizeof(cplx), hipMemcpyDeviceToHost, st));
+  DP_HIP(hipMemcpyAsync(kk.data(), d_kk.p, npair * 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  DP_HIP(hipStreamSynchronize(st));
+  P->eidx.resize(npair * 4);
+  for (size_t q = 0; q < npair; ++q) {
+    const int i = (int)(q / (m - 1));
+    int j = (int)(q % (m - 1));
+    if (j >= i) ++j;
+    P->eidx[4 * q] = i;
+    P->eidx[4 * q + 1] = j;
+    P->eidx[4 * q + 2] = kk[2 * q];
+    P->eidx[4 * q + 3] = kk[2 * q + 1];
+  }
+
+  // ---- pattern of floor(W) = E + antidiag(T) in CSC; each stored entry
+  // keeps the list of its sources (an antidiagonal entry of T_i, coded
+  // -(offK_i + r) - 1, or the E entry q), summed in that order once T is known
+  const int NW = P->NW;
+  std::vector<int> cp(NW + 1, 0), ri, ssrc_ptr(1, 0), ssrc;
+  {
+    std::vector<std::vector<std::pair<int, int>>> cols(NW);  // (row, source)
+    for (int i = 0; i < m; ++i) {
+      const int K = P->classes[P->cls[i]].K;
+      for (int r = 0; r < K; ++r) cols[P->offK[i] + K - 1 - r].push_back({P->offK[i] + r, -(P->offK[i] + r) - 1});
+    }
+    for (size_t q = 0; q < npair; ++q) {
+      const int i = P->eidx[4 * q], j = P->eidx[4 * q + 1];
+      const int row_ = P->offK[i] + P->eidx[4 * q + 2] + P->J[i];
+      const int col_ = P->offK[j] + P->eidx[4 * q + 3] + P->J[j];
+      cols[col_].push_back({row_, (int)q});
+    }
+    for (int c = 0; c < NW; ++c) {
+      auto& v = cols[c];
+      std::stable_sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+      for (size_t q = 0; q < v.size(); ++q) {
+        // an E entry landing on an antidiagonal position is added to it
+        if (q == 0 || v[q].first != v[q - 1].first) {
+          ri.push_back(v[q].first);
+          ssrc_ptr.push_back(ssrc_ptr.back());
+        }
+        ssrc.push_back(v[q].second);
+        ssrc_ptr.back()++;
+      }
+      cp[c + 1] = (int)ri.size();
+    }
+  }
+  P->nnzW = (int64_t)ri.size();
+  // Host sparse LU unless the ordering predicts more than 32 factor entries
+  // per row (many segments coupled all-to-all through E): then the sparse
+  // solves are slower than dense ones and the host factorisation takes
+  // seconds, so floor(W) is factored densely on the device instead.
+  // With more than 2 N_W pair entries (m (m - 1) > 2 N_W) the coupling is
+  // all-to-all enough that the ordering need not be tried.  The ordering
+  // needs only the pattern: it runs on a host thread while the device
+  // inverts the size classes.
+  const int64_t fill_cap = o->w_solver == 1 ? INT64_MAX : 32 * (int64_t)NW;
+  const bool go_dense = o->w_solver == 2 || (o->w_solver == 0 && (int64_t)m * (m - 1) > 2 * (int64_t)NW);
+  std::vector<int> order;
+  struct Joiner {
+    std::thread t;
+    ~Joiner() {
+      if (t.joinable()) t.join();
+    }
+  } ordering;
+  if (!go_dense) ordering.t = std::thread([&] { order = sparse_lu_order(NW, cp, ri, fill_cap); });
+
   for (int ci = 0; ci < ncls; ++ci) {
     SizeClass& c = P->classes[ci];
     const int s = c.s, K = c.K;
@@ -1091,112 +1206,31 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     threshold_T(c.T, K, o->t_keep, Tt);
     DP_HIP(hipMemcpyAsync(c.Tt.p, Tt.data(), Tt.size() * sizeof(cplx), hipMemcpyHostToDevice, st));
     DP_HIP(hipStreamSynchronize(st));
-    lagrange_mean<<<mc, 256, 0, st>>>(d_alpha.as<double>() + ci * mc, s, mc);
   }
   DP_HIP(hipGetLastError());
 
-  // ---- segment geometry: centre + m_c Chebyshev points, by trigonometric interpolation
-  const int npts = m * (1 + mc);
-  std::vector<double> uh(npts);
-  for (int i = 0; i < m; ++i) {
-    const double uc = P->off[i] + 0.5 * (P->len[i] - 1);
-    uh[(size_t)i * (1 + mc)] = uc;
-    for (int b = 0; b < mc; ++b) {
-      const double xi = std::cos((2.0 * b + 1.0) * kPi / (2.0 * mc));
-      double u = uc + xi * 0.5 * P->len[i];
-      if (u < 0) u += n;
-      if (u >= n) u -= n;
-      uh[(size_t)i * (1 + mc) + 1 + b] = u;
-    }
-  }
-  DevBuf d_u, d_geo, d_seg, d_e, d_kk;
-  std::vector<int> seg4(4 * m);
-  for (int i = 0; i < m; ++i) {
-    seg4[4 * i] = P->off[i];
-    seg4[4 * i + 1] = P->len[i];
-    seg4[4 * i + 2] = P->J[i];
-    seg4[4 * i + 3] = P->cls[i];
-  }
-  const size_t npair = (size_t)m * (m - 1);
-  int rc;
-  if ((rc = upload(d_u, uh, st)) || (rc = d_geo.reserve((size_t)npts * 4 * sizeof(double))) ||
-      (rc = upload(d_seg, seg4, st)) || (rc = d_e.reserve(npair * sizeof(cplx))) ||
-      (rc = d_kk.reserve(npair * 2 * sizeof(int))))
-    return fail(rc);
-  trig_interp<<<npts, 256, 0, st>>>(p->src.as<SrcRec>(), d_u.as<double>(), d_geo.as<double>(), n);
-  EArgs ea;
-  ea.geo = d_geo.as<double>();
-  ea.seg = d_seg.as<int>();
-  ea.alpha = d_alpha.as<double>();
-  ea.e = d_e.as<cplx>();
-  ea.kk = d_kk.as<int>();
-  ea.m = m;
-  ea.mc = mc;
-  ea.n = n;
-  ea.omega = omega;
-  ea.eta = p->eta;
-  ea.ds = ds;
-  ea.kind = p->kind;
-  e_entries<<<(unsigned)npair, 128, 0, st>>>(ea);
-  DP_HIP(hipGetLastError());
-  P->eval.resize(npair);
-  std::vector<int> kk(npair * 2);
-  DP_HIP(hipMemcpyAsync(P->eval.data(), d_e.p, npair * sizeof(cplx), hipMemcpyDeviceToHost, st));
-  DP_HIP(hipMemcpyAsync(kk.data(), d_kk.p, npair * 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-  DP_HIP(hipStreamSynchronize(st));
-  P->eidx.resize(npair * 4);
-  for (size_t q = 0; q < npair; ++q) {
-    const int i = (int)(q / (m - 1));
-    int j = (int)(q % (m - 1));
-    if (j >= i) ++j;
-    P->eidx[4 * q] = i;
-    P->eidx[4 * q + 1] = j;
-    P->eidx[4 * q + 2] = kk[2 * q];
-    P->eidx[4 * q + 3] = kk[2 * q + 1];
-  }
-
-  // ---- floor(W) = E + antidiag(T) in CSC, sparse LU on the host
-  const int NW = P->NW;
-  std::vector<std::vector<std::pair<int, zc>>> cols(NW);
-  for (int i = 0; i < m; ++i) {
-    const SizeClass& c = P->classes[P->cls[i]];
-    for (int r = 0; r < c.K; ++r) {
-      const cplx v = c.T[(size_t)r * c.K + (c.K - 1 - r)];
-      cols[P->offK[i] + c.K - 1 - r].push_back({P->offK[i] + r, zc(v.re, v.im)});
-    }
-  }
-  for (size_t q = 0; q < npair; ++q) {
-    const int i = P->eidx[4 * q], j = P->eidx[4 * q + 1];
-    const int row_ = P->offK[i] + P->eidx[4 * q + 2] + P->J[i];
-    const int col_ = P->offK[j] + P->eidx[4 * q + 3] + P->J[j];
-    cols[col_].push_back({row_, zc(P->eval[q].re, P->eval[q].im)});
-  }
-  std::vector<int> cp(NW + 1, 0), ri;
-  std::vector<zc> vx;
-  for (int c = 0; c < NW; ++c) {
-    auto& v = cols[c];
-    std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
-    // merge duplicates (an E entry landing on an antidiagonal position)
-    for (size_t q = 0; q < v.size(); ++q) {
-      if (!ri.empty() && (int)ri.size() > cp[c] && ri.back() == v[q].first) {
-        vx.back() += v[q].second;
+  // ---- values of floor(W) (sources summed in their stored order); LU
+  std::vector<zc> vx(ri.size());
+  for (size_t e = 0; e < ri.size(); ++e) {
+    zc v = 0.0;
+    for (int q = ssrc_ptr[e]; q < ssrc_ptr[e + 1]; ++q) {
+      const int src = ssrc[q];
+      if (src < 0) {
+        const int a = -src - 1;  // offK_i + r
+        const int i = (int)(std::upper_bound(P->offK.begin(), P->offK.end(), a) - P->offK.begin()) - 1;
+        const SizeClass& c = P->classes[P->cls[i]];
+        const int r = a - P->offK[i];
+        const cplx t = c.T[(size_t)r * c.K + (c.K - 1 - r)];
+        v += zc(t.re, t.im);
       } else {
-        ri.push_back(v[q].first);
-        vx.push_back(v[q].second);
+        v += zc(P->eval[src].re, P->eval[src].im);
       }
     }
-    cp[c + 1] = (int)ri.size();
+    vx[e] = v;
   }
-  P->nnzW = (int64_t)ri.size();
-  // Host sparse LU unless the ordering predicts more than 32 factor entries
-  // per row (many segments coupled all-to-all through E): then the sparse
-  // solves are slower than dense ones and the host factorisation takes
-  // seconds, so floor(W) is factored densely on the device instead.
-  // With more than 2 N_W pair entries (m (m - 1) > 2 N_W) the coupling is
-  // all-to-all enough that the ordering need not be tried.
-  const int64_t fill_cap = o->w_solver == 1 ? INT64_MAX : 32 * (int64_t)NW;
-  const bool go_dense = o->w_solver == 2 || (o->w_solver == 0 && (int64_t)m * (m - 1) > 2 * (int64_t)NW);
-  rc = go_dense ? kSparseFillLimit : sparse_lu_factor(NW, cp, ri, vx, P->lu, fill_cap);
+  if (ordering.t.joinable()) ordering.t.join();
+  if (go_dense || (order.empty() && NW > 0)) rc = kSparseFillLimit;
+  else rc = sparse_lu_factor_ordered(NW, cp, ri, vx, order, P->lu, fill_cap);
   if (rc == kSparseFillLimit) {
     if ((double)NW * NW * sizeof(cplx) > 48.0 * (1 << 30)) {
       set_error("floor(W) of dimension %d needs a dense factorisation larger than 48 GiB", NW);

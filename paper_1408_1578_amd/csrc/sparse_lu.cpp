@@ -77,9 +77,8 @@ static std::vector<int> min_degree(int n, std::vector<std::vector<int>> adj, int
   return order;
 }
 
-int sparse_lu_factor(int n, const std::vector<int>& cp, const std::vector<int>& ri, const std::vector<zc>& vx,
-                     SparseLU& out, int64_t max_fill) {
-  // ---- ordering on the symmetrised pattern
+std::vector<int> sparse_lu_order(int n, const std::vector<int>& cp, const std::vector<int>& ri, int64_t max_fill) {
+  // ordering on the symmetrised pattern
   std::vector<std::vector<int>> adj(n);
   for (int j = 0; j < n; ++j)
     for (int p = cp[j]; p < cp[j + 1]; ++p) {
@@ -92,8 +91,18 @@ int sparse_lu_factor(int n, const std::vector<int>& cp, const std::vector<int>& 
     std::sort(a.begin(), a.end());
     a.erase(std::unique(a.begin(), a.end()), a.end());
   }
-  std::vector<int> Q = min_degree(n, adj, max_fill);
+  return min_degree(n, adj, max_fill);
+}
+
+int sparse_lu_factor(int n, const std::vector<int>& cp, const std::vector<int>& ri, const std::vector<zc>& vx,
+                     SparseLU& out, int64_t max_fill) {
+  const std::vector<int> Q = sparse_lu_order(n, cp, ri, max_fill);
   if (Q.empty() && n > 0) return kSparseFillLimit;
+  return sparse_lu_factor_ordered(n, cp, ri, vx, Q, out, max_fill);
+}
+
+int sparse_lu_factor_ordered(int n, const std::vector<int>& cp, const std::vector<int>& ri,
+                             const std::vector<zc>& vx, const std::vector<int>& Q, SparseLU& out, int64_t max_fill) {
   std::vector<int> Qinv(n);
   for (int a = 0; a < n; ++a) Qinv[Q[a]] = a;
   // A' = W(Q, Q) in CSC: column b of A' is column Q[b] of W with rows relabelled

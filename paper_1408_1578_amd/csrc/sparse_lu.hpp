@@ -26,4 +26,15 @@ int sparse_lu_factor(int n, const std::vector<int>& colptr, const std::vector<in
                      const std::vector<std::complex<double>>& val, SparseLU& out,
                      int64_t max_fill = INT64_MAX);
 
+// The two halves of sparse_lu_factor.  The ordering needs only the pattern
+// (so it can run before the values are known); it is empty when the
+// predicted fill exceeds max_fill.  The numeric factorisation takes that
+// ordering and returns DP_OK, DP_ESINGULAR or kSparseFillLimit (fill beyond
+// twice max_fill).
+std::vector<int> sparse_lu_order(int n, const std::vector<int>& colptr, const std::vector<int>& rowind,
+                                 int64_t max_fill);
+int sparse_lu_factor_ordered(int n, const std::vector<int>& colptr, const std::vector<int>& rowind,
+                             const std::vector<std::complex<double>>& val, const std::vector<int>& order,
+                             SparseLU& out, int64_t max_fill = INT64_MAX);
+
 }  // namespace dp
