@@ -43,7 +43,8 @@ struct DevBuf {
 
 // One boundary node (64 bytes): position, outward normal, speed |x'(t)| and
 // curvature in FP64, and for the single-precision sweep the FP32 normal,
-// a quarter of the trapezoid weight, (2 pi/n) |x'(t)| / 4, and |x'(t)| / (4 pi).
+// a quarter of the trapezoid weight, (2 pi/n) |x'(t)| / 4, and |x'(t)| / (4 pi)
+// (unused by the current kernels).
 struct SrcRec {
   double x, y, nx, ny, sp, kappa;
   float nxf, nyf, wf, spf;
@@ -55,7 +56,7 @@ enum SweepOp { OP_SOFT = 0, OP_HARD = 1, OP_S = 2, OP_D = 3, OP_DP = 4 };
 struct SweepParams {
   const SrcRec* src;       // n records
   const double* C;         // n: Kress correction C_k (index (i - j) mod n)
-  const float* C32;        // its FP32 copy
+  const float* C32;        // C_k / (pi dt) in FP32 (single-precision sweep)
   const cplx* dens;        // [j][nd][nrp] source densities (transposed layout)
   cplx* partial;           // [chunk][nd][nrp][n] partial sums
   const cplxf* dens32;     // FP32 copies (near field and the few-column FP32 sweep)
@@ -104,7 +105,7 @@ struct dp_problem {
   std::vector<double> hx, hy, hnx, hny, hsp, hkap;  // host copies
   dp::DevBuf src;       // SrcRec[n]
   dp::DevBuf C;         // double[n]
-  dp::DevBuf C32;       // float[n], FP32 copy of C
+  dp::DevBuf C32;       // float[n], C_k / (pi dt) (single-precision sweep)
   dp::DevBuf diag;      // double4[n]: S_ii (re, im), D_ii
   dp::DevBuf twiddle;   // cplx[n]   (e^{-2 pi i l/n})
   dp::DevBuf dens;      // sweep operands

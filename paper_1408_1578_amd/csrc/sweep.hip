@@ -46,6 +46,7 @@ __global__ __launch_bounds__(256) void sweep_private(SweepParams p) {
   const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
   const Far32 f = far32_consts(p.omega, p.eta, p.r2near, 1.0f, 1.0f);
   const Tgt32 tf = tgt32<OP>(tr.nx, tr.ny, f);
+  const double rho_scale = 1.0 / (kPi * p.dt);  // rho = C_k / (pi dt)
   const int j0 = blockIdx.y * p.chunk_len;
   const int j1 = min(n, j0 + p.chunk_len);
   cplx acc[ND][NR];
@@ -325,6 +326,7 @@ __global__ __launch_bounds__(256) void sweep_private32(SweepParams p) {
   const Tgt t = {tr.x, tr.y, tr.nx, tr.ny};
   const Far32 f = far32_consts(p.omega, p.eta, p.r2near, 1.0f, 1.0f);
   const Tgt32 tf = tgt32<OP>(tr.nx, tr.ny, f);
+  const double rho_scale = 1.0 / (kPi * p.dt);  // rho = C_k / (pi dt)
   const int j0 = blockIdx.y * p.chunk_len;
   const int j1 = min(n, j0 + p.chunk_len);
   cplx acc[ND][NR];
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(256) void sweep_private32(SweepParams p) {
   for (int j = j0; j < j1; ++j) {
     const SrcRec s = p.src[j];
     cplxf K[ND];
-    pair_kernel_far32<OP>(t, tf, s, (float)p.C[k], ii == j, f, K);
+    pair_kernel_far32<OP>(t, tf, s, (float)(p.C[k] * rho_scale), false, f, K);
     const cplx* dj = p.dens + (size_t)j * ND * NR;
 #pragma unroll
     for (int d = 0; d < ND; ++d)
@@ -407,7 +409,7 @@ __device__ __forceinline__ flt4 mma16(const uint32_t (&a)[4], const uint4& b, fl
 // every lane evaluates 8 pairs (target lane % 16, sources 4 e + lane / 16),
 // which is exactly its A fragment; the four lane groups then read adjacent
 // source records, on distinct LDS banks.  The step's density tile, its 32 source
-// records and the C_k window of the block (FP32 copy of the table) reach LDS
+// records and the C_k window of the block (FP32 table of C_k / (pi dt)) reach LDS
 // by direct global-to-LDS loads issued one step ahead into the other of two
 // buffers; the steps alternate between two separate sets of LDS arrays so
 // that reads of one set never wait for the loads into the other.  In LDS the
@@ -482,7 +484,7 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
       for (int h = 0; h < 2; ++h) {
         const int jj = 4 * (2 * e2 + h) + lk;  // k-index 8 lk + e holds source 4 e + lk
         const int j = jb + jj;
-        pair_kernel_far32<OP>(t, tf, ss[jj], Cs[31 + ti - jj], ii == j || j >= j1, f, K[h]);
+        pair_kernel_far32<OP>(t, tf, ss[jj], Cs[31 + ti - jj], j >= j1, f, K[h]);
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {

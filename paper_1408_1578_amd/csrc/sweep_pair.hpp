@@ -145,15 +145,17 @@ __host__ __device__ inline Tgt32 tgt32(double nx, double ny, const Far32& f) {
 // Far-field pair with FP32 kernel values.  r comes from the FP32 reciprocal
 // square root y0 refined by one Newton step for sqrt in FP64 (relative error
 // ~1e-14), so the phase omega r keeps an absolute error below 1e-9 for
-// omega r < 5e4; 1/r in the FP32 factors is y0 itself.  With the source's
-// FP32 fields wf = dt |x'_j| / 4 and spf = |x'_j| / (4 pi), the S-type and
-// D-type values share
-//   A0 = wf Im H0 + cq Re H0,  B1 = wf Im H1 + cq Re H1,  cq = C_k spf,
-// (S = -A0 + i wf Re H0, D' = omega nu_i.rhat (B1 - i wf Re H1)).  Pairs with
-// zero set (self, near field, outside the caller's range) get wf = cq = 0
-// and hence K = 0; their distance is replaced by 1 so every value is finite.
+// omega r < 5e4; 1/r in the FP32 factors is y0 itself.  The source's FP32
+// weight wf = dt |x'_j| / 4 multiplies the Hankel values (h = wf H), and
+// rho = C_k / (pi dt) is the ratio of the Kress weight C_k |x'_j| / (4 pi) to
+// it, so the S-type and D-type values share
+//   A0 = Im h0 + rho Re h0,  B1 = Im h1 + rho Re h1
+// (S = -A0 + i Re h0, D' = omega nu_i.rhat (B1 - i Re h1)).  Pairs with zero
+// set (outside the caller's range) or in the near field (self pairs
+// included: r = 0) get wf = 0 and hence K = 0; their distance is replaced
+// by 1 so every value is finite.
 template <int OP>
-__device__ __forceinline__ void pair_kernel_far32(const Tgt& t, const Tgt32& tf, const SrcRec& s, float Ck,
+__device__ __forceinline__ void pair_kernel_far32(const Tgt& t, const Tgt32& tf, const SrcRec& s, float rho,
                                                   bool zero, const Far32& f, cplxf* K) {
   const double dx = t.x - s.x, dy = t.y - s.y;
   double r2 = pair_r2(t.x, t.y, s.x, s.y);
@@ -163,18 +165,17 @@ __device__ __forceinline__ void pair_kernel_far32(const Tgt& t, const Tgt32& tf,
   const double yd = (double)y0;
   const double r0 = r2 * yd;
   const double r = fma(0.5 * yd, fma(-r0, r0, r2), r0);
-  const H01f h = hankel01_far32(fmax(f.omega * r, DP_HANKEL_ZA), f.sc0);
-  const float dxf = (float)dx, dyf = (float)dy;
   const float wq = zero ? 0.0f : s.wf;
-  const float cq = zero ? 0.0f : Ck * s.spf;
-  const float A0 = fmaf(wq, h.h0.im, cq * h.h0.re);
-  const float Sr = wq * h.h0.re;
+  const H01f h = hankel01_far32(fmax(f.omega * r, DP_HANKEL_ZA), f.sc0 * wq);
+  const float dxf = (float)dx, dyf = (float)dy;
+  const float A0 = fmaf(rho, h.h0.re, h.h0.im);
+  const float Sr = h.h0.re;
   if constexpr (OP == OP_S) {
     K[0] = {-A0, Sr};
     return;
   }
-  const float B1 = fmaf(wq, h.h1.im, cq * h.h1.re);
-  const float T1 = wq * h.h1.re;
+  const float B1 = fmaf(rho, h.h1.re, h.h1.im);
+  const float T1 = h.h1.re;
   if constexpr (OP == OP_SOFT || OP == OP_D) {
     const float on = fmaf(s.nxf, dxf, s.nyf * dyf) * (y0 * f.om);  // omega nu_j.rhat
     if constexpr (OP == OP_SOFT) K[0] = {fmaf(f.eta, Sr, -on * B1), fmaf(f.eta, A0, on * T1)};

@@ -75,7 +75,10 @@ int build_tables(dp_problem* p) {
   p->R0 = hc[0];
   p->cmax = 0;
   for (int k = 1; k < n; ++k) p->cmax = std::max(p->cmax, std::fabs(hc[k]));
-  std::vector<float> hc32(hc.begin(), hc.end());
+  // FP32 copy for the single-precision sweep, as the ratio C_k / (pi dt) of
+  // the Kress weight to the trapezoid weight (both times |x'_j|/4)
+  std::vector<float> hc32(n);
+  for (int k = 0; k < n; ++k) hc32[k] = (float)(hc[k] * (double)n / (2.0 * kPi * kPi));
   DP_TRY(p->C32.reserve(n * sizeof(float)));
   DP_HIP(hipMemcpyAsync(p->C32.p, hc32.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
   DP_HIP(hipStreamSynchronize(st));
