@@ -500,33 +500,44 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
         nih[e] = aih[d][e] ^ 0x80008000u;
         nil[e] = ail[d][e] ^ 0x80008000u;
       }
-      // two column blocks at a time: four independent accumulation chains
+      // two column blocks at a time (four independent accumulation chains);
+      // the next pair's B fragments are read from LDS while this pair's
+      // products run
       constexpr int CP = NCB >= 2 ? 2 : 1;
-#pragma unroll
-      for (int cb0 = 0; cb0 < NCB; cb0 += CP) {
-        uint4 brh[CP], brl[CP], bih[CP], bil[CP];
-        flt4 r[CP], m[CP];
+      constexpr int NG = NCB / CP;
+      uint4 bb[2][CP][4];
+      auto read_b = [&](int cb0, uint4 (&dst)[CP][4]) {
 #pragma unroll
         for (int u = 0; u < CP; ++u) {
           const int row = d * 4 * NC + (cb0 + u) * 16 + li;
-          brh[u] = Bt[row * 4 + gsw];
-          brl[u] = Bt[(row + NC) * 4 + gsw];
-          bih[u] = Bt[(row + 2 * NC) * 4 + gsw];
-          bil[u] = Bt[(row + 3 * NC) * 4 + gsw];
+#pragma unroll
+          for (int part = 0; part < 4; ++part) dst[u][part] = Bt[(row + part * NC) * 4 + gsw];
+        }
+      };
+      read_b(0, bb[0]);
+#pragma unroll
+      for (int gq = 0; gq < NG; ++gq) {
+        const int cb0 = gq * CP;
+        if (gq + 1 < NG) read_b(cb0 + CP, bb[(gq + 1) & 1]);
+        const uint4 (&B)[CP][4] = bb[gq & 1];
+        flt4 r[CP], m[CP];
+#pragma unroll
+        for (int u = 0; u < CP; ++u) {
           r[u] = Re[d][cb0 + u];
           m[u] = Im[d][cb0 + u];
         }
-#define DP_MMA2(AR, BR, AI, BI)                  \
+        // parts: 0 re hi, 1 re lo, 2 im hi, 3 im lo
+#define DP_MMA2(AR, PR, AI, PI)                    \
   _Pragma("unroll") for (int u = 0; u < CP; ++u) { \
-    r[u] = mma16(AR, BR[u], r[u]);               \
-    m[u] = mma16(AI, BI[u], m[u]);               \
+    r[u] = mma16(AR, B[u][PR], r[u]);              \
+    m[u] = mma16(AI, B[u][PI], m[u]);              \
   }
-        DP_MMA2(arh[d], brh, arh[d], bih)
-        DP_MMA2(arh[d], brl, arh[d], bil)
-        DP_MMA2(arl[d], brh, arl[d], bih)
-        DP_MMA2(nih, bih, aih[d], brh)
-        DP_MMA2(nih, bil, aih[d], brl)
-        DP_MMA2(nil, bih, ail[d], brh)
+        DP_MMA2(arh[d], 0, arh[d], 2)
+        DP_MMA2(arh[d], 1, arh[d], 3)
+        DP_MMA2(arl[d], 0, arl[d], 2)
+        DP_MMA2(nih, 2, aih[d], 0)
+        DP_MMA2(nih, 3, aih[d], 1)
+        DP_MMA2(nil, 2, ail[d], 0)
 #undef DP_MMA2
 #pragma unroll
         for (int u = 0; u < CP; ++u) {
