@@ -41,13 +41,13 @@ PEAK_FP16_MFMA = 2500.0
 # Executed matrix-core flops per pair, density and column in that sweep: a
 # complex product is 4 real products, each split into 3 FP16 products.
 FLOPS_MFMA16_PER_COL = 24
-# HBM bytes per launch of the 64-column FP64 hard sweep at n = 32768 with a
-# 2048-block grid (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the counts of
-# a 512 MiB device copy in the same run).  It describes the current kernel in
-# that configuration; another configuration or a changed kernel must be
-# measured again before it is reported.
-TRAFFIC_FP64_SWEEP = 1.3985e9
-TRAFFIC_FP32_SWEEP = None
+# HBM bytes per launch of the two 64-column hard sweeps at n = 32768 with the
+# default 2048-block grid (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the
+# counts of a 512 MiB device copy in the same run).  They describe the current
+# kernels in that configuration; another configuration or a changed kernel
+# must be measured again before they are reported.
+TRAFFIC_FP64_SWEEP = 1.4016e9
+TRAFFIC_FP32_SWEEP = 0.5773e9
 
 # Algorithmic FP64 flops of one ordered pair in the sound-hard sweep (far-field
 # evaluation path; an FMA counts 2): geometry 5, 1/r 8, r and z 2, H0/H1 142,
@@ -214,6 +214,8 @@ def main():
                     help="also serve a stream of N independent requests (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2.5, help="mean arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default sweep launch configuration (2048-block grid)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -317,8 +319,13 @@ def main():
         return out
 
     # launch configuration of the sweep for this shape, chosen before the timed region
+    # (--no-autotune keeps the default 2048-block grid, e.g. for counter runs
+    # that must all see one configuration)
     tuned = {}
     for precision in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
+        if args.no_autotune:
+            tuned[precision] = {"target_blocks": 2048, "default": True}
+            continue
         tuned[precision] = dp.dp_autotune(prob, nrhs, dp.DP_PREC_MIXED if precision == "mixed" else dp.DP_PREC_FP64)
         log(f"autotune [{precision}]: {tuned[precision]}")
     runs = {}
