@@ -44,16 +44,20 @@ __device__ void lds_fft(cplx* buf, int Lf, int lines, int loglines, const cplx* 
 // Column pass: for each column b and each j2 in [0, n2): line over j1 (stride
 // n2).  Optional twiddle e^{dir 2 pi i j2 k1/n}: applied after the transform
 // (forward) or before it (inverse).
-__global__ void fft_col_pass(cplx* data, int n, int n1, int n2, int logn1, int lines,
-                             const cplx* __restrict__ tw, int dir, int twiddle) {
+// `in` may equal `data` (in place: a block reads all its lines before it
+// writes).  With `speed`, each written element is divided by the speed of
+// its node (the last pass of the inverse transform is in natural order).
+__global__ void fft_col_pass(const cplx* in, cplx* data, int n, int n1, int n2, int logn1, int lines,
+                             const cplx* __restrict__ tw, int dir, int twiddle, const SrcRec* __restrict__ speed) {
   extern __shared__ cplx sbuf[];
   const int b = blockIdx.y;
   const int j2_0 = blockIdx.x * lines;
   const int loglines = __builtin_ctz(lines);
   cplx* base = data + (size_t)b * n;
+  const cplx* ibase = in + (size_t)b * n;
   for (int t = threadIdx.x; t < n1 * lines; t += blockDim.x) {
     const int l = t & (lines - 1), j1 = t >> loglines;
-    cplx v = base[(size_t)n2 * j1 + j2_0 + l];
+    cplx v = ibase[(size_t)n2 * j1 + j2_0 + l];
     if (twiddle && dir > 0) {  // inverse: pre-twiddle e^{+2 pi i j2 k1/n} (k1 = j1 here)
       cplx w = tw[((j2_0 + l) * j1) & (n - 1)];
       w.im = -w.im;
@@ -67,7 +71,12 @@ __global__ void fft_col_pass(cplx* data, int n, int n1, int n2, int logn1, int l
     const int l = t & (lines - 1), k1 = t >> loglines;
     cplx v = sbuf[k1 * lines + l];
     if (twiddle && dir < 0) v = cmul(v, tw[((j2_0 + l) * k1) & (n - 1)]);
-    base[(size_t)n2 * k1 + j2_0 + l] = v;
+    const size_t o = (size_t)n2 * k1 + j2_0 + l;
+    if (speed) {
+      const double r = 1.0 / speed[o].sp;
+      v = {v.re * r, v.im * r};
+    }
+    base[o] = v;
   }
 }
 
@@ -84,6 +93,53 @@ __global__ void fft_row_pass(cplx* data, int n, int n2, int logn2, int lines, co
   }
   __syncthreads();
   lds_fft(sbuf, n2, lines, __builtin_ctz(lines), tw, n, dir);
+  for (int t = threadIdx.x; t < n2 * lines; t += blockDim.x) {
+    const int e = t & (n2 - 1), l = t >> logn2;
+    base[(size_t)l * n2 + e] = sbuf[e * lines + l];
+  }
+}
+
+// Row pass of the derivative: per line (fixed k1) the forward transform over
+// j2, the multiplication of X[k1 + n1 k2] by i m / n (m the signed
+// frequency, Nyquist zeroed), and the inverse transform back over j2, all in
+// LDS.
+__global__ void fft_row_deriv(cplx* data, int n, int n1, int n2, int logn2, int lines, const cplx* __restrict__ tw) {
+  extern __shared__ cplx sbuf[];
+  const int b = blockIdx.y;
+  const int k1_0 = blockIdx.x * lines;
+  const int loglines = __builtin_ctz(lines);
+  cplx* base = data + (size_t)b * n + (size_t)k1_0 * n2;
+  for (int t = threadIdx.x; t < n2 * lines; t += blockDim.x) {
+    const int e = t & (n2 - 1), l = t >> logn2;
+    sbuf[bitrev(e, logn2) * lines + l] = base[(size_t)l * n2 + e];
+  }
+  __syncthreads();
+  lds_fft(sbuf, n2, lines, loglines, tw, n, -1);
+  // scale, then put the spectrum into bit-reversed order for the inverse:
+  // every element is read (into registers) before any is overwritten
+  constexpr int PER = kFftLds / 256;  // blockDim.x == 256, n2 * lines <= kFftLds
+  cplx tmp[PER];
+  int dst[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + 256 * q;
+    dst[q] = -1;
+    if (t < n2 * lines) {
+      const int e = t & (n2 - 1), l = t >> logn2;
+      const int k = k1_0 + l + n1 * e;
+      const int m = (k < n / 2) ? k : ((k == n / 2) ? 0 : k - n);
+      const double fm = (double)m / n;
+      const cplx v = sbuf[e * lines + l];
+      tmp[q] = {-fm * v.im, fm * v.re};
+      dst[q] = bitrev(e, logn2) * lines + l;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+    if (dst[q] >= 0) sbuf[dst[q]] = tmp[q];
+  __syncthreads();
+  lds_fft(sbuf, n2, lines, loglines, tw, n, +1);
   for (int t = threadIdx.x; t < n2 * lines; t += blockDim.x) {
     const int e = t & (n2 - 1), l = t >> logn2;
     base[(size_t)l * n2 + e] = sbuf[e * lines + l];
@@ -137,8 +193,8 @@ static void fft_passes(dp_problem* p, cplx* d, int nb, int dir) {
     int lines = kFftLds / n1;
     if (lines > n2) lines = n2;
     dim3 g(n2 / lines, nb);
-    fft_col_pass<<<g, 256, (size_t)n1 * lines * sizeof(cplx), st>>>(d, n, n1, n2, log1, lines, tw, dirc,
-                                                                     n2 > 1);
+    fft_col_pass<<<g, 256, (size_t)n1 * lines * sizeof(cplx), st>>>(d, d, n, n1, n2, log1, lines, tw, dirc,
+                                                                     n2 > 1, nullptr);
   };
   auto row = [&](int dirc) {
     if (n2 == 1) return;
@@ -175,6 +231,26 @@ int spectral_derivative(dp_problem* p, int nrhs, const cplx* in, cplx* out) {
   const int n = (int)p->n;
   const size_t tot = (size_t)n * nrhs;
   hipStream_t st = p->ctx->stream;
+  const int logn = ilog2(n);
+  const int log1 = logn <= 12 ? logn : (logn + 1) / 2;
+  const int n1 = 1 << log1, n2 = 1 << (logn - log1);
+  if (n2 > 1) {
+    // four-step: forward column pass (reading `in`), fused row pass
+    // (forward, derivative factor, inverse), inverse column pass dividing
+    // by the speed
+    const cplx* tw = p->twiddle.as<cplx>();
+    int lc = kFftLds / n1;
+    if (lc > n2) lc = n2;
+    int lr = kFftLds / n2;
+    if (lr > n1) lr = n1;
+    const dim3 gc(n2 / lc, nrhs), gr(n1 / lr, nrhs);
+    fft_col_pass<<<gc, 256, (size_t)n1 * lc * sizeof(cplx), st>>>(in, out, n, n1, n2, log1, lc, tw, -1, 1, nullptr);
+    fft_row_deriv<<<gr, 256, (size_t)n2 * lr * sizeof(cplx), st>>>(out, n, n1, n2, logn - log1, lr, tw);
+    fft_col_pass<<<gc, 256, (size_t)n1 * lc * sizeof(cplx), st>>>(out, out, n, n1, n2, log1, lc, tw, +1, 1,
+                                                                  p->src.as<SrcRec>());
+    DP_HIP(hipGetLastError());
+    return DP_OK;
+  }
   const int grid = grid_for(tot);
   copy_div_speed<<<grid, 256, 0, st>>>(in, out, p->src.as<SrcRec>(), n, tot, 0);
   t_derivative(p, out, nrhs);
