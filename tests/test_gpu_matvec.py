@@ -110,16 +110,20 @@ def test_layers(op, name):
     assert relerr(to_host(y), lay[name] @ q) < TOL
 
 
-@pytest.mark.parametrize("n", [64, 4096, 32768])
+# n > 4096 takes the four-step path with n = n1 n2: 8192 = 128 x 64,
+# 32768 = 256 x 128, 65536 = 256 x 256.  The Nyquist mode n/2 is dropped.
+@pytest.mark.parametrize("n", [64, 4096, 8192, 32768, 65536])
 def test_spectral_derivative(n):
     b = sample_boundary("disk", n)
     t = 2 * np.pi * np.arange(n) / n
-    m = np.array([1, 7, n // 2 - 1])
+    m = np.array([1, 7, -3, n // 2 - 1, n // 2])
     q = np.stack([np.exp(1j * mm * t) for mm in m], 1)
-    p = problem(b, 10.0, 10.0, 1)
-    y = empty(n, 3)
+    om = max(10.0, n / 16)  # D_s does not depend on omega; this keeps the near list small
+    p = problem(b, om, om, 1)
+    y = empty(n, len(m))
     dp.dp_layer_apply(p, dp.DP_OP_DS, to_dev(q), y)
-    ref = q * (1j * m)[None, :] / b.speed[:, None]
+    mult = np.where(m == n // 2, 0, m)
+    ref = q * (1j * mult)[None, :] / b.speed[:, None]
     # inputs at mode n/2 - 1 carry rounding ~ m t eps; allow eps * n * log2(n)
     assert relerr(to_host(y), ref) < max(1e-12, 1.1e-16 * n * np.log2(n))
     if n <= 4096:
