@@ -26,6 +26,7 @@
 #include <cmath>
 #include <complex>
 #include <map>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -285,6 +286,18 @@ __global__ void augment_identity(const cplx* __restrict__ S, cplx* A, int K) {
     const int r = idx / (2 * K), c = idx % (2 * K);
     A[idx] = c < K ? S[(size_t)r * K + c] : cplx{(c - K == r) ? 1.0 : 0.0, 0.0};
   }
+}
+
+// Inverts any number of matrices, eight per batch.
+static int gj_batch(hipStream_t st, GJBatch& b, int count, DevBuf& status);
+static int gj_invert(hipStream_t st, const std::vector<GJMat>& mats, DevBuf& status) {
+  for (size_t q0 = 0; q0 < mats.size(); q0 += 8) {
+    GJBatch b{};
+    const int count = (int)std::min<size_t>(8, mats.size() - q0);
+    for (int q = 0; q < count; ++q) b.m[q] = mats[q0 + q];
+    DP_TRY(gj_batch(st, b, count, status));
+  }
+  return DP_OK;
 }
 
 // Inverts the batch (at most 8 matrices): one launch per step of the largest.
@@ -1013,10 +1026,6 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
 
   // ---- size classes: B^{-1}, U, S, T, floor(T), alpha (batched over classes)
   const int ncls = (int)P->classes.size();
-  if (ncls > 8) {
-    set_error("dp_precond_build: more than 8 segment size classes");
-    return fail(DP_EINVAL);
-  }
   std::vector<DevBuf> augB(2 * ncls), augS(2 * ncls), colB(2 * ncls), colS(2 * ncls);
   DevBuf row, X, S, gstat;
   DevBuf d_alpha;
@@ -1030,7 +1039,7 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     }
   } release_locals{{&row, &X, &S, &gstat, &d_alpha}, {&augB, &augS, &colB, &colS}};
   DP_TRY(d_alpha.reserve(ncls * mc * sizeof(double)));
-  GJBatch gb{};
+  std::vector<GJMat> gb(ncls);
   for (int ci = 0; ci < ncls; ++ci)
     lagrange_mean<<<mc, 256, 0, st>>>(d_alpha.as<double>() + ci * mc, P->classes[ci].s, mc);
   // ---- segment geometry: centre + m_c Chebyshev points, by trigonometric interpolation
@@ -1143,7 +1152,13 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
       if (t.joinable()) t.join();
     }
   } ordering;
-  if (!go_dense) ordering.t = std::thread([&] { order = sparse_lu_order(NW, cp, ri, fill_cap); });
+  if (!go_dense) {
+    try {
+      ordering.t = std::thread([&] { order = sparse_lu_order(NW, cp, ri, fill_cap); });
+    } catch (const std::system_error&) {  // no thread available: order now
+      order = sparse_lu_order(NW, cp, ri, fill_cap);
+    }
+  }
 
   for (int ci = 0; ci < ncls; ++ci) {
     SizeClass& c = P->classes[ci];
@@ -1157,16 +1172,16 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
       return fail(rc);
     flat_row<<<(s + 255) / 256, 256, 0, st>>>(p->C.as<double>(), row.as<cplx>(), s, n, L, omega, p->eta, p->kind);
     toeplitz_aug<<<grid1((size_t)s * 2 * s), 256, 0, st>>>(row.as<cplx>(), augB[2 * ci].as<cplx>(), s);
-    gb.m[ci] = GJMat{{augB[2 * ci].as<cplx>(), augB[2 * ci + 1].as<cplx>()},
-                     {colB[2 * ci].as<cplx>(), colB[2 * ci + 1].as<cplx>()}, s};
+    gb[ci] = GJMat{{augB[2 * ci].as<cplx>(), augB[2 * ci + 1].as<cplx>()},
+                   {colB[2 * ci].as<cplx>(), colB[2 * ci + 1].as<cplx>()}, s};
     // the next class's flat row must not overwrite this one before it is read
     DP_HIP(hipStreamSynchronize(st));
   }
   {
     int rc;
-    if ((rc = gj_batch(st, gb, ncls, gstat))) return fail(rc);
+    if ((rc = gj_invert(st, gb, gstat))) return fail(rc);
   }
-  GJBatch gs{};
+  std::vector<GJMat> gs(ncls);
   for (int ci = 0; ci < ncls; ++ci) {
     SizeClass& c = P->classes[ci];
     const int s = c.s, K = c.K;
@@ -1184,14 +1199,14 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     // S = U^t X, then [S | I]
     dense_gemm<<<grid1((size_t)K * K), 256, 0, st>>>(c.Ut.as<cplx>(), X.as<cplx>(), S.as<cplx>(), K, K, s);
     augment_identity<<<grid1((size_t)K * 2 * K), 256, 0, st>>>(S.as<cplx>(), augS[2 * ci].as<cplx>(), K);
-    gs.m[ci] = GJMat{{augS[2 * ci].as<cplx>(), augS[2 * ci + 1].as<cplx>()},
-                     {colS[2 * ci].as<cplx>(), colS[2 * ci + 1].as<cplx>()}, K};
+    gs[ci] = GJMat{{augS[2 * ci].as<cplx>(), augS[2 * ci + 1].as<cplx>()},
+                   {colS[2 * ci].as<cplx>(), colS[2 * ci + 1].as<cplx>()}, K};
     // X and S are reused by the next class
     DP_HIP(hipStreamSynchronize(st));
   }
   {
     int rc;
-    if ((rc = gj_batch(st, gs, ncls, gstat))) return fail(rc);
+    if ((rc = gj_invert(st, gs, gstat))) return fail(rc);
   }
   for (int ci = 0; ci < ncls; ++ci) {
     SizeClass& c = P->classes[ci];
