@@ -181,33 +181,37 @@ DP_HD float dp_rsqrtf(float z) {
 #endif
 }
 
-// Asymptotic branch for z >= DP_HANKEL_ZA with FP32 arithmetic: the phase z
-// is reduced modulo pi/2 in FP64 (|z| up to 1e6 keeps ~1e-16 absolute phase
-// error), everything after the reduction is FP32 with the FP32-economized
-// polynomials (approximation error < 4e-9).  Relative accuracy ~3e-7.  Both
-// values come out multiplied by `scale` (a power of two, or 1).
-// With z = q pi/2 + r, e^{i(z - pi/4)} sqrt(2) = (c + s) + i (s - c) for
-// c = cos z, s = sin z; in terms of P = cos r + sin r and M = cos r - sin r
-// that pair is (P, -M), (M, P), (-P, M), (-M, -P) for q = 0, 1, 2, 3 mod 4.
-DP_HD H01f hankel01_far32(double z, float scale = 1.0f) {
-  const double kq = rint(z * kTwoOverPi);
-  double rr = fma(-kq, kPio2Hi, z);
-  rr = fma(-kq, kPio2Lo, rr);
-  const float r = (float)rr, v = r * r;
-  const float sr = fmaf(r * v, horner(kSinS32, v), r);
-  const float cr = fmaf(v, horner(kCosC32, v), 1.0f);
-  const int q = (int)kq;  // kq < 2^31 for z < 3e9
+// Asymptotic branch for z >= DP_HANKEL_ZA with FP32 arithmetic, with the
+// argument in quarter turns, w = 2 z / pi (FP64).  The reduction
+// f = w - rint(w), |f| <= 1/2, is exact in FP64 (|w| up to 1e6 keeps ~1e-16
+// absolute phase error); everything after it is FP32 with the quarter-turn
+// polynomials of hankel_poly.hpp (sine and cosine of (pi/2) f to ~5e-8, the
+// amplitude polynomials in s = 1/w^2 to ~4e-9).  Relative accuracy ~3e-7.
+// Both values come out multiplied by `scale` (a power of two, or 1, and
+// never negative).
+// With z = (pi/2)(q + f), e^{i(z - pi/4)} sqrt(2) = (c + s) + i (s - c) for
+// c = cos z, s = sin z; in terms of P = cos + sin and M = cos - sin of
+// (pi/2) f that pair is (P, -M), (M, P), (-P, M), (-M, -P) for
+// q = 0, 1, 2, 3 mod 4.  The amplitude sqrt(2/(pi z)) is (2/pi)/sqrt(w);
+// its constant (2/pi)/sqrt(2) (with the 1/sqrt(2) of P and M) is folded into
+// the sine and cosine polynomials, and the sign of q = 2, 3 is set on the
+// non-negative magnitude as its sign bit.
+DP_HD H01f hankel01_far32w(double w, float scale = 1.0f) {
+  const double kq = rint(w);
+  const float fr = (float)(w - kq), v = fr * fr;
+  const float sr = fr * horner(kSinQ32, v);  // kappa sin((pi/2) f)
+  const float cr = horner(kCosQ32, v);       // kappa cos((pi/2) f)
+  const int q = (int)kq;  // kq < 2^31 for w < 2e9
   const float P = cr + sr, M = cr - sr;
   const float a = (q & 1) ? M : P;
   const float b = (q & 1) ? P : -M;
-  const float zf = (float)z;
-  const float y = dp_rsqrtf(zf);
-  const float t = y * y;
-  const float u = t * t;
-  const float p0 = horner(kHankP032, u), p1 = horner(kHankP132, u);
-  const float q0 = horner(kHankQ032, u) * t, q1 = horner(kHankQ132, u) * t;
-  const float m0 = (float)(kSqrt2OverPi * kInvSqrt2) * scale * y;
-  const float m = (q & 2) ? -m0 : m0;
+  const float y = dp_rsqrtf((float)w);  // 1/sqrt(w)
+  const float tw = y * y;                // 1/w
+  const float s = tw * tw;
+  const float p0 = horner(kHankP0W32, s), p1 = horner(kHankP1W32, s);
+  const float q0 = horner(kHankQ0W32, s) * tw, q1 = horner(kHankQ1W32, s) * tw;
+  const float m0 = scale * y;
+  const float m = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, m0) | ((uint32_t)(q & 2) << 30));
   const cplxf e0 = {a * m, b * m};  // e1 = -i e0
   H01f h;
   h.h0 = {e0.re * p0 - e0.im * q0, e0.re * q0 + e0.im * p0};

@@ -20,6 +20,20 @@ Sine/cosine on the reduced range |r| <= pi/4 (v = r^2):
     cos r = 1 + v C(v),    C = sum_k (-1)^{k+1} v^k/(2k+2)!
 economized the same way on [0, V], V slightly above (pi/4)^2.
 
+The single-precision evaluation works in quarter turns, w = 2 z / pi, so
+that the FP64 reduction is w - rint(w) with no multiple of pi/2 to subtract:
+  * the Hankel polynomials become polynomials in s = 1/w^2 = (pi/2)^2 u, i.e.
+    P'_k = P_k (2/pi)^{2k} and, with Q multiplied by 1/w instead of t,
+    Q'_k = Q_k (2/pi)^{2k+1} (the same functions, so the same error bounds);
+  * sine and cosine of (pi/2) f for |f| <= 1/2 (v = f^2), times the
+    amplitude constant kappa = (2/pi)/sqrt(2) of the Hankel functions in
+    quarter turns (which the sine/cosine pair otherwise needs as an extra
+    multiplication):
+    kappa sin = f SQ(v), SQ = kappa sum_k (-1)^k (pi/2)^{2k+1} v^k/(2k+1)!,
+    kappa cos = CQ(v),   CQ = kappa sum_k (-1)^k (pi/2)^{2k} v^k/(2k)!,
+    economized on [0, VQ], VQ slightly above 1/4, to 3e-8: the split FP16
+    products downstream carry ~5e-7 relative error anyway.
+
 The script checks every economized polynomial against its full series at
 2001 points of its interval in exact arithmetic and fails if the error
 exceeds the bound it prints.
@@ -32,6 +46,11 @@ import sys
 ZA = 25
 U = F(1, ZA * ZA)
 V = F(617, 1000)  # > (pi/4)^2 = 0.61685...
+VQ = F(2501, 10000)  # > (1/2)^2
+PI = F("3.14159265358979323846264338327950288419716939937510582097494459")
+TWO_OVER_PI = 2 / PI
+SQRT2 = F("1.41421356237309504880168872420969807856967187537694807317667974")
+KAPPA = SQRT2 / PI  # (2/pi)/sqrt(2)
 
 
 def a(k, nu):
@@ -118,28 +137,51 @@ def main():
             Pe, dP = economize(P, U, tol_p)
             Qe, dQ = economize(Q, U, tol_p * ZA)  # Q is multiplied by t <= 1/ZA
             fl = F(1, 10 ** 7) if ctype == "float" else F(0)  # float rounding of the coefficients
-            eP = check(P, Pe, U, 2 * tol_p + fl, f"P{nu}{sfx}", ctype)
-            eQ = check(Q, Qe, U, 2 * tol_p * ZA + fl, f"Q{nu}{sfx}", ctype)
-            out.append(emit(f"kHankP{nu}{sfx}", Pe, ctype))
-            out.append(emit(f"kHankQ{nu}{sfx}", Qe, ctype))
-            report.append(f"// P{nu}{sfx}: {len(Pe)} terms, max error {eP:.2e}; "
-                          f"Q{nu}{sfx}: {len(Qe)} terms, max error (times t) {eQ / ZA:.2e}\n")
-        S = [F((-1) ** (k + 1), math.factorial(2 * k + 3)) for k in range(12)]
-        C = [F((-1) ** (k + 1), math.factorial(2 * k + 2)) for k in range(12)]
-        Se, _ = economize(S, V, tol_p)
-        Ce, _ = economize(C, V, tol_p)
+            if ctype == "float":
+                # quarter-turn variable s = 1/w^2 = (pi/2)^2 u
+                G = TWO_OVER_PI ** 2
+                P = [c * G ** k for k, c in enumerate(P)]
+                Pe = [c * G ** k for k, c in enumerate(Pe)]
+                Q = [c * G ** k * TWO_OVER_PI for k, c in enumerate(Q)]
+                Qe = [c * G ** k * TWO_OVER_PI for k, c in enumerate(Qe)]
+                X, qb, nm, tmax = U / G, TWO_OVER_PI * 2 * tol_p * ZA + fl, "W", PI / (2 * ZA)
+            else:
+                X, qb, nm, tmax = U, 2 * tol_p * ZA + fl, "", F(1, ZA)
+            eP = check(P, Pe, X, 2 * tol_p + fl, f"P{nu}{nm}{sfx}", ctype)
+            eQ = check(Q, Qe, X, qb, f"Q{nu}{nm}{sfx}", ctype)
+            out.append(emit(f"kHankP{nu}{nm}{sfx}", Pe, ctype))
+            out.append(emit(f"kHankQ{nu}{nm}{sfx}", Qe, ctype))
+            report.append(f"// P{nu}{nm}{sfx}: {len(Pe)} terms, max error {eP:.2e}; "
+                          f"Q{nu}{nm}{sfx}: {len(Qe)} terms, max error (times {'1/w' if nm else 't'}) "
+                          f"{eQ * float(tmax):.2e}\n")
         fl = F(1, 10 ** 7) if ctype == "float" else F(0)
-        eS = check(S, Se, V, 2 * tol_p + fl, f"S{sfx}", ctype)
-        eC = check(C, Ce, V, 2 * tol_p + fl, f"C{sfx}", ctype)
-        out.append(emit(f"kSinS{sfx}", Se, ctype))
-        out.append(emit(f"kCosC{sfx}", Ce, ctype))
-        report.append(f"// sin S{sfx}: {len(Se)} terms, max error {eS:.2e}; cos C{sfx}: {len(Ce)} terms, "
+        if ctype == "float":
+            tq = F(3, 10 ** 8)
+            S = [KAPPA * (-1) ** k * (PI / 2) ** (2 * k + 1) / math.factorial(2 * k + 1) for k in range(14)]
+            C = [KAPPA * (-1) ** k * (PI / 2) ** (2 * k) / math.factorial(2 * k) for k in range(14)]
+            Se, _ = economize(S, VQ, tq)
+            Ce, _ = economize(C, VQ, tq)
+            eS = check(S, Se, VQ, 2 * tq + fl, f"SQ{sfx}", ctype)
+            eC = check(C, Ce, VQ, 2 * tq + fl, f"CQ{sfx}", ctype)
+            names = ("kSinQ", "kCosQ")
+        else:
+            S = [F((-1) ** (k + 1), math.factorial(2 * k + 3)) for k in range(12)]
+            C = [F((-1) ** (k + 1), math.factorial(2 * k + 2)) for k in range(12)]
+            Se, _ = economize(S, V, tol_p)
+            Ce, _ = economize(C, V, tol_p)
+            eS = check(S, Se, V, 2 * tol_p + fl, f"S{sfx}", ctype)
+            eC = check(C, Ce, V, 2 * tol_p + fl, f"C{sfx}", ctype)
+            names = ("kSinS", "kCosC")
+        out.append(emit(f"{names[0]}{sfx}", Se, ctype))
+        out.append(emit(f"{names[1]}{sfx}", Ce, ctype))
+        report.append(f"// {names[0]}{sfx}: {len(Se)} terms, max error {eS:.2e}; {names[1]}{sfx}: {len(Ce)} terms, "
                       f"max error {eC:.2e}\n")
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "hankel_poly.hpp")
     with open(path, "w") as f:
         f.write("// Generated by gen_poly.py: economized coefficients (ascending powers of u = 1/z^2\n"
                 f"// on [0, 1/{ZA}^2] for the Hankel asymptotic branch, of v = r^2 on [0, {float(V)}] for\n"
-                "// sine and cosine).  Do not edit.\n")
+                "// sine and cosine; the single-precision W/Q sets in quarter turns w = 2 z / pi:\n"
+                f"// s = 1/w^2 and v = f^2 on [0, {float(VQ)}]).  Do not edit.\n")
         f.writelines(report)
         f.write("#pragma once\n\nnamespace dp {\n\n")
         f.write(f"constexpr double kHankelZA = {ZA}.0;\n")

@@ -387,11 +387,31 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
 // hi = fp16(a, b) and lo = fp16 of the remainders, both round toward zero
 // (never overflows to infinity), packed two halves per word.
+// x - h for the FP16 half `SEL` of h, as one mixed-precision FMA
+// (x + (-h) * 1), or -x - h with NEG (the negation as a source modifier).
+// With h = x rounded toward zero to FP16 the difference has at most 13
+// significant bits, so it is exact in FP32.
+template <int SEL, bool NEG>
+__device__ __forceinline__ float sub_half(float x, uint32_t h) {
+  float r;
+  if constexpr (SEL == 0 && !NEG)
+    asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(x));
+  else if constexpr (SEL == 0)
+    asm("v_fma_mix_f32 %0, -%1, 1.0, -%2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(x));
+  else if constexpr (!NEG)
+    asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(x));
+  else
+    asm("v_fma_mix_f32 %0, -%1, 1.0, -%2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(x));
+  return r;
+}
+
+// hi = FP16 pair (a, b) rounded toward zero, lo = FP16 pair of the
+// remainders; with NEG the pair split is (-a, -b).
+template <bool NEG = false>
 __device__ __forceinline__ void split_h2(float a, float b, uint32_t& hi, uint32_t& lo) {
-  const auto h = __builtin_amdgcn_cvt_pkrtz(a, b);
-  const auto l = __builtin_amdgcn_cvt_pkrtz(a - (float)h[0], b - (float)h[1]);
-  hi = __builtin_bit_cast(uint32_t, h);
-  lo = __builtin_bit_cast(uint32_t, l);
+  hi = __builtin_bit_cast(uint32_t, NEG ? __builtin_amdgcn_cvt_pkrtz(-a, -b) : __builtin_amdgcn_cvt_pkrtz(a, b));
+  lo = __builtin_bit_cast(uint32_t,
+                          __builtin_amdgcn_cvt_pkrtz(sub_half<0, NEG>(a, hi), sub_half<1, NEG>(b, hi)));
 }
 
 __device__ __forceinline__ flt4 mma16(const uint32_t (&a)[4], const uint4& b, flt4 c) {
@@ -410,9 +430,11 @@ __device__ __forceinline__ flt4 mma16(const uint32_t (&a)[4], const uint4& b, fl
 // which is exactly its A fragment; the four lane groups then read adjacent
 // source records, on distinct LDS banks.  The step's density tile, its 32 source
 // records and the C_k window of the block (FP32 table of C_k / (pi dt)) reach LDS
-// by direct global-to-LDS loads issued one step ahead into the other of two
-// buffers; the steps alternate between two separate sets of LDS arrays so
-// that reads of one set never wait for the loads into the other.  In LDS the
+// by direct global-to-LDS loads issued two steps ahead; the steps cycle
+// through four separate sets of LDS arrays, so that reads of one set never
+// wait for the loads into another, and the block synchronises after every
+// second step (the loads for the next two steps are then complete, and the
+// two sets they overwrite have been read).  In LDS the
 // tile row (d, part, c) holds its four 16-byte chunks g at positions
 // g ^ ((row / 4) % 4), which keeps the 16 lanes reading one chunk of 16
 // consecutive rows on distinct banks.
@@ -422,9 +444,9 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
   constexpr int NC = 16 * NCB;
   constexpr int TQ = ND * 4 * NC * 4;      // uint4 per tile
   constexpr int NQ = TQ / 64;              // wave loads per tile
-  __shared__ uint4 Bt0[TQ], Bt1[TQ];
-  __shared__ uint4 Ss0[128], Ss1[128];     // 32 source records (64 bytes each)
-  __shared__ float Cs0[192], Cs1[192];     // C_k for k = kb .. kb + 159 (mod n)
+  __shared__ uint4 Bt0[TQ], Bt1[TQ], Bt2[TQ], Bt3[TQ];
+  __shared__ uint4 Ss0[128], Ss1[128], Ss2[128], Ss3[128];  // 32 source records (64 bytes each)
+  __shared__ float Cs0[192], Cs1[192], Cs2[192], Cs3[192];  // C_k for k = kb .. kb + 159 (mod n)
   const int n = p.n;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -471,8 +493,9 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
       Re[d][cb] = flt4{0, 0, 0, 0};
       Im[d][cb] = flt4{0, 0, 0, 0};
     }
-  auto step = [&](int st, const uint4* Bt, const uint4* Ss, const float* Cs, uint4* Btn, uint4* Ssn, float* Csn) {
-    if (st + 1 < nsteps) dma(st + 1, Btn, Ssn, Csn);
+  auto step = [&](int st, const uint4* Bt, const uint4* Ss, const float* Cs, uint4* Btn, uint4* Ssn, float* Csn,
+                  bool sync) {
+    if (st + 2 < nsteps) dma(st + 2, Btn, Ssn, Csn);
     const int jb = j0 + 32 * st;
     // A fragments: this lane's 8 pairs, hi and lo parts of Re K and Im K
     uint32_t arh[ND][4], arl[ND][4], aih[ND][4], ail[ND][4];
@@ -488,7 +511,12 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
-        split_h2(K[0][d].re, K[1][d].re, arh[d][e2], arl[d][e2]);
+        // the S-type value's real part is -A0 (pair_kernel_far32): split
+        // it from A0 with the negation as a source modifier
+        if (d == 0 && (OP == OP_S || OP == OP_HARD))
+          split_h2<true>(-K[0][d].re, -K[1][d].re, arh[d][e2], arl[d][e2]);
+        else
+          split_h2(K[0][d].re, K[1][d].re, arh[d][e2], arl[d][e2]);
         split_h2(K[0][d].im, K[1][d].im, aih[d][e2], ail[d][e2]);
       }
     }
@@ -546,14 +574,18 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
         }
       }
     }
-    // the next step's loads are complete and this step's reads are done
-    __syncthreads();
+    // after every second step: the loads of the next two steps are
+    // complete and the reads of the two buffer sets they replace are done
+    if (sync) __syncthreads();
   };
   dma(0, Bt0, Ss0, Cs0);
+  if (nsteps > 1) dma(1, Bt1, Ss1, Cs1);
   __syncthreads();
-  for (int st = 0; st < nsteps; st += 2) {
-    step(st, Bt0, Ss0, Cs0, Bt1, Ss1, Cs1);
-    if (st + 1 < nsteps) step(st + 1, Bt1, Ss1, Cs1, Bt0, Ss0, Cs0);
+  for (int st = 0; st < nsteps; st += 4) {
+    step(st, Bt0, Ss0, Cs0, Bt2, Ss2, Cs2, false);
+    if (st + 1 < nsteps) step(st + 1, Bt1, Ss1, Cs1, Bt3, Ss3, Cs3, true);
+    if (st + 2 < nsteps) step(st + 2, Bt2, Ss2, Cs2, Bt0, Ss0, Cs0, false);
+    if (st + 3 < nsteps) step(st + 3, Bt3, Ss3, Cs3, Bt1, Ss1, Cs1, true);
   }
   cplxf* part = p.partial32;
 #pragma unroll

@@ -97,8 +97,8 @@ __device__ __forceinline__ void pair_kernel_far(const Tgt& t, const SrcRec& s, d
 
 // ------------------------------------------------------------ mixed precision
 // FP32 kernel values: the geometry, r and the phase omega r are FP64 (the
-// phase is reduced modulo pi/2 in FP64 inside hankel01_far32), everything
-// after the reduction is FP32.  Near-field pairs are left to the FP64
+// phase, in quarter turns, is reduced in FP64 inside hankel01_far32w),
+// everything after the reduction is FP32.  Near-field pairs are left to the FP64
 // near-field pass, as in the FP64 sweep.
 template <int OP>
 struct Nd32 {
@@ -109,7 +109,8 @@ struct Nd32 {
 // powers of two (1 when unscaled): sc0 multiplies the Hankel values, and the
 // hard operator's second density takes the ratio sc1/sc0 in its factors.
 struct Far32 {
-  double omega, r2near;
+  double r2near;
+  double qt, qh;  // 2 omega / pi (quarter turns of phase per unit distance), omega / pi
   float sc0;   // scale of density 0 (applied to H0, H1)
   float om;    // omega
   float eta;   // eta
@@ -119,8 +120,9 @@ struct Far32 {
 
 __host__ __device__ inline Far32 far32_consts(double omega, double eta, double r2near, float sc0, float sc1) {
   Far32 f;
-  f.omega = omega;
   f.r2near = r2near;
+  f.qt = 2.0 * omega / kPi;
+  f.qh = omega / kPi;
   f.sc0 = sc0;
   f.om = (float)omega;
   f.eta = (float)eta;
@@ -142,31 +144,41 @@ __host__ __device__ inline Tgt32 tgt32(double nx, double ny, const Far32& f) {
   return Tgt32{(float)nx * o, (float)ny * o, (float)nx * f.g_r, (float)ny * f.g_r};
 }
 
+// max(a, b) for finite a and b as one instruction (fmax first quiets a
+// possible signaling NaN in a separate instruction).
+__device__ __forceinline__ double max_f64(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // Far-field pair with FP32 kernel values.  r comes from the FP32 reciprocal
 // square root y0 refined by one Newton step for sqrt in FP64 (relative error
-// ~1e-14), so the phase omega r keeps an absolute error below 1e-9 for
-// omega r < 5e4; 1/r in the FP32 factors is y0 itself.  The source's FP32
+// ~1e-14), computed directly in quarter turns, w = (2 omega / pi) r, so the
+// phase keeps an absolute error below 1e-9 for omega r < 5e4; 1/r in the
+// FP32 factors is y0 itself.  The source's FP32
 // weight wf = dt |x'_j| / 4 multiplies the Hankel values (h = wf H), and
 // rho = C_k / (pi dt) is the ratio of the Kress weight C_k |x'_j| / (4 pi) to
 // it, so the S-type and D-type values share
 //   A0 = Im h0 + rho Re h0,  B1 = Im h1 + rho Re h1
 // (S = -A0 + i Re h0, D' = omega nu_i.rhat (B1 - i Re h1)).  Pairs with zero
 // set (outside the caller's range) or in the near field (self pairs
-// included: r = 0) get wf = 0 and hence K = 0; their distance is replaced
-// by 1 so every value is finite.
+// included: r = 0) get wf = 0 and hence K = 0; their squared distance is
+// raised to at least r2near, which keeps every value finite and the argument
+// of the asymptotic branch at or above DP_HANKEL_ZA.
 template <int OP>
 __device__ __forceinline__ void pair_kernel_far32(const Tgt& t, const Tgt32& tf, const SrcRec& s, float rho,
                                                   bool zero, const Far32& f, cplxf* K) {
   const double dx = t.x - s.x, dy = t.y - s.y;
-  double r2 = pair_r2(t.x, t.y, s.x, s.y);
-  zero = zero || r2 < f.r2near;
-  r2 = zero ? 1.0 : r2;
+  const double r2p = pair_r2(t.x, t.y, s.x, s.y);
+  zero = zero || r2p < f.r2near;
+  const double r2 = max_f64(r2p, f.r2near);
   const float y0 = dp_rsqrtf((float)r2);
   const double yd = (double)y0;
   const double r0 = r2 * yd;
-  const double r = fma(0.5 * yd, fma(-r0, r0, r2), r0);
+  const double w = fma(yd * f.qh, fma(-r0, r0, r2), r0 * f.qt);  // (2 omega / pi) r
   const float wq = zero ? 0.0f : s.wf;
-  const H01f h = hankel01_far32(fmax(f.omega * r, DP_HANKEL_ZA), f.sc0 * wq);
+  const H01f h = hankel01_far32w(w, f.sc0 * wq);
   const float dxf = (float)dx, dyf = (float)dy;
   const float A0 = fmaf(rho, h.h0.re, h.h0.im);
   const float Sr = h.h0.re;
