@@ -520,59 +520,61 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
         split_h2(K[0][d].im, K[1][d].im, aih[d][e2], ail[d][e2]);
       }
     }
+    // Products, in groups of two column blocks (four independent
+    // accumulation chains) over (d, column pair); each group's B fragments
+    // are read from LDS one group ahead, while the previous group's products
+    // run (the scheduling barriers keep the reads from being hoisted into
+    // one batch that would wait for all of them).
+    constexpr int CP = NCB >= 2 ? 2 : 1;
+    constexpr int NG = NCB / CP;
+    uint4 bb[2][CP][4];
+    auto read_b = [&](int g, uint4 (&dst)[CP][4]) {
+      const int d = g / NG, cb0 = (g % NG) * CP;
 #pragma unroll
-    for (int d = 0; d < ND; ++d) {
+      for (int u = 0; u < CP; ++u) {
+        const int row = d * 4 * NC + (cb0 + u) * 16 + li;
+#pragma unroll
+        for (int part = 0; part < 4; ++part) dst[u][part] = Bt[(row + part * NC) * 4 + gsw];
+      }
+    };
+    read_b(0, bb[0]);
+#pragma unroll
+    for (int g = 0; g < ND * NG; ++g) {
+      const int d = g / NG, cb0 = (g % NG) * CP;
+      if (g + 1 < ND * NG) read_b(g + 1, bb[(g + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);
       uint32_t nih[4], nil[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         nih[e] = aih[d][e] ^ 0x80008000u;
         nil[e] = ail[d][e] ^ 0x80008000u;
       }
-      // two column blocks at a time (four independent accumulation chains);
-      // the next pair's B fragments are read from LDS while this pair's
-      // products run
-      constexpr int CP = NCB >= 2 ? 2 : 1;
-      constexpr int NG = NCB / CP;
-      uint4 bb[2][CP][4];
-      auto read_b = [&](int cb0, uint4 (&dst)[CP][4]) {
+      const uint4 (&B)[CP][4] = bb[g & 1];
+      flt4 r[CP], m[CP];
 #pragma unroll
-        for (int u = 0; u < CP; ++u) {
-          const int row = d * 4 * NC + (cb0 + u) * 16 + li;
-#pragma unroll
-          for (int part = 0; part < 4; ++part) dst[u][part] = Bt[(row + part * NC) * 4 + gsw];
-        }
-      };
-      read_b(0, bb[0]);
-#pragma unroll
-      for (int gq = 0; gq < NG; ++gq) {
-        const int cb0 = gq * CP;
-        if (gq + 1 < NG) read_b(cb0 + CP, bb[(gq + 1) & 1]);
-        const uint4 (&B)[CP][4] = bb[gq & 1];
-        flt4 r[CP], m[CP];
-#pragma unroll
-        for (int u = 0; u < CP; ++u) {
-          r[u] = Re[d][cb0 + u];
-          m[u] = Im[d][cb0 + u];
-        }
-        // parts: 0 re hi, 1 re lo, 2 im hi, 3 im lo
+      for (int u = 0; u < CP; ++u) {
+        r[u] = Re[d][cb0 + u];
+        m[u] = Im[d][cb0 + u];
+      }
+      // parts: 0 re hi, 1 re lo, 2 im hi, 3 im lo
 #define DP_MMA2(AR, PR, AI, PI)                    \
   _Pragma("unroll") for (int u = 0; u < CP; ++u) { \
     r[u] = mma16(AR, B[u][PR], r[u]);              \
     m[u] = mma16(AI, B[u][PI], m[u]);              \
   }
-        DP_MMA2(arh[d], 0, arh[d], 2)
-        DP_MMA2(arh[d], 1, arh[d], 3)
-        DP_MMA2(arl[d], 0, arl[d], 2)
-        DP_MMA2(nih, 2, aih[d], 0)
-        DP_MMA2(nih, 3, aih[d], 1)
-        DP_MMA2(nil, 2, ail[d], 0)
+      DP_MMA2(arh[d], 0, arh[d], 2)
+      DP_MMA2(arh[d], 1, arh[d], 3)
+      DP_MMA2(arl[d], 0, arl[d], 2)
+      DP_MMA2(nih, 2, aih[d], 0)
+      DP_MMA2(nih, 3, aih[d], 1)
+      DP_MMA2(nil, 2, ail[d], 0)
 #undef DP_MMA2
 #pragma unroll
-        for (int u = 0; u < CP; ++u) {
-          Re[d][cb0 + u] = r[u];
-          Im[d][cb0 + u] = m[u];
-        }
+      for (int u = 0; u < CP; ++u) {
+        Re[d][cb0 + u] = r[u];
+        Im[d][cb0 + u] = m[u];
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
     // after every second step: the loads of the next two steps are
     // complete and the reads of the two buffer sets they replace are done
