@@ -126,6 +126,9 @@ typedef struct {
   int graphs;      /* 1: after the first dp_precond_apply with a given column count,
                       capture the apply's kernels into a HIP graph and replay it;
                       0: launch them one by one; default 1 */
+  int gj_steps;    /* Gauss-Jordan steps per launch in the inversions of the size-class
+                      blocks B_s and S_s: 0 = automatic (up to 8, as the panel fits in
+                      LDS), k > 0 = at most k (1 = one launch per step); default 0 */
 } dp_precond_opts;
 
 typedef struct {

@@ -44,7 +44,7 @@ class DpError(RuntimeError):
 class PrecondOpts(ctypes.Structure):
     _fields_ = [("m_ell", ctypes.c_double), ("min_pts", ctypes.c_int),
                 ("m_c", ctypes.c_int), ("t_keep", ctypes.c_double), ("w_solver", ctypes.c_int),
-                ("graphs", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("gj_steps", ctypes.c_int)]
 
 
 class PrecondInfo(ctypes.Structure):
@@ -292,8 +292,8 @@ def dp_layer_apply(p, op, q, y):
 W_AUTO, W_SPARSE, W_DENSE = 0, 1, 2
 
 
-def dp_precond_build(p, m_ell=4.0, min_pts=8, m_c=10, t_keep=3.0, w_solver=W_AUTO, graphs=True):
-    o = PrecondOpts(m_ell, min_pts, m_c, t_keep, int(w_solver), 1 if graphs else 0)
+def dp_precond_build(p, m_ell=4.0, min_pts=8, m_c=10, t_keep=3.0, w_solver=W_AUTO, graphs=True, gj_steps=0):
+    o = PrecondOpts(m_ell, min_pts, m_c, t_keep, int(w_solver), 1 if graphs else 0, int(gj_steps))
     _check("dp_precond_build", lib().dp_precond_build(p.h, ctypes.byref(o)))
 
 

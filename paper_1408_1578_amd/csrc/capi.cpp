@@ -253,10 +253,10 @@ int dp_autotune(dp_problem* p, int64_t nrhs, int precision, dp_tune_info* info) 
 int dp_precond_build(dp_problem* p, const dp_precond_opts* opts) {
   DP_CHECK(p != nullptr, "dp_precond_build: NULL problem");
   DP_CHECK(p->equispaced, "dp_precond_build: nodes must be arclength-equispaced (equal weights)");
-  dp_precond_opts o = {4.0, 8, 10, 3.0, 0, 1};
+  dp_precond_opts o = {4.0, 8, 10, 3.0, 0, 1, 0};
   if (opts) o = *opts;
   DP_CHECK(o.m_ell > 0 && o.min_pts >= 2 && o.m_c >= 2 && o.m_c <= 32 && o.t_keep >= 0 && o.w_solver >= 0 &&
-               o.w_solver <= 2 && (o.graphs == 0 || o.graphs == 1),
+               o.w_solver <= 2 && (o.graphs == 0 || o.graphs == 1) && o.gj_steps >= 0,
            "dp_precond_build: bad options");
   DP_SETDEV(p->ctx);
   return precond_build(p, &o);

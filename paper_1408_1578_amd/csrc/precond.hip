@@ -185,6 +185,7 @@ struct GJMat {
   cplx* a[2];
   cplx* col[2];  // contiguous copies of the pivot column of buffer k % 2 (column k)
   int s;
+  int res;       // set by gj_invert: the buffer a[res] that holds the result
 };
 struct GJBatch {
   GJMat m[8];
@@ -272,6 +273,176 @@ __global__ __launch_bounds__(256) void gj_step(GJBatch b, int k) {
   }
 }
 
+// Gauss–Jordan steps k .. k + nb - 1 (nb = min(nbw, s - k)) of [A | I] in
+// one launch; block (i, q) writes row i of matrix q from buffer `par` into the
+// other one.  Every block repeats, in LDS, the partial-pivoting elimination
+// of the panel (columns k .. k + nb - 1 of the rows k .. s - 1).  Its pivots
+// are the ones the step-by-step elimination chooses (largest modulus of the
+// updated column, ties to the lower row; eliminating the rows above k does not
+// change them), and its factors P_R = L_R U (P_R: the panel of the pivot rows
+// in pivot order, L_R unit lower, U upper, nb x nb) give the rows after the nb
+// steps directly: pivot row t becomes e_t U^-1 L_R^-1 times the old pivot
+// rows, and any other row x its old row minus P_x U^-1 L_R^-1 times them
+// (P_x: its panel).  Only the columns past the panel are written: the panel's
+// own columns have become unit columns and are not read again.
+constexpr int kGJPanel = 8;
+
+__global__ __launch_bounds__(256) void gj_panel(GJBatch b, int k, int par, int nbw) {
+  const GJMat M = b.m[blockIdx.y];
+  const int s = M.s;
+  const int i = blockIdx.x;  // this block's row
+  if (k >= s || i >= s) return;
+  const int nb = min(nbw, s - k);
+  const int w = 2 * s;
+  const int m = s - k;  // candidate rows k .. s - 1, local index r = row - k
+  const cplx* A = M.a[par];
+  cplx* O = M.a[par ^ 1];
+  extern __shared__ double gj_lds[];
+  cplx* V = reinterpret_cast<cplx*>(gj_lds);                // m x nbw panel, row-major
+  int* orig = reinterpret_cast<int*>(V + (size_t)m * nbw);  // old row at each local position
+  __shared__ cplx g[kGJPanel];  // coefficients of the old pivot rows in this block's row
+  __shared__ int R[kGJPanel];   // old pivot rows, in pivot order
+  __shared__ double bv[4];
+  __shared__ int bi[4];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < m * nb; e += 256) {
+    const int r = e / nb, t = e - r * nb;
+    V[r * nbw + t] = A[(size_t)(k + r) * w + k + t];
+  }
+  for (int r = tid; r < m; r += 256) orig[r] = k + r;
+  __syncthreads();
+  for (int t = 0; t < nb; ++t) {
+    // pivot: wave-level argmax (ties to the lower row), then across the 4 waves
+    double best = -1.0;
+    int bidx = m;
+    for (int r = t + tid; r < m; r += 256) {
+      const cplx a = V[r * nbw + t];
+      const double q = a.re * a.re + a.im * a.im;
+      if (q > best) {
+        best = q;
+        bidx = r;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bidx, off);
+      if (o > best || (o == best && oi < bidx)) {
+        best = o;
+        bidx = oi;
+      }
+    }
+    if ((tid & 63) == 0) {
+      bv[tid >> 6] = best;
+      bi[tid >> 6] = bidx;
+    }
+    __syncthreads();
+    best = bv[0];
+    int p = bi[0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+      if (bv[q] > best || (bv[q] == best && bi[q] < p)) {
+        best = bv[q];
+        p = bi[q];
+      }
+    if (!(best > 0.0)) {  // the same in every thread and block of this matrix
+      if (i == 0 && tid == 0) b.status[blockIdx.y] = 1;
+      return;
+    }
+    if (p != t) {
+      if (tid < nb) {
+        const cplx x = V[p * nbw + tid];
+        V[p * nbw + tid] = V[t * nbw + tid];
+        V[t * nbw + tid] = x;
+      }
+      if (tid == 0) {
+        const int x = orig[p];
+        orig[p] = orig[t];
+        orig[t] = x;
+      }
+    }
+    __syncthreads();
+    // eliminate column t below the pivot in the panel's later columns; the
+    // column itself keeps the unnormalised multipliers (L = V / U_tt)
+    const int nc = nb - t - 1;
+    if (nc > 0) {
+      const cplx pv = V[t * nbw + t];
+      const double den = pv.re * pv.re + pv.im * pv.im;
+      const cplx inv = {pv.re / den, -pv.im / den};
+      for (int e = tid; e < (m - t - 1) * nc; e += 256) {
+        const int r = t + 1 + e / nc, u = t + 1 + e % nc;
+        const cplx l = cmul(V[r * nbw + t], inv);
+        const cplx pu = V[t * nbw + u];
+        cplx& x = V[r * nbw + u];
+        x = {x.re - (l.re * pu.re - l.im * pu.im), x.im - (l.re * pu.im + l.im * pu.re)};
+      }
+    }
+    __syncthreads();
+  }
+  // in parallel: 1/U_uu, L_R (below the diagonal) and the right-hand side
+  // (e_t for pivot row t, else the panel of the old source row)
+  __shared__ cplx Lr[kGJPanel * kGJPanel], invd[kGJPanel], rhs[kGJPanel];
+  const bool piv = i >= k && i < k + nb;
+  const int src = piv ? 0 : (i < k ? i : orig[i - k]);
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int r = e / nb, u = e - r * nb;
+    const cplx d = V[u * nbw + u];
+    const double den = d.re * d.re + d.im * d.im;
+    const cplx inv = {d.re / den, -d.im / den};
+    if (r > u) Lr[e] = cmul(V[r * nbw + u], inv);
+    if (r == u) invd[u] = inv;
+  }
+  if (tid < nb) rhs[tid] = piv ? cplx{tid == i - k ? 1.0 : 0.0, 0.0} : A[(size_t)src * w + k + tid];
+  __syncthreads();
+  if (tid == 0) {
+    // y U = rhs, then c L_R = y; the row is alpha (old source row) + g (old pivot rows)
+    cplx y[kGJPanel], c[kGJPanel];
+    for (int u = 0; u < nb; ++u) {
+      cplx acc = rhs[u];
+      for (int v = 0; v < u; ++v) {
+        const cplx uv = V[v * nbw + u];
+        acc = {acc.re - (y[v].re * uv.re - y[v].im * uv.im), acc.im - (y[v].re * uv.im + y[v].im * uv.re)};
+      }
+      y[u] = cmul(acc, invd[u]);
+    }
+    for (int u = nb - 1; u >= 0; --u) {
+      cplx acc = y[u];
+      for (int r = u + 1; r < nb; ++r) {
+        const cplx l = Lr[r * nb + u];
+        acc = {acc.re - (c[r].re * l.re - c[r].im * l.im), acc.im - (c[r].re * l.im + c[r].im * l.re)};
+      }
+      c[u] = acc;
+    }
+    for (int u = 0; u < nb; ++u) {
+      g[u] = piv ? c[u] : cplx{-c[u].re, -c[u].im};
+      R[u] = orig[u];
+    }
+  }
+  __syncthreads();
+  const double alpha = piv ? 0.0 : 1.0;
+  const cplx* srow = A + (size_t)src * w;
+  cplx* orow = O + (size_t)i * w;
+  cplx gg[kGJPanel];
+  const cplx* prow[kGJPanel];
+#pragma unroll
+  for (int u = 0; u < kGJPanel; ++u) {
+    gg[u] = u < nb ? g[u] : cplx{0.0, 0.0};
+    prow[u] = A + (size_t)(u < nb ? R[u] : R[0]) * w;
+  }
+  for (int c = k + nb + tid; c < w; c += 256) {
+    const cplx x = srow[c];
+    cplx v = {alpha * x.re, alpha * x.im};
+#pragma unroll
+    for (int u = 0; u < kGJPanel; ++u) {
+      if (u < nb) {
+        const cplx pr = prow[u][c];
+        v = {v.re + (gg[u].re * pr.re - gg[u].im * pr.im), v.im + (gg[u].re * pr.im + gg[u].im * pr.re)};
+      }
+    }
+    orow[c] = v;
+  }
+}
+
 // col[i] = A[i][0] of a row-major matrix with w columns
 __global__ void copy_column(const cplx* __restrict__ A, cplx* col, int rows, int w) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -289,27 +460,42 @@ __global__ void augment_identity(const cplx* __restrict__ S, cplx* A, int K) {
 }
 
 // Inverts any number of matrices, eight per batch.
-static int gj_batch(hipStream_t st, GJBatch& b, int count, DevBuf& status);
-static int gj_invert(hipStream_t st, const std::vector<GJMat>& mats, DevBuf& status) {
+static int gj_batch(hipStream_t st, GJBatch& b, int count, DevBuf& status, int cap);
+// cap: at most this many steps per launch (0: as many as fit, up to kGJPanel)
+static int gj_invert(hipStream_t st, std::vector<GJMat>& mats, DevBuf& status, int cap) {
   for (size_t q0 = 0; q0 < mats.size(); q0 += 8) {
     GJBatch b{};
     const int count = (int)std::min<size_t>(8, mats.size() - q0);
     for (int q = 0; q < count; ++q) b.m[q] = mats[q0 + q];
-    DP_TRY(gj_batch(st, b, count, status));
+    DP_TRY(gj_batch(st, b, count, status, cap));
+    for (int q = 0; q < count; ++q) mats[q0 + q].res = b.m[q].res;
   }
   return DP_OK;
 }
 
 // Inverts the batch (at most 8 matrices): one launch per step of the largest.
-static int gj_batch(hipStream_t st, GJBatch& b, int count, DevBuf& status) {
+static int gj_batch(hipStream_t st, GJBatch& b, int count, DevBuf& status, int cap) {
   DP_TRY(status.reserve(8 * sizeof(int)));
   b.status = status.as<int>();
   DP_HIP(hipMemsetAsync(b.status, 0, 8 * sizeof(int), st));
   int smax = 0;
   for (int q = 0; q < count; ++q) smax = std::max(smax, b.m[q].s);
-  for (int q = 0; q < count; ++q)  // pivot column of step 0
-    copy_column<<<(b.m[q].s + 255) / 256, 256, 0, st>>>(b.m[q].a[0], b.m[q].col[0], b.m[q].s, 2 * b.m[q].s);
-  for (int k = 0; k < smax; ++k) gj_step<<<dim3(smax, count), 256, 0, st>>>(b, k);
+  // panel width: the panel and the row map of the largest matrix in 63 KB of
+  // LDS (with the kernel's own small arrays, under 64 KB)
+  int nbw = cap > 0 ? std::min(cap, kGJPanel) : kGJPanel;
+  while (nbw > 1 && (size_t)smax * (16 * nbw + 4) > 63 * 1024) nbw /= 2;
+  if (nbw >= 2) {
+    const size_t lds = (size_t)smax * (16 * nbw + 4);
+    int launches = 0;
+    for (int k = 0; k < smax; k += nbw, ++launches)
+      gj_panel<<<dim3(smax, count), 256, lds, st>>>(b, k, launches & 1, nbw);
+    for (int q = 0; q < count; ++q) b.m[q].res = ((b.m[q].s + nbw - 1) / nbw) & 1;
+  } else {  // one launch per step
+    for (int q = 0; q < count; ++q)  // pivot column of step 0
+      copy_column<<<(b.m[q].s + 255) / 256, 256, 0, st>>>(b.m[q].a[0], b.m[q].col[0], b.m[q].s, 2 * b.m[q].s);
+    for (int k = 0; k < smax; ++k) gj_step<<<dim3(smax, count), 256, 0, st>>>(b, k);
+    for (int q = 0; q < count; ++q) b.m[q].res = b.m[q].s & 1;
+  }
   DP_HIP(hipGetLastError());
   int h[8] = {0};
   DP_HIP(hipMemcpyAsync(h, b.status, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1173,19 +1359,19 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     flat_row<<<(s + 255) / 256, 256, 0, st>>>(p->C.as<double>(), row.as<cplx>(), s, n, L, omega, p->eta, p->kind);
     toeplitz_aug<<<grid1((size_t)s * 2 * s), 256, 0, st>>>(row.as<cplx>(), augB[2 * ci].as<cplx>(), s);
     gb[ci] = GJMat{{augB[2 * ci].as<cplx>(), augB[2 * ci + 1].as<cplx>()},
-                   {colB[2 * ci].as<cplx>(), colB[2 * ci + 1].as<cplx>()}, s};
+                   {colB[2 * ci].as<cplx>(), colB[2 * ci + 1].as<cplx>()}, s, 0};
     // the next class's flat row must not overwrite this one before it is read
     DP_HIP(hipStreamSynchronize(st));
   }
   {
     int rc;
-    if ((rc = gj_invert(st, gb, gstat))) return fail(rc);
+    if ((rc = gj_invert(st, gb, gstat, o->gj_steps))) return fail(rc);
   }
   std::vector<GJMat> gs(ncls);
   for (int ci = 0; ci < ncls; ++ci) {
     SizeClass& c = P->classes[ci];
     const int s = c.s, K = c.K;
-    copy_right_half<<<grid1((size_t)s * s), 256, 0, st>>>(augB[2 * ci + (s & 1)].as<cplx>(), c.Binv.as<cplx>(), s);
+    copy_right_half<<<grid1((size_t)s * s), 256, 0, st>>>(augB[2 * ci + gb[ci].res].as<cplx>(), c.Binv.as<cplx>(), s);
     augB[2 * ci].release();
     augB[2 * ci + 1].release();
     int rc;
@@ -1200,18 +1386,18 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     dense_gemm<<<grid1((size_t)K * K), 256, 0, st>>>(c.Ut.as<cplx>(), X.as<cplx>(), S.as<cplx>(), K, K, s);
     augment_identity<<<grid1((size_t)K * 2 * K), 256, 0, st>>>(S.as<cplx>(), augS[2 * ci].as<cplx>(), K);
     gs[ci] = GJMat{{augS[2 * ci].as<cplx>(), augS[2 * ci + 1].as<cplx>()},
-                   {colS[2 * ci].as<cplx>(), colS[2 * ci + 1].as<cplx>()}, K};
+                   {colS[2 * ci].as<cplx>(), colS[2 * ci + 1].as<cplx>()}, K, 0};
     // X and S are reused by the next class
     DP_HIP(hipStreamSynchronize(st));
   }
   {
     int rc;
-    if ((rc = gj_invert(st, gs, gstat))) return fail(rc);
+    if ((rc = gj_invert(st, gs, gstat, o->gj_steps))) return fail(rc);
   }
   for (int ci = 0; ci < ncls; ++ci) {
     SizeClass& c = P->classes[ci];
     const int s = c.s, K = c.K;
-    copy_right_half<<<grid1((size_t)K * K), 256, 0, st>>>(augS[2 * ci + (K & 1)].as<cplx>(), c.Tt.as<cplx>(), K);
+    copy_right_half<<<grid1((size_t)K * K), 256, 0, st>>>(augS[2 * ci + gs[ci].res].as<cplx>(), c.Tt.as<cplx>(), K);
     c.T.resize((size_t)K * K);
     DP_HIP(hipMemcpyAsync(c.T.data(), c.Tt.p, c.T.size() * sizeof(cplx), hipMemcpyDeviceToHost, st));
     DP_HIP(hipStreamSynchronize(st));

@@ -48,6 +48,20 @@ def test_apply_parity(cfg, n, kind):
         assert relerr(to_host(z), pc.apply(P, v)) < 1e-10
 
 
+@pytest.mark.parametrize("gj_steps", [1, 2, 3, 4, 8])
+def test_apply_parity_gauss_jordan_panels(gj_steps):
+    # the size-class inverses with each panel width of the batched
+    # Gauss-Jordan elimination (1: one launch per step; 3: a ragged last panel)
+    b, om, eta, _ = config_boundary("kite", 4096)
+    P = pc.build(b, om, eta, 1)
+    p = problem(b, om, eta, 1)
+    dp.dp_precond_build(p, gj_steps=gj_steps)
+    v = random_density(b.n, 5, seed=4)
+    z = empty(b.n, 5)
+    dp.dp_precond_apply(p, to_dev(v), z)
+    assert relerr(to_host(z), pc.apply(P, v)) < 1e-10
+
+
 @pytest.mark.parametrize("cfg,n,kind", [("star", 4096, 0), ("kite", 4096, 1)])
 def test_preconditioned_solve(cfg, n, kind):
     b, om, eta, P, p = _setup(cfg, n, kind)
