@@ -25,29 +25,54 @@ constexpr int kDotRows = 2048;
 __global__ __launch_bounds__(256) void gram_dots(const cplx* __restrict__ V, size_t vstride,
                                                  const cplx* __restrict__ W, int n, int nrhs, int kp1,
                                                  cplx* __restrict__ partial) {
-  __shared__ cplx red[256];
+  // eight basis vectors per pass over the rows; each sum is reduced within
+  // its wave by a fixed butterfly, then over the four waves in order
+  constexpr int G = 8;
+  __shared__ cplx red[4][G];
   const int c = blockIdx.y;
   const int j0 = blockIdx.x * kDotRows;
   const int j1 = min(n, j0 + kDotRows);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const cplx* w = W + (size_t)c * n;
-  for (int i = 0; i < kp1; ++i) {
-    const cplx* v = V + i * vstride + (size_t)c * n;
-    cplx s = {0.0, 0.0};
+  for (int i0 = 0; i0 < kp1; i0 += G) {
+    const int g = min(G, kp1 - i0);
+    cplx s[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) s[u] = {0.0, 0.0};
     for (int j = j0 + threadIdx.x; j < j1; j += 256) {
-      const cplx a = v[j], b = w[j];
-      s.re = fma(a.re, b.re, fma(a.im, b.im, s.re));
-      s.im = fma(a.re, b.im, fma(-a.im, b.re, s.im));
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (threadIdx.x < st) {
-        red[threadIdx.x].re += red[threadIdx.x + st].re;
-        red[threadIdx.x].im += red[threadIdx.x + st].im;
+      const cplx b = w[j];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        if (u < g) {
+          const cplx a = V[(i0 + u) * vstride + (size_t)c * n + j];
+          s[u].re = fma(a.re, b.re, fma(a.im, b.im, s[u].re));
+          s[u].im = fma(a.re, b.im, fma(-a.im, b.re, s[u].im));
+        }
       }
-      __syncthreads();
     }
-    if (threadIdx.x == 0) partial[((size_t)blockIdx.x * kp1 + i) * nrhs + c] = red[0];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        s[u].re += __shfl_xor(s[u].re, off);
+        s[u].im += __shfl_xor(s[u].im, off);
+      }
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < G; ++u) red[wv][u] = s[u];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < g) {
+      const int u = threadIdx.x;
+      cplx t = red[0][u];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) {
+        t.re += red[q][u].re;
+        t.im += red[q][u].im;
+      }
+      partial[((size_t)blockIdx.x * kp1 + i0 + u) * nrhs + c] = t;
+    }
     __syncthreads();
   }
 }

@@ -886,6 +886,156 @@ __global__ __launch_bounds__(256) void seg_gemm_mfma32(SegGemm<cplxf> g) {
   }
 }
 
+// Single-precision batched per-segment complex GEMM on the BF16 matrix cores.
+// Every FP32 operand x is cut, by truncating masks, into three BF16 pieces
+// x = h + m + l exactly (8 significant bits each); a real product keeps the
+// six piece products of level h = 0, m = 1, l = 2 up to 2 (dropped terms are
+// 2^-24 relative, like FP32 rounding) with FP32 accumulation, on
+// v_mfma_f32_16x16x32_bf16 (A[i][k] in lane i + 16 (k / 8), element k % 8;
+// B[k][c] in lane c + 16 (k / 8); D[i][c] in register i % 4 of lane
+// c + 16 (i / 4)).  Grid (segment, row tile of 64, column tile of 64);
+// 4 waves, each 16 rows x 64 columns; per 32-deep slice the A and X tiles
+// are split into LDS as [piece][re/im][row or column][32 k], the four 16-byte
+// chunks of a row stored at chunk ^ ((row / 4) % 4) so that 16 lanes reading
+// one chunk of 16 rows hit distinct banks.
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split3_bf16(float x, uint32_t& h, uint32_t& m, uint32_t& l) {
+  const uint32_t xb = __builtin_bit_cast(uint32_t, x);
+  const float hf = __builtin_bit_cast(float, xb & 0xffff0000u);
+  const float r = x - hf;  // exact: at most 16 significant bits remain
+  const uint32_t rb = __builtin_bit_cast(uint32_t, r);
+  const float mf = __builtin_bit_cast(float, rb & 0xffff0000u);
+  const float lf = r - mf;  // exact, and exactly a BF16 value
+  h = xb >> 16;
+  m = rb >> 16;
+  l = __builtin_bit_cast(uint32_t, lf) >> 16;
+}
+
+__device__ __forceinline__ flt4v mma_bf16(const uint4& a, const uint4& b, flt4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8v, a), __builtin_bit_cast(bf16x8v, b), c,
+                                                 0, 0, 0);
+}
+
+__global__ __launch_bounds__(256) void seg_gemm_bf16x3(SegGemm<cplxf> g) {
+  // [piece 3][re, im][64 rows or columns][16 words of two k]
+  __shared__ __align__(16) uint32_t As[3][2][64][16];
+  __shared__ __align__(16) uint32_t Xs[3][2][64][16];
+  const int sg = blockIdx.x;
+  const int off = g.segs[4 * sg], offK = g.segs[4 * sg + 2], cls = g.segs[4 * sg + 3];
+  const int s = g.dims[2 * cls], K = g.dims[2 * cls + 1];
+  const int M = g.mrows ? K : s;
+  const int Kd = g.kin ? K : s;
+  const int r0 = blockIdx.y * 64;
+  if (r0 >= M) return;
+  const int c0 = blockIdx.z * 64;
+  const cplxf* A = g.A[cls];
+  const int xo = g.kin ? offK : off;
+  const int yo = g.yoff ? offK : off;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  flt4v re[4], im[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    re[cb] = flt4v{0, 0, 0, 0};
+    im[cb] = flt4v{0, 0, 0, 0};
+  }
+  // each thread moves two consecutive k of four rows of A and four columns
+  // of X per slice (word kp = k / 2 of row rr); the next slice is requested
+  // before the current one's products
+  cplxf ra[4][2], rx[4][2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e >> 4, kp = e & 15;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = k0 + 2 * kp + h;
+        const int r = r0 + rr, c = c0 + rr;
+        ra[q][h] = (r < M && k < Kd) ? A[(size_t)r * Kd + k] : cplxf{0, 0};
+        rx[q][h] = (k < Kd && c < g.nrhs) ? g.X[(size_t)c * g.ldx + xo + k] : cplxf{0, 0};
+      }
+    }
+  };
+  auto put = [&](uint32_t (&T)[3][2][64][16], int rr, int kp, const cplxf (&v)[2]) {
+    const int pos = (((kp >> 2) ^ ((rr >> 2) & 3)) << 2) | (kp & 3);
+    uint32_t h0, m0, l0, h1, m1, l1;
+    split3_bf16(v[0].re, h0, m0, l0);
+    split3_bf16(v[1].re, h1, m1, l1);
+    T[0][0][rr][pos] = h0 | (h1 << 16);
+    T[1][0][rr][pos] = m0 | (m1 << 16);
+    T[2][0][rr][pos] = l0 | (l1 << 16);
+    split3_bf16(v[0].im, h0, m0, l0);
+    split3_bf16(v[1].im, h1, m1, l1);
+    T[0][1][rr][pos] = h0 | (h1 << 16);
+    T[1][1][rr][pos] = m0 | (m1 << 16);
+    T[2][1][rr][pos] = l0 | (l1 << 16);
+  };
+  auto frag = [&](const uint32_t (&T)[3][2][64][16], int pc, int part, int rr) {
+    const int pos = (lk ^ ((rr >> 2) & 3)) << 2;
+    return *reinterpret_cast<const uint4*>(&T[pc][part][rr][pos]);
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < Kd; k0 += 32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      put(As, e >> 4, e & 15, ra[q]);
+      put(Xs, e >> 4, e & 15, rx[q]);
+    }
+    __syncthreads();
+    if (k0 + 32 < Kd) fetch(k0 + 32);
+    uint4 ar[3], ai[3], an[3];
+#pragma unroll
+    for (int pc = 0; pc < 3; ++pc) {
+      ar[pc] = frag(As, pc, 0, 16 * w + li);
+      ai[pc] = frag(As, pc, 1, 16 * w + li);
+      an[pc] = uint4{ai[pc].x ^ 0x80008000u, ai[pc].y ^ 0x80008000u, ai[pc].z ^ 0x80008000u,
+                     ai[pc].w ^ 0x80008000u};
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      uint4 xr[3], xi[3];
+#pragma unroll
+      for (int pc = 0; pc < 3; ++pc) {
+        xr[pc] = frag(Xs, pc, 0, 16 * cb + li);
+        xi[pc] = frag(Xs, pc, 1, 16 * cb + li);
+      }
+      // piece pairs (a, x) with level a + x <= 2
+#pragma unroll
+      for (int pa = 0; pa < 3; ++pa) {
+#pragma unroll
+        for (int px = 0; px + pa < 3; ++px) {
+          re[cb] = mma_bf16(ar[pa], xr[px], re[cb]);
+          im[cb] = mma_bf16(ar[pa], xi[px], im[cb]);
+          re[cb] = mma_bf16(an[pa], xi[px], re[cb]);
+          im[cb] = mma_bf16(ai[pa], xr[px], im[cb]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int c = c0 + 16 * cb + li;
+    if (c >= g.nrhs) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + 16 * w + 4 * lk + r;
+      if (row >= M) continue;
+      const size_t o = (size_t)c * g.ldy + yo + row;
+      if (g.mode == 1) {
+        const cplxf z = g.Z[o];
+        g.Y[o] = {z.re - re[cb][r], z.im - im[cb][r]};
+      } else {
+        g.Y[o] = {re[cb][r], im[cb][r]};
+      }
+    }
+  }
+}
+
 // precision conversions of n-element complex arrays
 __global__ void to_single(const cplx* __restrict__ a, cplxf* b, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -1568,7 +1718,7 @@ static int run_seg_gemm(dp_problem* p, int which, int mrows, int kin, int yoff, 
   if constexpr (sizeof(C) == sizeof(cplxf)) {
     if (nrhs >= 16) {
       dim3 grid(P->m, (maxM + 63) / 64, (nrhs + 63) / 64);
-      seg_gemm_mfma32<<<grid, 256, 0, p->ctx->stream>>>(g);
+      seg_gemm_bf16x3<<<grid, 256, 0, p->ctx->stream>>>(g);
       DP_HIP(hipGetLastError());
       return DP_OK;
     }
