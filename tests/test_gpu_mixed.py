@@ -17,7 +17,7 @@ TOL32 = 1e-5
 
 
 @pytest.mark.parametrize("cfg,n,nrhs", [("disk", 1024, 1), ("disk", 1024, 3), ("disk", 1024, 70),
-                                        ("kite", 1024, 16), ("kite", 2048, 64)])
+                                        ("kite", 1024, 16), ("kite", 2048, 64), ("disk", 1000, 64)])
 def test_mixed_operator(cfg, n, nrhs):
     b = sample_boundary(cfg, n)
     om = 100.0 if cfg == "disk" else omega_for_ppw(n, b.L, 10.0)
