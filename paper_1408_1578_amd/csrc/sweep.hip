@@ -892,9 +892,8 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   e.eta = p->eta;
   e.dt = sp.dt;
   e.R0 = p->R0;
-  // two rows per thread (n is even)
-  if (part32) sweep_epilogue2<cplxf><<<grid1d((size_t)(n / 2) * nrhs), 256, 0, st>>>(e);
-  else sweep_epilogue2<cplx><<<grid1d((size_t)(n / 2) * nrhs), 256, 0, st>>>(e);
+  if (part32) sweep_epilogue<cplxf><<<grid1d((size_t)n * nrhs), 256, 0, st>>>(e);
+  else sweep_epilogue<cplx><<<grid1d((size_t)n * nrhs), 256, 0, st>>>(e);
   DP_HIP(hipGetLastError());
   return DP_OK;
 }

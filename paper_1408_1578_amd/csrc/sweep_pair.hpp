@@ -217,97 +217,66 @@ struct EpiParams {
   double omega, eta, dt, R0;
 };
 
-// Diagonal (Kress limits, per-row table) and identity terms of row i, column
-// c, added to the off-diagonal sums in FP64; writes the result(s).
-__device__ __forceinline__ void epi_finish(const EpiParams& e, int i, int c, cplx (&sum)[2]) {
-  const double4 dg = e.diag[i];  // S_ii (re, im), D_ii = D'_ii
-  const cplx Sii = {dg.x, dg.y};
-  const double Dii = dg.z;
-  const size_t o = (size_t)(e.col0 + c) * e.n + i;
-  const cplx qi = e.q[o];
-  if (e.op == OP_SOFT) {
-    // (1/2 + D_ii - i eta S_ii) q_i
-    const cplx a = {0.5 + Dii + e.eta * Sii.im, -e.eta * Sii.re};
-    cfma(sum[0], a, qi);
-    e.out0[o] = sum[0];
-  } else if (e.op == OP_S) {
-    cfma(sum[0], Sii, qi);
-    e.out0[o] = sum[0];
-  } else if (e.op == OP_D || e.op == OP_DP) {
-    cfma(sum[0], cplx{Dii, 0.0}, qi);
-    e.out0[o] = sum[0];
-  } else {
-    const cplx s1 = e.q2[o];
-    cfma(sum[0], Sii, s1);
-    // G_ii = -i (omega^2/eta) S_ii - D'_ii
-    const double g = e.omega * e.omega / e.eta;
-    cfma(sum[1], cplx{g * Sii.im - Dii, -g * Sii.re}, qi);
-    e.out0[o] = sum[0];
-    e.out1[o] = sum[1];
-  }
-}
-
 // Sum the near-field sums and the chunk partials (FP64 or FP32), add the
 // diagonal (Kress limits, per-row table) and the identity terms, in FP64.
-// Two adjacent rows per thread (n is even), so that every partial load is
-// 16 (FP32) or 2 x 16 (FP64) bytes wide; the partials of four chunks are
-// requested together.
+// The partials of four chunks are requested together.
 template <class PT>
-__device__ __forceinline__ void load_pair(const PT* p, PT& a, PT& b) {
-  if constexpr (sizeof(PT) == 8) {
-    const float4 v = *reinterpret_cast<const float4*>(p);
-    a = PT{v.x, v.y};
-    b = PT{v.z, v.w};
-  } else {
-    a = p[0];
-    b = p[1];
-  }
-}
-
-template <class PT>
-__global__ void sweep_epilogue2(EpiParams e) {
-  const int nh = e.n / 2;
-  const size_t tot = (size_t)nh * e.nrhs;
+__global__ void sweep_epilogue(EpiParams e) {
+  const size_t tot = (size_t)e.n * e.nrhs;
   const int nd = e.op == OP_HARD ? 2 : 1;
   const PT* part = static_cast<const PT*>(e.partial);
   const size_t cs = (size_t)nd * e.nrp * e.n;  // elements between chunks
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
        idx += (size_t)gridDim.x * blockDim.x) {
-    const int i = 2 * (int)(idx % nh);
-    const int c = idx / nh;
-    cplx sum[2][2] = {{{0.0, 0.0}, {0.0, 0.0}}, {{0.0, 0.0}, {0.0, 0.0}}};  // [row][d]
+    const int i = idx % e.n;
+    const int c = idx / e.n;
+    const double4 dg = e.diag[i];  // S_ii (re, im), D_ii = D'_ii
+    const cplx Sii = {dg.x, dg.y};
+    const double Dii = dg.z;
+    cplx sum[2] = {{0.0, 0.0}, {0.0, 0.0}};
     if (e.nearp)
-      for (int d = 0; d < nd; ++d) {
-        const cplx* np = e.nearp + ((size_t)d * e.nrp + c) * e.n + i;
-        sum[0][d] = np[0];
-        sum[1][d] = np[1];
-      }
+      for (int d = 0; d < nd; ++d) sum[d] = e.nearp[((size_t)d * e.nrp + c) * e.n + i];
     for (int d = 0; d < nd; ++d) {
       const PT* pd = part + ((size_t)d * e.nrp + c) * e.n + i;
       int ch = 0;
       for (; ch + 4 <= e.nchunks; ch += 4) {
-        PT v[4][2];
+        PT v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) load_pair(pd + (ch + u) * cs, v[u][0], v[u][1]);
+        for (int u = 0; u < 4; ++u) v[u] = pd[(ch + u) * cs];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int r = 0; r < 2; ++r) {
-            sum[r][d].re += (double)v[u][r].re;
-            sum[r][d].im += (double)v[u][r].im;
-          }
+        for (int u = 0; u < 4; ++u) {
+          sum[d].re += (double)v[u].re;
+          sum[d].im += (double)v[u].im;
+        }
       }
       for (; ch < e.nchunks; ++ch) {
-        PT v0, v1;
-        load_pair(pd + ch * cs, v0, v1);
-        sum[0][d].re += (double)v0.re;
-        sum[0][d].im += (double)v0.im;
-        sum[1][d].re += (double)v1.re;
-        sum[1][d].im += (double)v1.im;
+        const PT v = pd[ch * cs];
+        sum[d].re += (double)v.re;
+        sum[d].im += (double)v.im;
       }
     }
-    epi_finish(e, i, c, sum[0]);
-    epi_finish(e, i + 1, c, sum[1]);
+    const cplx qi = e.q[(size_t)(e.col0 + c) * e.n + i];
+    const size_t o = (size_t)(e.col0 + c) * e.n + i;
+    if (e.op == OP_SOFT) {
+      // (1/2 + D_ii - i eta S_ii) q_i
+      const cplx a = {0.5 + Dii + e.eta * Sii.im, -e.eta * Sii.re};
+      cfma(sum[0], a, qi);
+      e.out0[o] = sum[0];
+    } else if (e.op == OP_S) {
+      cfma(sum[0], Sii, qi);
+      e.out0[o] = sum[0];
+    } else if (e.op == OP_D || e.op == OP_DP) {
+      cfma(sum[0], cplx{Dii, 0.0}, qi);
+      e.out0[o] = sum[0];
+    } else {
+      const cplx s1 = e.q2[(size_t)(e.col0 + c) * e.n + i];
+      cfma(sum[0], Sii, s1);
+      // G_ii = -i (omega^2/eta) S_ii - D'_ii
+      const double g = e.omega * e.omega / e.eta;
+      cfma(sum[1], cplx{g * Sii.im - Dii, -g * Sii.re}, qi);
+      e.out0[o] = sum[0];
+      e.out1[o] = sum[1];
+    }
   }
 }
 
