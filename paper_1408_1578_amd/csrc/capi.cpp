@@ -188,6 +188,7 @@ void dp_problem_destroy(dp_problem* p) {
   p->tmp1.release();
   p->tmp2.release();
   p->tmp3.release();
+  for (auto& b : p->krylov_ws) b.release();
   delete p;
 }
 

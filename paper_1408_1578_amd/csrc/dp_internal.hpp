@@ -125,6 +125,10 @@ struct dp_problem {
   dp::DevBuf near_kv[5];       // kernel values of the entries, per sweep operator ([q][nd])
   bool near_kv_ready[5] = {};
   dp::DevBuf tmp1, tmp2, tmp3;
+  // GMRES workspaces (basis, preconditioned basis, w, r, partial sums, the
+  // small Hessenberg/norm block), kept between solves so that repeated
+  // solves (refinement corrections, serving) do not allocate and free them
+  dp::DevBuf krylov_ws[6];
   dp::Precond* pc = nullptr;
   // sweep launch configuration per (precision, operator, padded column count),
   // chosen by dp_autotune; absent keys use the default rule

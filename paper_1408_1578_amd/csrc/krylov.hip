@@ -77,6 +77,84 @@ __global__ __launch_bounds__(256) void gram_dots(const cplx* __restrict__ V, siz
   }
 }
 
+// The first projection's update and the second projection's dot products in
+// one pass over the basis, for kp1 <= kFuseK: per row, W[c] -= sum_i V_i[c]
+// h[i][c] with the row's basis values held in registers, then the partial
+// sums conj(V_i[c]) W[c] of the updated row, reduced as in gram_dots.  The
+// grid is that of gram_dots.
+constexpr int kFuseK = 16;
+
+__global__ __launch_bounds__(256) void gram_update_dots(const cplx* __restrict__ V, size_t vstride,
+                                                        cplx* __restrict__ W, const cplx* __restrict__ h, int n,
+                                                        int nrhs, int kp1, cplx* __restrict__ partial) {
+  __shared__ cplx red[4][kFuseK];
+  const int c = blockIdx.y;
+  const int j0 = blockIdx.x * kDotRows;
+  const int j1 = min(n, j0 + kDotRows);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  cplx* w = W + (size_t)c * n;
+  cplx hc[kFuseK], s[kFuseK];
+#pragma unroll
+  for (int u = 0; u < kFuseK; ++u) {
+    hc[u] = u < kp1 ? h[u * nrhs + c] : cplx{0.0, 0.0};
+    s[u] = {0.0, 0.0};
+  }
+  for (int j = j0 + threadIdx.x; j < j1; j += 256) {
+    cplx a[kFuseK];
+    cplx acc = w[j];
+#pragma unroll
+    for (int u = 0; u < kFuseK; ++u) {
+      if (u < kp1) {
+        a[u] = V[u * vstride + (size_t)c * n + j];
+        acc.re -= a[u].re * hc[u].re - a[u].im * hc[u].im;
+        acc.im -= a[u].re * hc[u].im + a[u].im * hc[u].re;
+      }
+    }
+    w[j] = acc;
+#pragma unroll
+    for (int u = 0; u < kFuseK; ++u) {
+      if (u < kp1) {
+        s[u].re = fma(a[u].re, acc.re, fma(a[u].im, acc.im, s[u].re));
+        s[u].im = fma(a[u].re, acc.im, fma(-a[u].im, acc.re, s[u].im));
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kFuseK; ++u) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s[u].re += __shfl_xor(s[u].re, off);
+      s[u].im += __shfl_xor(s[u].im, off);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int u = 0; u < kFuseK; ++u) red[wv][u] = s[u];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < kp1) {
+    const int u = threadIdx.x;
+    cplx t = red[0][u];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+      t.re += red[q][u].re;
+      t.im += red[q][u].im;
+    }
+    partial[((size_t)blockIdx.x * kp1 + u) * nrhs + c] = t;
+  }
+}
+
+// Pinned host memory, freed with its owner.
+struct PinnedHost {
+  void* p = nullptr;
+  PinnedHost() = default;
+  PinnedHost(const PinnedHost&) = delete;
+  PinnedHost& operator=(const PinnedHost&) = delete;
+  ~PinnedHost() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
 // out[i * nrhs + c] = sum_bx partial[...]  (fixed order)
 __global__ void gram_reduce(const cplx* __restrict__ partial, int nbx, int kp1, int nrhs, cplx* out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -238,7 +316,8 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
   hipStream_t st = p->ctx->stream;
   const size_t blk = (size_t)n * nrhs;
 
-  DevBuf V, Zb, W, R, part, small;
+  DevBuf &V = p->krylov_ws[0], &Zb = p->krylov_ws[1], &W = p->krylov_ws[2], &R = p->krylov_ws[3],
+         &part = p->krylov_ws[4], &small = p->krylov_ws[5];
   DP_TRY(V.reserve((m + 1) * blk * sizeof(cplx)));
   if (pre) DP_TRY(Zb.reserve(m * blk * sizeof(cplx)));
   DP_TRY(W.reserve(blk * sizeof(cplx)));
@@ -279,8 +358,14 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
       g((size_t)(m + 1) * nrhs);
   std::vector<int> kc(nrhs);
   std::vector<char> active(nrhs), conv_est(nrhs);
-  std::vector<cplx> hbuf(2 * hsz);
-  std::vector<double> nbuf(nrhs), sbuf(nrhs);
+  // pinned host copy of h1 | h2 | norm^2 | scale (the layout of `small`):
+  // the per-step readback is one asynchronous copy, with no staging through
+  // pageable memory
+  PinnedHost hpin;
+  DP_HIP(hipHostMalloc(&hpin.p, (2 * hsz + 2 * (size_t)nrhs) * sizeof(cplx), hipHostMallocDefault));
+  cplx* hbuf = static_cast<cplx*>(hpin.p);
+  double* nbuf = reinterpret_cast<double*>(hbuf + 2 * hsz);
+  double* sbuf = nbuf + nrhs;
   std::vector<cplx> yh((size_t)m * nrhs);
   int rc = DP_OK;
   auto Hat = [&](int i, int k, int c) -> zc& { return H[((size_t)c * (m + 1) + i) * m + k]; };
@@ -296,7 +381,7 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
       g[(size_t)c * (m + 1)] = active[c] ? zc(beta[c], 0.0) : zc(0.0, 0.0);
     }
     if (!any) break;
-    DP_HIP(hipMemcpyAsync(scl, sbuf.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    DP_HIP(hipMemcpyAsync(scl, sbuf, nrhs * sizeof(double), hipMemcpyHostToDevice, st));
     scale_cols<<<g1(blk), 256, 0, st>>>(Rp, Vp, scl, n, nrhs);
     int kdone = 0;
     for (int k = 0; k < m; ++k) {
@@ -315,8 +400,12 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
       const int kp1 = k + 1;
       gram_dots<<<dim3(nbx, nrhs), 256, 0, st>>>(Vp, blk, Wp, n, nrhs, kp1, part.as<cplx>());
       gram_reduce<<<(kp1 * nrhs + 255) / 256, 256, 0, st>>>(part.as<cplx>(), nbx, kp1, nrhs, h1);
-      gram_update<<<g1(blk), 256, 0, st>>>(Vp, blk, Wp, h1, n, nrhs, kp1);
-      gram_dots<<<dim3(nbx, nrhs), 256, 0, st>>>(Vp, blk, Wp, n, nrhs, kp1, part.as<cplx>());
+      if (kp1 <= kFuseK) {
+        gram_update_dots<<<dim3(nbx, nrhs), 256, 0, st>>>(Vp, blk, Wp, h1, n, nrhs, kp1, part.as<cplx>());
+      } else {
+        gram_update<<<g1(blk), 256, 0, st>>>(Vp, blk, Wp, h1, n, nrhs, kp1);
+        gram_dots<<<dim3(nbx, nrhs), 256, 0, st>>>(Vp, blk, Wp, n, nrhs, kp1, part.as<cplx>());
+      }
       gram_reduce<<<(kp1 * nrhs + 255) / 256, 256, 0, st>>>(part.as<cplx>(), nbx, kp1, nrhs, h2);
       gram_update<<<g1(blk), 256, 0, st>>>(Vp, blk, Wp, h2, n, nrhs, kp1);
       {
@@ -324,9 +413,8 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
         col_norm2<<<dim3(nbx, nrhs), 256, 0, st>>>(Wp, n, nrhs, pp);
         norm_reduce<<<(nrhs + 63) / 64, 64, 0, st>>>(pp, nbx, nrhs, nrm);
       }
-      DP_HIP(hipMemcpyAsync(hbuf.data(), h1, (size_t)kp1 * nrhs * sizeof(cplx), hipMemcpyDeviceToHost, st));
-      DP_HIP(hipMemcpyAsync(hbuf.data() + hsz, h2, (size_t)kp1 * nrhs * sizeof(cplx), hipMemcpyDeviceToHost, st));
-      DP_HIP(hipMemcpyAsync(nbuf.data(), nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      // h1, h2 and the norms in one copy (h2 and the norms sit at fixed offsets)
+      DP_HIP(hipMemcpyAsync(hbuf, h1, 2 * hsz * sizeof(cplx) + nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
       DP_HIP(hipStreamSynchronize(st));
       tm.collect();
       ta.collect();
@@ -372,7 +460,7 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
       }
       kdone = k + 1;
       if (!still) break;
-      DP_HIP(hipMemcpyAsync(scl, sbuf.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+      DP_HIP(hipMemcpyAsync(scl, sbuf, nrhs * sizeof(double), hipMemcpyHostToDevice, st));
       scale_cols<<<g1(blk), 256, 0, st>>>(Wp, Vp + (k + 1) * blk, scl, n, nrhs);
     }
     // y = H^{-1} g per column (upper triangular), X += Z y
@@ -444,13 +532,7 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
   }
   tm.destroy();
   ta.destroy();
-  V.release();
-  Zb.release();
-  W.release();
-  R.release();
-  part.release();
-  small.release();
-  return rc;
+  return rc;  // the workspaces stay with the problem
 }
 
 // out[c] = F[c] - R[c] for columns with keep[c] != 0, else 0

@@ -1319,12 +1319,43 @@ static void threshold_T(const std::vector<cplx>& T, int K, double t_keep, std::v
 int precond_build(dp_problem* p, const dp_precond_opts* o) {
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = p->ctx->stream;
-  if (p->pc) {
-    precond_destroy(p->pc);
-    p->pc = nullptr;
-  }
+  // A rebuild takes over the previous preconditioner's device buffers:
+  // those already large enough are reused rather than freed and allocated
+  // again (each hipFree waits for the device).  Its graphs and host state
+  // are not kept.
+  Precond* old = p->pc;
+  p->pc = nullptr;
   Precond* P = new Precond();
+  auto take = [](DevBuf& dst, DevBuf& src) {
+    dst = src;
+    src = DevBuf{};
+  };
+  if (old) {
+    for (auto pr : {std::make_pair(&P->d_segs, &old->d_segs), std::make_pair(&P->d_ptrs, &old->d_ptrs),
+                    std::make_pair(&P->d_ptrs32, &old->d_ptrs32), std::make_pair(&P->d_dims, &old->d_dims),
+                    std::make_pair(&P->Lp, &old->Lp), std::make_pair(&P->Lj, &old->Lj),
+                    std::make_pair(&P->Lx, &old->Lx), std::make_pair(&P->Up, &old->Up),
+                    std::make_pair(&P->Uj, &old->Uj), std::make_pair(&P->Ux, &old->Ux),
+                    std::make_pair(&P->Ud, &old->Ud), std::make_pair(&P->lvlL, &old->lvlL),
+                    std::make_pair(&P->lvlLr, &old->lvlLr), std::make_pair(&P->lvlU, &old->lvlU),
+                    std::make_pair(&P->lvlUr, &old->lvlUr), std::make_pair(&P->pin, &old->pin),
+                    std::make_pair(&P->pout, &old->pout), std::make_pair(&P->slots, &old->slots),
+                    std::make_pair(&P->slots32, &old->slots32), std::make_pair(&P->wy, &old->wy),
+                    std::make_pair(&P->wg, &old->wg), std::make_pair(&P->wz, &old->wz),
+                    std::make_pair(&P->wu, &old->wu), std::make_pair(&P->wt, &old->wt),
+                    std::make_pair(&P->wn, &old->wn), std::make_pair(&P->sy, &old->sy),
+                    std::make_pair(&P->sg, &old->sg), std::make_pair(&P->sz, &old->sz),
+                    std::make_pair(&P->su, &old->su), std::make_pair(&P->sn, &old->sn),
+                    std::make_pair(&P->sv, &old->sv), std::make_pair(&P->sq, &old->sq),
+                    std::make_pair(&P->win, &old->win), std::make_pair(&P->wq, &old->wq)})
+      take(*pr.first, *pr.second);
+  }
+  auto drop_old = [&]() {
+    if (old) precond_destroy(old);
+    old = nullptr;
+  };
   auto fail = [&](int rc) {
+    drop_old();
     precond_destroy(P);
     return rc;
   };
@@ -1349,6 +1380,18 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     c.K = 2 * c.J + 1;
     P->classes.push_back(std::move(c));
   }
+  if (old) {  // per-class buffers, by class index
+    for (size_t ci = 0; ci < std::min(P->classes.size(), old->classes.size()); ++ci) {
+      SizeClass& c = P->classes[ci];
+      SizeClass& oc = old->classes[ci];
+      for (auto pr : {std::make_pair(&c.Binv, &oc.Binv), std::make_pair(&c.U, &oc.U), std::make_pair(&c.Ut, &oc.Ut),
+                      std::make_pair(&c.Tt, &oc.Tt), std::make_pair(&c.alpha, &oc.alpha),
+                      std::make_pair(&c.Binv32, &oc.Binv32), std::make_pair(&c.U32, &oc.U32),
+                      std::make_pair(&c.Ut32, &oc.Ut32), std::make_pair(&c.Tt32, &oc.Tt32)})
+        take(*pr.first, *pr.second);
+    }
+  }
+  drop_old();
   P->offK.assign(m + 1, 0);
   P->cls.resize(m);
   P->J.resize(m);
