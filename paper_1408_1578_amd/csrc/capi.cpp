@@ -189,6 +189,7 @@ void dp_problem_destroy(dp_problem* p) {
   p->tmp2.release();
   p->tmp3.release();
   for (auto& b : p->krylov_ws) b.release();
+  for (auto& b : p->refine_ws) b.release();
   delete p;
 }
 

@@ -129,6 +129,7 @@ struct dp_problem {
   // small Hessenberg/norm block), kept between solves so that repeated
   // solves (refinement corrections, serving) do not allocate and free them
   dp::DevBuf krylov_ws[6];
+  dp::DevBuf refine_ws[4];  // the same for the mixed-precision refinement (r, d, partial sums, flags)
   dp::Precond* pc = nullptr;
   // sweep launch configuration per (precision, operator, padded column count),
   // chosen by dp_autotune; absent keys use the default rule

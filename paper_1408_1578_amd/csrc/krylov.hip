@@ -144,6 +144,17 @@ __global__ __launch_bounds__(256) void gram_update_dots(const cplx* __restrict__
   }
 }
 
+// A HIP event, destroyed with its owner.
+struct OwnedEvent {
+  hipEvent_t e = nullptr;
+  OwnedEvent() = default;
+  OwnedEvent(const OwnedEvent&) = delete;
+  OwnedEvent& operator=(const OwnedEvent&) = delete;
+  ~OwnedEvent() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+
 // Pinned host memory, freed with its owner.
 struct PinnedHost {
   void* p = nullptr;
@@ -358,6 +369,8 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
       g((size_t)(m + 1) * nrhs);
   std::vector<int> kc(nrhs);
   std::vector<char> active(nrhs), conv_est(nrhs);
+  OwnedEvent ev_mv;  // after each step's matrix-vector product
+  DP_HIP(hipEventCreateWithFlags(&ev_mv.e, hipEventDisableTiming));
   // pinned host copy of h1 | h2 | norm^2 | scale (the layout of `small`):
   // the per-step readback is one asynchronous copy, with no staging through
   // pageable memory
@@ -396,6 +409,7 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
       tm.start(st);
       DP_TRY(matvec(p, nrhs, zk, Wp, prec));
       tm.stop(st);
+      DP_HIP(hipEventRecord(ev_mv.e, st));
       ++matvecs;
       const int kp1 = k + 1;
       gram_dots<<<dim3(nbx, nrhs), 256, 0, st>>>(Vp, blk, Wp, n, nrhs, kp1, part.as<cplx>());
@@ -415,7 +429,16 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
       }
       // h1, h2 and the norms in one copy (h2 and the norms sit at fixed offsets)
       DP_HIP(hipMemcpyAsync(hbuf, h1, 2 * hsz * sizeof(cplx) + nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      DP_HIP(hipStreamSynchronize(st));
+      // wait (blocking) for the matrix-vector product, then poll the stream
+      // through the short orthogonalisation tail: a blocking wait for the
+      // readback itself adds the host thread's wake-up to every step
+      DP_HIP(hipEventSynchronize(ev_mv.e));
+      {
+        hipError_t q;
+        while ((q = hipStreamQuery(st)) == hipErrorNotReady) {
+        }
+        DP_HIP(q);
+      }
       tm.collect();
       ta.collect();
       p->clock.collect();
@@ -565,7 +588,7 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
   const int n = (int)p->n;
   hipStream_t st = p->ctx->stream;
   const size_t blk = (size_t)n * nrhs;
-  DevBuf R, D, part, keep;
+  DevBuf &R = p->refine_ws[0], &D = p->refine_ws[1], &part = p->refine_ws[2], &keep = p->refine_ws[3];
   DP_TRY(R.reserve(blk * sizeof(cplx)));
   DP_TRY(D.reserve(blk * sizeof(cplx)));
   DP_TRY(keep.reserve(nrhs * sizeof(double)));
@@ -668,11 +691,7 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
     info->t_sweep_fp32 = p->clock32.seconds;
   }
   tm.destroy();
-  R.release();
-  D.release();
-  part.release();
-  keep.release();
-  return rc;
+  return rc;  // the workspaces stay with the problem
 }
 
 }  // namespace dp

@@ -1405,18 +1405,21 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
 
   // ---- size classes: B^{-1}, U, S, T, floor(T), alpha (batched over classes)
   const int ncls = (int)P->classes.size();
-  std::vector<DevBuf> augB(2 * ncls), augS(2 * ncls), colB(2 * ncls), colS(2 * ncls);
-  DevBuf row, X, S, gstat;
+  // per class (so that no class's buffer is reallocated while a kernel of
+  // the previous class may still read it, and the loops need no waits)
+  std::vector<DevBuf> augB(2 * ncls), augS(2 * ncls), colB(2 * ncls), colS(2 * ncls), rows(ncls), Xs(ncls),
+      Ss(ncls);
+  DevBuf gstat;
   DevBuf d_alpha;
   struct Release {  // the setup's own buffers, on every return path
     std::vector<DevBuf*> bufs;
-    std::vector<DevBuf>* vecs[4];
+    std::vector<DevBuf>* vecs[7];
     ~Release() {
       for (DevBuf* q : bufs) q->release();
       for (auto* v : vecs)
         for (DevBuf& q : *v) q.release();
     }
-  } release_locals{{&row, &X, &S, &gstat, &d_alpha}, {&augB, &augS, &colB, &colS}};
+  } release_locals{{&gstat, &d_alpha}, {&augB, &augS, &colB, &colS, &rows, &Xs, &Ss}};
   DP_TRY(d_alpha.reserve(ncls * mc * sizeof(double)));
   std::vector<GJMat> gb(ncls);
   for (int ci = 0; ci < ncls; ++ci)
@@ -1543,6 +1546,7 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     SizeClass& c = P->classes[ci];
     const int s = c.s, K = c.K;
     int rc;
+    DevBuf& row = rows[ci];
     if ((rc = row.reserve(s * sizeof(cplx))) || (rc = augB[2 * ci].reserve((size_t)s * 2 * s * sizeof(cplx))) ||
         (rc = augB[2 * ci + 1].reserve((size_t)s * 2 * s * sizeof(cplx))) ||
         (rc = colB[2 * ci].reserve((size_t)s * sizeof(cplx))) || (rc = colB[2 * ci + 1].reserve((size_t)s * sizeof(cplx))) ||
@@ -1553,8 +1557,6 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     toeplitz_aug<<<grid1((size_t)s * 2 * s), 256, 0, st>>>(row.as<cplx>(), augB[2 * ci].as<cplx>(), s);
     gb[ci] = GJMat{{augB[2 * ci].as<cplx>(), augB[2 * ci + 1].as<cplx>()},
                    {colB[2 * ci].as<cplx>(), colB[2 * ci + 1].as<cplx>()}, s, 0};
-    // the next class's flat row must not overwrite this one before it is read
-    DP_HIP(hipStreamSynchronize(st));
   }
   {
     int rc;
@@ -1565,8 +1567,7 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     SizeClass& c = P->classes[ci];
     const int s = c.s, K = c.K;
     copy_right_half<<<grid1((size_t)s * s), 256, 0, st>>>(augB[2 * ci + gb[ci].res].as<cplx>(), c.Binv.as<cplx>(), s);
-    augB[2 * ci].release();
-    augB[2 * ci + 1].release();
+    DevBuf &X = Xs[ci], &S = Ss[ci];
     int rc;
     if ((rc = X.reserve((size_t)s * K * sizeof(cplx))) || (rc = S.reserve((size_t)K * K * sizeof(cplx))) ||
         (rc = augS[2 * ci].reserve((size_t)K * 2 * K * sizeof(cplx))) ||
@@ -1580,25 +1581,27 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     augment_identity<<<grid1((size_t)K * 2 * K), 256, 0, st>>>(S.as<cplx>(), augS[2 * ci].as<cplx>(), K);
     gs[ci] = GJMat{{augS[2 * ci].as<cplx>(), augS[2 * ci + 1].as<cplx>()},
                    {colS[2 * ci].as<cplx>(), colS[2 * ci + 1].as<cplx>()}, K, 0};
-    // X and S are reused by the next class
-    DP_HIP(hipStreamSynchronize(st));
   }
   {
     int rc;
     if ((rc = gj_invert(st, gs, gstat, o->gj_steps))) return fail(rc);
   }
+  // T_s to the host for all classes, one wait, threshold, back for all
   for (int ci = 0; ci < ncls; ++ci) {
     SizeClass& c = P->classes[ci];
-    const int s = c.s, K = c.K;
+    const int K = c.K;
     copy_right_half<<<grid1((size_t)K * K), 256, 0, st>>>(augS[2 * ci + gs[ci].res].as<cplx>(), c.Tt.as<cplx>(), K);
     c.T.resize((size_t)K * K);
     DP_HIP(hipMemcpyAsync(c.T.data(), c.Tt.p, c.T.size() * sizeof(cplx), hipMemcpyDeviceToHost, st));
-    DP_HIP(hipStreamSynchronize(st));
-    augS[2 * ci].release();
-    augS[2 * ci + 1].release();
-    std::vector<cplx> Tt;
-    threshold_T(c.T, K, o->t_keep, Tt);
-    DP_HIP(hipMemcpyAsync(c.Tt.p, Tt.data(), Tt.size() * sizeof(cplx), hipMemcpyHostToDevice, st));
+  }
+  DP_HIP(hipStreamSynchronize(st));
+  {
+    std::vector<std::vector<cplx>> Tts(ncls);
+    for (int ci = 0; ci < ncls; ++ci) {
+      SizeClass& c = P->classes[ci];
+      threshold_T(c.T, c.K, o->t_keep, Tts[ci]);
+      DP_HIP(hipMemcpyAsync(c.Tt.p, Tts[ci].data(), Tts[ci].size() * sizeof(cplx), hipMemcpyHostToDevice, st));
+    }
     DP_HIP(hipStreamSynchronize(st));
   }
   DP_HIP(hipGetLastError());
@@ -1721,10 +1724,7 @@ int precond_build(dp_problem* p, const dp_precond_opts* o) {
     if ((rc = upload(P->d_ptrs32, ptrs32, st))) return fail(rc);
   }
   DP_HIP(hipStreamSynchronize(st));
-  row.release();
   gstat.release();
-  X.release();
-  S.release();
   d_alpha.release();
   d_u.release();
   d_geo.release();
