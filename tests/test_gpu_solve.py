@@ -66,3 +66,32 @@ def test_zero_rhs_column():
     info = dp.dp_solve(p, to_dev(F), q, tol=1e-8)
     assert info["converged"]
     assert np.all(to_host(q)[:, 0] == 0)
+
+
+@pytest.mark.parametrize("precision", [dp.DP_PREC_FP64, dp.DP_PREC_MIXED])
+def test_repeated_solves_reuse_workspaces(precision):
+    # the GMRES and refinement workspaces stay with the problem between
+    # solves: a solve after others with different column counts and restart
+    # lengths reproduces a solve on a fresh problem bit for bit
+    b = sample_boundary("kite", 1024)
+    om = omega_for_ppw(b.n, b.L, 10.0)
+    ang = plane_wave_angles(4)
+
+    def solve(p, cols, restart):
+        f, q = empty(b.n, len(cols)), empty(b.n, len(cols))
+        dp.dp_rhs_plane_wave(p, ang[cols], f)
+        info = dp.dp_solve(p, f, q, tol=1e-9, restart=restart, use_precond=True, precision=precision)
+        assert info["converged"]
+        return to_host(q)
+
+    fresh = problem(b, om, om, 1)
+    dp.dp_precond_build(fresh)
+    ref = solve(fresh, [0, 1, 2, 3], 40)
+    fresh.close()
+    p = problem(b, om, om, 1)
+    dp.dp_precond_build(p)
+    solve(p, [3], 80)
+    solve(p, [0, 2], 10)
+    dp.dp_precond_build(p)  # the rebuild takes over the previous buffers
+    assert np.array_equal(solve(p, [0, 1, 2, 3], 40), ref)
+    p.close()
