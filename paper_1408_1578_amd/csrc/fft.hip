@@ -16,26 +16,56 @@ constexpr int kFftLds = 4096;  // complex elements per block
 
 __device__ __forceinline__ unsigned bitrev(unsigned v, int bits) { return __brev(v) >> (32 - bits); }
 
-// In-LDS radix-2 DIT transform of `lines` lines of length Lf stored as
+// In-LDS DIT transform of `lines` lines of length Lf stored as
 // buf[e * lines + l] (element-major, so that loads over lines coalesce).
 // Input must be in bit-reversed element order.  dir = -1 forward, +1 inverse.
-// Lf, lines and ntw are powers of two (loglines = log2 lines).
+// Lf, lines and ntw are powers of two (loglines = log2 lines).  The radix-2
+// stages of half sizes h and 2h are done together as one radix-4 stage
+// (elements pos, pos + h, pos + 2h, pos + 3h of a block of 4h: twiddles
+// W_2h^pos for the first pair of butterflies, W_4h^pos and
+// W_4h^(pos + h) = W_4h^pos (-+i) for the second); one plain radix-2 stage
+// comes first when log2 Lf is odd.  Half the stages, barriers and LDS round
+// trips of the radix-2 form, with the same pairing and output order.
 __device__ void lds_fft(cplx* buf, int Lf, int lines, int loglines, const cplx* tw, int ntw, int dir) {
-  for (int half = 1; half < Lf; half <<= 1) {
+  int half = 1;
+  if (__builtin_ctz(Lf) & 1) {  // half = 1: the twiddle is 1
     const int nb = (Lf >> 1) * lines;
-    const int stride = ntw / (2 * half);
     for (int t = threadIdx.x; t < nb; t += blockDim.x) {
       const int l = t & (lines - 1);
-      const int b = t >> loglines;
-      const int pos = b & (half - 1);
-      const int i0 = ((b - pos) << 1) + pos;
-      const int i1 = i0 + half;
-      cplx w = tw[pos * stride];
-      if (dir > 0) w.im = -w.im;
-      const cplx a = buf[i0 * lines + l];
-      const cplx bb = cmul(buf[i1 * lines + l], w);
-      buf[i0 * lines + l] = {a.re + bb.re, a.im + bb.im};
-      buf[i1 * lines + l] = {a.re - bb.re, a.im - bb.im};
+      const int i0 = (t >> loglines) << 1;
+      const cplx a = buf[i0 * lines + l], c = buf[(i0 + 1) * lines + l];
+      buf[i0 * lines + l] = {a.re + c.re, a.im + c.im};
+      buf[(i0 + 1) * lines + l] = {a.re - c.re, a.im - c.im};
+    }
+    __syncthreads();
+    half = 2;
+  }
+  for (; half < Lf; half <<= 2) {
+    const int h = half;
+    const int nb = (Lf >> 2) * lines;
+    const int s1 = ntw / (2 * h), s2 = ntw / (4 * h);
+    for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+      const int l = t & (lines - 1);
+      const int b = t >> loglines;  // radix-4 butterfly, [0, Lf / 4)
+      const int pos = b & (h - 1);
+      const int i0 = ((b - pos) << 2) + pos;
+      cplx w1 = tw[pos * s1], w2 = tw[pos * s2];
+      if (dir > 0) {
+        w1.im = -w1.im;
+        w2.im = -w2.im;
+      }
+      cplx* p0 = buf + (size_t)i0 * lines + l;
+      const size_t hs = (size_t)h * lines;
+      const cplx a0 = p0[0], a1 = p0[hs], a2 = p0[2 * hs], a3 = p0[3 * hs];
+      const cplx m1 = cmul(a1, w1), m3 = cmul(a3, w1);
+      const cplx t0 = {a0.re + m1.re, a0.im + m1.im}, t1 = {a0.re - m1.re, a0.im - m1.im};
+      const cplx t2 = {a2.re + m3.re, a2.im + m3.im}, t3 = {a2.re - m3.re, a2.im - m3.im};
+      const cplx u2 = cmul(t2, w2), u3 = cmul(t3, w2);
+      const cplx v3 = dir < 0 ? cplx{u3.im, -u3.re} : cplx{-u3.im, u3.re};  // W_4h^h = -i (forward), +i
+      p0[0] = {t0.re + u2.re, t0.im + u2.im};
+      p0[2 * hs] = {t0.re - u2.re, t0.im - u2.im};
+      p0[hs] = {t1.re + v3.re, t1.im + v3.im};
+      p0[3 * hs] = {t1.re - v3.re, t1.im - v3.im};
     }
     __syncthreads();
   }
