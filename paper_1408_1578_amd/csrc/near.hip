@@ -162,9 +162,11 @@ void launch_values(int op, const NearParams& np, cplx* kv, hipStream_t st) {
   }
 }
 
+constexpr int kNearGroup = 8;  // near-field entries whose density rows are gathered together
+
 // All 64 columns: one lane per column, so a row's entries are the same for
-// the whole wave (scalar loads of the column index and kernel values, four
-// entries in flight).  A block covers 16 consecutive rows, 4 per wave, and
+// the whole wave (scalar loads of the column index and kernel values,
+// kNearGroup entries in flight).  A block covers 16 consecutive rows, 4 per wave, and
 // stages the sums in LDS (row stride padded to 17) so that each (density,
 // column) is written as one 16-row run.  Row blocks are spread over the XCDs
 // as in near_apply.
@@ -187,22 +189,24 @@ __global__ __launch_bounds__(256) void near_apply64(NearParams p) {
     if (i < p.n) {
       const int e0 = p.ptr[i], e1 = p.ptr[i + 1];
       int q = e0;
-      for (; q + 4 <= e1; q += 4) {
-        int j[4];
-        cplx K[4][ND];
-        DT v[4][ND];
+      // groups of kNearGroup entries: all their density rows are requested
+      // before the first product, so that enough gathers are in flight
+      for (; q + kNearGroup <= e1; q += kNearGroup) {
+        int j[kNearGroup];
+        cplx K[kNearGroup][ND];
+        DT v[kNearGroup][ND];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kNearGroup; ++u) {
           j[u] = p.col[q + u];
 #pragma unroll
           for (int d = 0; d < ND; ++d) K[u][d] = p.kv[(size_t)(q + u) * ND + d];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kNearGroup; ++u)
 #pragma unroll
           for (int d = 0; d < ND; ++d) v[u][d] = dens[((size_t)j[u] * ND + d) * 64 + lane];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kNearGroup; ++u)
 #pragma unroll
           for (int d = 0; d < ND; ++d) cfma(acc[d], K[u][d], cplx{(double)v[u][d].re, (double)v[u][d].im});
       }
