@@ -212,8 +212,12 @@ typedef struct {
  * apply.  With DP_PREC_MIXED the solve is q_{k+1} = q_k + GMRES_32(f - A q_k)
  * until the FP64 residual meets tol.  f, q: device n x nrhs complex.
  * opts/info may be NULL.  iters, relres: optional host arrays of nrhs entries
- * (per-column iteration counts and true FP64 relative residuals).  Returns
- * DP_OK or DP_ENOCONV. */
+ * (per-column iteration counts and true FP64 relative residuals).  The
+ * solve's device workspaces (the Krylov basis and its preconditioned copy,
+ * (restart + 1) and restart n x nrhs complex arrays, and the refinement
+ * vectors) stay allocated with the problem, grown as needed, until
+ * dp_problem_destroy, so that repeated solves do not allocate; calls on one
+ * problem must not overlap.  Returns DP_OK or DP_ENOCONV. */
 int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_solve_opts* opts,
              dp_solve_info* info, int64_t* iters, double* relres);
 
