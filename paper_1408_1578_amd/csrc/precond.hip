@@ -917,7 +917,7 @@ __device__ __forceinline__ flt4v mma_bf16(const uint4& a, const uint4& b, flt4v 
                                                  0, 0, 0);
 }
 
-__global__ __launch_bounds__(256) void seg_gemm_bf16x3(SegGemm<cplxf> g) {
+__global__ __launch_bounds__(256, 3) void seg_gemm_bf16x3(SegGemm<cplxf> g) {
   // [piece 3][re, im][64 rows or columns][16 words of two k]
   __shared__ __align__(16) uint32_t As[3][2][64][16];
   __shared__ __align__(16) uint32_t Xs[3][2][64][16];
