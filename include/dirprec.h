@@ -189,7 +189,7 @@ typedef struct {
                        and whose residuals f - A q are FP64 */
   double inner_tol; /* mixed: relative tolerance of the correction solves, at least the one
                        that takes every column from its current FP64 residual r to
-                       tol/10 (0.1 tol/r for the worst column); default 1e-5 */
+                       0.3 tol (0.3 tol/r for the worst column); default 1e-5 */
 } dp_solve_opts;
 
 typedef struct {

@@ -622,12 +622,14 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
     }
     oi.max_iters = (int)std::max<int64_t>(1, left);
     // A column at FP64 residual rel needs its correction solve to reduce the
-    // residual by tol/rel only; ask for ten times that of the worst column,
-    // and never less than inner_tol (the first step, rel = 1, gets inner_tol).
+    // residual by tol/rel only; ask for 0.3 of that for the worst column (its
+    // FP64 residual then ends near 0.3 tol, and a column that still misses tol
+    // gets one more refinement), and never less than inner_tol (the first
+    // step, rel = 1, gets inner_tol).
     double worst = 0.0;
     for (int c = 0; c < nrhs; ++c)
       if (rel[c] > o->tol) worst = std::max(worst, rel[c]);
-    oi.tol = std::max(o->inner_tol, worst > 0.0 ? 0.1 * o->tol / worst : o->inner_tol);
+    oi.tol = std::max(o->inner_tol, worst > 0.0 ? 0.3 * o->tol / worst : o->inner_tol);
     dp_solve_info ii;
     int r = gmres_core(p, nrhs, R.as<cplx>(), D.as<cplx>(), &oi, 1, true, &ii, its_in.data(), rel_in.data());
     if (r < 0) return r;
