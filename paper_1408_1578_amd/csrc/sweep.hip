@@ -497,6 +497,22 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
                   bool sync) {
     if (st + 2 < nsteps) dma(st + 2, Btn, Ssn, Csn);
     const int jb = j0 + 32 * st;
+    constexpr int CP = NCB >= 2 ? 2 : 1;
+    constexpr int NG = NCB / CP;
+    uint4 bb[2][CP][4];
+    auto read_b = [&](int g, uint4 (&dst)[CP][4]) {
+      const int d = g / NG, cb0 = (g % NG) * CP;
+#pragma unroll
+      for (int u = 0; u < CP; ++u) {
+        const int row = d * 4 * NC + (cb0 + u) * 16 + li;
+#pragma unroll
+        for (int part = 0; part < 4; ++part) dst[u][part] = Bt[(row + part * NC) * 4 + gsw];
+      }
+    };
+    // the first group's B fragments are requested before the pair
+    // evaluation, so that they have arrived when its products start
+    read_b(0, bb[0]);
+    __builtin_amdgcn_sched_barrier(0);
     // A fragments: this lane's 8 pairs, hi and lo parts of Re K and Im K
     uint32_t arh[ND][4], arl[ND][4], aih[ND][4], ail[ND][4];
     const SrcRec* ss = reinterpret_cast<const SrcRec*>(Ss);
@@ -525,19 +541,6 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
     // are read from LDS one group ahead, while the previous group's products
     // run (the scheduling barriers keep the reads from being hoisted into
     // one batch that would wait for all of them).
-    constexpr int CP = NCB >= 2 ? 2 : 1;
-    constexpr int NG = NCB / CP;
-    uint4 bb[2][CP][4];
-    auto read_b = [&](int g, uint4 (&dst)[CP][4]) {
-      const int d = g / NG, cb0 = (g % NG) * CP;
-#pragma unroll
-      for (int u = 0; u < CP; ++u) {
-        const int row = d * 4 * NC + (cb0 + u) * 16 + li;
-#pragma unroll
-        for (int part = 0; part < 4; ++part) dst[u][part] = Bt[(row + part * NC) * 4 + gsw];
-      }
-    };
-    read_b(0, bb[0]);
 #pragma unroll
     for (int g = 0; g < ND * NG; ++g) {
       const int d = g / NG, cb0 = (g % NG) * CP;
