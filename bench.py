@@ -46,8 +46,8 @@ FLOPS_MFMA16_PER_COL = 24
 # counts of a 512 MiB device copy in the same run).  They describe the current
 # kernels in that configuration; another configuration or a changed kernel
 # must be measured again before they are reported.
-TRAFFIC_FP64_SWEEP = 1.4012e9
-TRAFFIC_FP32_SWEEP = 0.5778e9
+TRAFFIC_FP64_SWEEP = 1.4011e9
+TRAFFIC_FP32_SWEEP = 0.5774e9
 
 # Algorithmic FP64 flops of one ordered pair in the sound-hard sweep (far-field
 # evaluation path; an FMA counts 2): geometry 5, 1/r 8, r and z 2, H0/H1 142,
