@@ -356,18 +356,29 @@ __global__ __launch_bounds__(256) void sweep_private32(SweepParams p) {
   }
 }
 
-// dens[j][d][c] = in_d[c*n + j] (zero for padded columns c >= nrhs), FP32
-__global__ void pack_dens32(const cplx* __restrict__ a, const cplx* __restrict__ b, cplxf* __restrict__ dens,
-                            int n, int nrhs, int nrp, int nd, int col0) {
-  const size_t tot = (size_t)n * nrp * nd;
-  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int c = idx % nrp;
-    const int d = (idx / nrp) % nd;
-    const size_t j = idx / ((size_t)nrp * nd);
-    const cplx* src = d == 0 ? a : b;
-    const cplx v = (c < nrhs) ? src[(size_t)(col0 + c) * n + j] : cplx{0.0, 0.0};
-    dens[idx] = {(float)v.re, (float)v.im};
+// dens[j][d][c] = in_d[c*n + j] (zero for padded columns c >= nrhs), in
+// FP64 (OT = cplx) or FP32 (OT = cplxf)
+template <class OT>
+__global__ __launch_bounds__(256) void pack_dens_t(const cplx* __restrict__ a, const cplx* __restrict__ b,
+                                                   OT* __restrict__ dens, int n, int nrhs, int nrp, int nd,
+                                                   int col0) {
+  // block (32-row block, density): the 32 x nrp slab (nrp <= 64) is read
+  // along the rows of each column, transposed through LDS and written along
+  // the columns
+  __shared__ OT tile[32][65];
+  const int j0 = blockIdx.x * 32, d = blockIdx.y;
+  const cplx* src = d == 0 ? a : b;
+  for (int e = threadIdx.x; e < 32 * nrp; e += 256) {
+    const int c = e >> 5, jj = e & 31;
+    const int j = j0 + jj;
+    const cplx v = (c < nrhs && j < n) ? src[(size_t)(col0 + c) * n + j] : cplx{0.0, 0.0};
+    tile[jj][c] = OT{(decltype(OT{}.re))v.re, (decltype(OT{}.re))v.im};
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * nrp; e += 256) {
+    const int jj = e / nrp, c = e - jj * nrp;
+    const int j = j0 + jj;
+    if (j < n) dens[((size_t)j * nd + d) * nrp + c] = tile[jj][c];
   }
 }
 
@@ -612,22 +623,22 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
 // eK: the kernel-value exponent of density d.  The density scale puts the
 // column's largest |re| or |im| below 2^14; the combined exponent stays in
 // [-120, 120] so that the FP32 unscale factor is a normal number.
-__global__ __launch_bounds__(256) void dens16_scales(const cplx* __restrict__ a, const cplx* __restrict__ b,
-                                                     int n, int nrhs, int nrp, int col0, int eK0, int eK1,
-                                                     double* __restrict__ bscale, float* __restrict__ unscale) {
+__global__ __launch_bounds__(1024) void dens16_scales(const cplx* __restrict__ a, const cplx* __restrict__ b,
+                                                      int n, int nrhs, int nrp, int col0, int eK0, int eK1,
+                                                      double* __restrict__ bscale, float* __restrict__ unscale) {
   const int d = blockIdx.x / nrp, c = blockIdx.x % nrp;
-  __shared__ double red[256];
+  __shared__ double red[1024];
   double m = 0.0;
   if (c < nrhs) {
     const cplx* src = (d == 0 ? a : b) + (size_t)(col0 + c) * n;
-    for (int j = threadIdx.x; j < n; j += 256) {
+    for (int j = threadIdx.x; j < n; j += 1024) {
       const cplx v = src[j];
       m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
     }
   }
   red[threadIdx.x] = m;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = 512; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
@@ -680,20 +691,6 @@ __global__ void pack_dens16(const cplx* __restrict__ a, const cplx* __restrict__
     o[ps] = uint4{rl[0], rl[1], rl[2], rl[3]};
     o[2 * ps] = uint4{ih[0], ih[1], ih[2], ih[3]};
     o[3 * ps] = uint4{il[0], il[1], il[2], il[3]};
-  }
-}
-
-// dens[j][d][c] = in_d[c*n + j] (zero for padded columns c >= nrhs)
-__global__ void pack_dens(const cplx* __restrict__ a, const cplx* __restrict__ b, cplx* __restrict__ dens,
-                          int n, int nrhs, int nrp, int nd, int col0) {
-  const size_t tot = (size_t)n * nrp * nd;
-  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int c = idx % nrp;
-    const int d = (idx / nrp) % nd;
-    const size_t j = idx / ((size_t)nrp * nd);
-    const cplx* src = d == 0 ? a : b;
-    dens[idx] = (c < nrhs) ? src[(size_t)(col0 + c) * n + j] : cplx{0.0, 0.0};
   }
 }
 
@@ -823,14 +820,14 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   double* bscale = p->sc16.as<double>();
   float* unscale = reinterpret_cast<float*>(bscale + nd * nrp);
   {
-    size_t tot = (size_t)n * nrp * nd;
     if (part32) {
-      pack_dens32<<<grid1d(tot), 256, 0, st>>>(a, b, reinterpret_cast<cplxf*>(p->dens.p), n, nrhs, nrp, nd, col0);
-      dens16_scales<<<nd * nrp, 256, 0, st>>>(a, b ? b : a, n, nrhs, nrp, col0, eK[0], eK[1], bscale, unscale);
+      pack_dens_t<cplxf><<<dim3((n + 31) / 32, nd), 256, 0, st>>>(a, b, reinterpret_cast<cplxf*>(p->dens.p), n,
+                                                                 nrhs, nrp, nd, col0);
+      dens16_scales<<<nd * nrp, 1024, 0, st>>>(a, b ? b : a, n, nrhs, nrp, col0, eK[0], eK[1], bscale, unscale);
       pack_dens16<<<grid1d((size_t)nb * 4 * nd * nrp), 256, 0, st>>>(a, b ? b : a, bscale, p->dens16.as<uint4>(),
                                                                       n, nrhs, nrp, nd, col0, nb);
     } else {
-      pack_dens<<<grid1d(tot), 256, 0, st>>>(a, b, p->dens.as<cplx>(), n, nrhs, nrp, nd, col0);
+      pack_dens_t<cplx><<<dim3((n + 31) / 32, nd), 256, 0, st>>>(a, b, p->dens.as<cplx>(), n, nrhs, nrp, nd, col0);
     }
   }
   SweepParams sp;
