@@ -305,11 +305,11 @@ __global__ __launch_bounds__(256) void gj_panel(GJBatch b, int k, int par, int n
   __shared__ double bv[4];
   __shared__ int bi[4];
   const int tid = threadIdx.x;
-  for (int e = tid; e < m * nb; e += 256) {
-    const int r = e / nb, t = e - r * nb;
-    V[r * nbw + t] = A[(size_t)(k + r) * w + k + t];
+  for (int r = tid; r < m; r += 256) {  // one row per thread: no division
+    const cplx* ar = A + (size_t)(k + r) * w + k;
+    for (int t = 0; t < nb; ++t) V[r * nbw + t] = ar[t];
+    orig[r] = k + r;
   }
-  for (int r = tid; r < m; r += 256) orig[r] = k + r;
   __syncthreads();
   for (int t = 0; t < nb; ++t) {
     // pivot: wave-level argmax (ties to the lower row), then across the 4 waves
@@ -369,12 +369,13 @@ __global__ __launch_bounds__(256) void gj_panel(GJBatch b, int k, int par, int n
       const cplx pv = V[t * nbw + t];
       const double den = pv.re * pv.re + pv.im * pv.im;
       const cplx inv = {pv.re / den, -pv.im / den};
-      for (int e = tid; e < (m - t - 1) * nc; e += 256) {
-        const int r = t + 1 + e / nc, u = t + 1 + e % nc;
+      for (int r = t + 1 + tid; r < m; r += 256) {  // one row per thread
         const cplx l = cmul(V[r * nbw + t], inv);
-        const cplx pu = V[t * nbw + u];
-        cplx& x = V[r * nbw + u];
-        x = {x.re - (l.re * pu.re - l.im * pu.im), x.im - (l.re * pu.im + l.im * pu.re)};
+        for (int u = t + 1; u < nb; ++u) {
+          const cplx pu = V[t * nbw + u];
+          cplx& x = V[r * nbw + u];
+          x = {x.re - (l.re * pu.re - l.im * pu.im), x.im - (l.re * pu.im + l.im * pu.re)};
+        }
       }
     }
     __syncthreads();
