@@ -220,8 +220,8 @@ def main():
                     help="also run one device-to-device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU row split is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
+              "a multi-GPU split of the sweep by target rows is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
