@@ -18,11 +18,18 @@
  *     of double; an n x nrhs complex array is column-major (column c starts
  *     at complex offset c*n);
  *   - pointers documented as "device" must point to device memory of the
- *     context's GPU; the library reads/writes them on the context stream and
- *     returns after that work has completed (every call is synchronous);
+ *     context's GPU, with the whole array inside one allocation; the library
+ *     checks this (hipPointerGetAttributes, hipMemGetAddressRange) before any
+ *     kernel runs and returns DP_EINVAL otherwise (also when an operation's
+ *     input and output overlap); it reads/writes them on the context stream
+ *     and returns after that work has completed (every call is synchronous);
  *   - "host" pointers are read/written before the call returns;
  *   - the caller owns every buffer it passes; the library copies what it
- *     keeps and frees its own allocations in the matching destroy call;
+ *     keeps and frees its own allocations in the matching destroy call.  Its
+ *     device memory is stream-ordered (hipMallocAsync / hipFreeAsync on the
+ *     context stream, kept in the device's memory pool), so destroying a
+ *     problem does not wait for the device; destroy every problem before its
+ *     context;
  *   - return value: DP_OK (0) on success, DP_ENOCONV (> 0, a warning) when a
  *     solve stopped before reaching the tolerance, a negative DP_E* code on
  *     error; dp_last_error() then describes it (thread-local string);

@@ -160,10 +160,12 @@ def _check(name, rc, allow=()):
     return rc
 
 
-def _ptr(t):
-    """Device pointer of a torch tensor (complex128 or float64, contiguous)."""
-    if t is None:
-        return None
+def _ptr(t, ctx):
+    """Device pointer of a contiguous torch tensor on the context's GPU."""
+    if not getattr(t, "is_cuda", False):
+        raise ValueError("expected a torch tensor in device memory")
+    if t.device.index != ctx.device:
+        raise ValueError(f"tensor is on device {t.device.index}, the context on device {ctx.device}")
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
     return ctypes.c_void_p(t.data_ptr())
@@ -265,28 +267,28 @@ def dp_rhs_plane_wave(p, angles, f):
     nr = _cols(f, p.n)
     if nr != a.size:
         raise ValueError("angles / columns mismatch")
-    _check("dp_rhs_plane_wave", lib().dp_rhs_plane_wave(p.h, nr, ap, _ptr(f)))
+    _check("dp_rhs_plane_wave", lib().dp_rhs_plane_wave(p.h, nr, ap, _ptr(f, p.ctx)))
 
 
 def dp_matvec(p, q, y):
     nr = _cols(q, p.n)
     if _cols(y, p.n) != nr:
         raise ValueError("shape mismatch")
-    _check("dp_matvec", lib().dp_matvec(p.h, nr, _ptr(q), _ptr(y)))
+    _check("dp_matvec", lib().dp_matvec(p.h, nr, _ptr(q, p.ctx), _ptr(y, p.ctx)))
 
 
 def dp_matvec_mixed(p, q, y):
     nr = _cols(q, p.n)
     if _cols(y, p.n) != nr:
         raise ValueError("shape mismatch")
-    _check("dp_matvec_mixed", lib().dp_matvec_mixed(p.h, nr, _ptr(q), _ptr(y)))
+    _check("dp_matvec_mixed", lib().dp_matvec_mixed(p.h, nr, _ptr(q, p.ctx), _ptr(y, p.ctx)))
 
 
 def dp_layer_apply(p, op, q, y):
     nr = _cols(q, p.n)
     if _cols(y, p.n) != nr:
         raise ValueError("shape mismatch")
-    _check("dp_layer_apply", lib().dp_layer_apply(p.h, int(op), nr, _ptr(q), _ptr(y)))
+    _check("dp_layer_apply", lib().dp_layer_apply(p.h, int(op), nr, _ptr(q, p.ctx), _ptr(y, p.ctx)))
 
 
 W_AUTO, W_SPARSE, W_DENSE = 0, 1, 2
@@ -301,14 +303,14 @@ def dp_precond_apply(p, v, z):
     nr = _cols(v, p.n)
     if _cols(z, p.n) != nr:
         raise ValueError("shape mismatch")
-    _check("dp_precond_apply", lib().dp_precond_apply(p.h, nr, _ptr(v), _ptr(z)))
+    _check("dp_precond_apply", lib().dp_precond_apply(p.h, nr, _ptr(v, p.ctx), _ptr(z, p.ctx)))
 
 
 def dp_precond_apply_mixed(p, v, z):
     nr = _cols(v, p.n)
     if _cols(z, p.n) != nr:
         raise ValueError("shape mismatch")
-    _check("dp_precond_apply_mixed", lib().dp_precond_apply_mixed(p.h, nr, _ptr(v), _ptr(z)))
+    _check("dp_precond_apply_mixed", lib().dp_precond_apply_mixed(p.h, nr, _ptr(v, p.ctx), _ptr(z, p.ctx)))
 
 
 def dp_precond_get_info(p):
@@ -339,7 +341,7 @@ def dp_solve(p, f, q, tol=1e-8, restart=80, max_iters=2000, use_precond=False, p
     info = SolveInfo()
     its = np.zeros(nr, np.int64)
     rel = np.zeros(nr, np.float64)
-    rc = _check("dp_solve", lib().dp_solve(p.h, nr, _ptr(f), _ptr(q), ctypes.byref(o), ctypes.byref(info),
+    rc = _check("dp_solve", lib().dp_solve(p.h, nr, _ptr(f, p.ctx), _ptr(q, p.ctx), ctypes.byref(o), ctypes.byref(info),
                                            its.ctypes.data_as(ctypes.c_void_p),
                                            rel.ctypes.data_as(ctypes.c_void_p)))
     out = {f_: getattr(info, f_) for f_, _ in SolveInfo._fields_}
@@ -356,7 +358,7 @@ def dp_autotune(p, nrhs, precision=DP_PREC_FP64):
 
 
 def dp_hankel_dev(ctx, z, out):
-    _check("dp_hankel_dev", lib().dp_hankel_dev(ctx.h, z.numel(), _ptr(z), _ptr(out)))
+    _check("dp_hankel_dev", lib().dp_hankel_dev(ctx.h, z.numel(), _ptr(z, ctx), _ptr(out, ctx)))
 
 
 def dp_hankel_host(z):

@@ -22,28 +22,138 @@ void set_error(const char* fmt, ...) {
   va_end(ap);
 }
 
+static thread_local hipStream_t g_alloc_stream = nullptr;
+
+AllocStream::AllocStream(hipStream_t s) : prev(g_alloc_stream) { g_alloc_stream = s; }
+AllocStream::~AllocStream() { g_alloc_stream = prev; }
+
+// The default memory pool of each device keeps freed memory for reuse
+// (release threshold: never), and reuses a block on another stream only once
+// its release has completed, never by making that stream wait for the other.
+static void configure_pool(int device) {
+  static std::mutex mu;
+  static std::vector<char> done;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)done.size() <= device) done.resize(device + 1, 0);
+  if (done[device]) return;
+  done[device] = 1;
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess || !pool) {
+    (void)hipGetLastError();
+    return;
+  }
+  uint64_t keep = ~0ull;
+  int no = 0;
+  (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  (void)hipMemPoolSetAttribute(pool, hipMemPoolReuseAllowInternalDependencies, &no);
+  (void)hipGetLastError();
+}
+
 int DevBuf::reserve(size_t want) {
   if (want <= bytes && p) return DP_OK;
   release();
   if (want == 0) want = 8;
-  if (hipMalloc(&p, want) != hipSuccess) {
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) configure_pool(dev);
+  if (hipMallocAsync(&p, want, g_alloc_stream) != hipSuccess) {
     p = nullptr;
     bytes = 0;
     (void)hipGetLastError();
-    set_error("hipMalloc of %zu bytes failed", want);
+    set_error("device allocation of %zu bytes failed", want);
     return DP_ENOMEM;
   }
+  s = g_alloc_stream;
   bytes = want;
   return DP_OK;
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p) (void)hipFreeAsync(p, s);
   p = nullptr;
   bytes = 0;
+  s = nullptr;
+}
+
+int pinned_borrow(dp_ctx* c, size_t bytes, void** out, size_t* got) {
+  {
+    std::lock_guard<std::mutex> lk(c->pin_mu);
+    for (size_t i = 0; i < c->pin_free.size(); ++i) {
+      if (c->pin_free[i].second >= bytes) {
+        *out = c->pin_free[i].first;
+        *got = c->pin_free[i].second;
+        c->pin_free.erase(c->pin_free.begin() + (long)i);
+        return DP_OK;
+      }
+    }
+  }
+  // grow in steps of 64 KiB so that later, slightly larger solves fit
+  const size_t want = (bytes + 65535) / 65536 * 65536;
+  void* h = nullptr;
+  if (hipHostMalloc(&h, want, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("pinned host allocation of %zu bytes failed", want);
+    return DP_ENOMEM;
+  }
+  *out = h;
+  *got = want;
+  return DP_OK;
+}
+
+void pinned_return(dp_ctx* c, void* p, size_t bytes) {
+  std::lock_guard<std::mutex> lk(c->pin_mu);
+  c->pin_free.emplace_back(p, bytes);
 }
 
 static bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// A pointer documented as "device" must lie in device memory of the
+// context's GPU, with `bytes` bytes inside one allocation; otherwise the call
+// is refused before any kernel could touch it.
+static int check_device_ptr(const dp_ctx* c, const void* ptr, size_t bytes, const char* fn, const char* name) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("%s: %s is not device memory of device %d", fn, name, c->device);
+    return DP_EINVAL;
+  }
+  if ((a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) || a.device != c->device) {
+    set_error("%s: %s is not device memory of device %d (memory type %d, device %d)", fn, name, c->device,
+              (int)a.type, a.device);
+    return DP_EINVAL;
+  }
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(ptr)) == hipSuccess) {
+    const char* b = static_cast<const char*>(base);
+    const char* q = static_cast<const char*>(ptr);
+    if (q + bytes > b + size) {
+      set_error("%s: %s holds %zu bytes from its address, %zu needed", fn, name, (size_t)(b + size - q), bytes);
+      return DP_EINVAL;
+    }
+  } else {
+    (void)hipGetLastError();
+  }
+  return DP_OK;
+}
+
+static bool overlap(const void* a, const void* b, size_t bytes) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+// Input and output of an n x nrhs complex operation: both device memory of
+// the context's GPU, large enough, and disjoint.
+static int check_io(const dp_problem* p, int64_t nrhs, const void* in, const void* out, const char* fn) {
+  const size_t bytes = (size_t)p->n * (size_t)nrhs * 16;
+  DP_TRY(check_device_ptr(p->ctx, in, bytes, fn, "input"));
+  DP_TRY(check_device_ptr(p->ctx, out, bytes, fn, "output"));
+  if (overlap(in, out, bytes)) {
+    set_error("%s: input and output overlap", fn);
+    return DP_EINVAL;
+  }
+  return DP_OK;
+}
 
 }  // namespace dp
 
@@ -57,7 +167,9 @@ using namespace dp;
     }                              \
   } while (0)
 
-#define DP_SETDEV(ctx) DP_HIP(hipSetDevice((ctx)->device))
+#define DP_SETDEV(ctx)                    \
+  DP_HIP(hipSetDevice((ctx)->device)); \
+  AllocStream alloc_stream_guard_((ctx)->stream)
 
 extern "C" {
 
@@ -87,10 +199,10 @@ int dp_ctx_create(int device, void* stream, dp_ctx** out) {
 
 void dp_ctx_destroy(dp_ctx* c) {
   if (!c) return;
-  if (c->own_stream) {
-    (void)hipSetDevice(c->device);
-    (void)hipStreamDestroy(c->stream);
-  }
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& b : c->pin_free) (void)hipHostFree(b.first);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -168,7 +280,9 @@ int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nr
 void dp_problem_destroy(dp_problem* p) {
   if (!p) return;
   (void)hipSetDevice(p->ctx->device);
-  (void)hipStreamSynchronize(p->ctx->stream);
+  AllocStream alloc_stream_guard_(p->ctx->stream);
+  // the releases below are ordered on the stream after the problem's work:
+  // no wait for the device here
   if (p->pc) precond_destroy(p->pc);
   p->clock.destroy();
   p->clock32.destroy();
@@ -202,6 +316,7 @@ int dp_problem_kappa(const dp_problem* p, double* kappa) {
 int dp_rhs_plane_wave(dp_problem* p, int64_t nrhs, const double* angles, double* f) {
   DP_CHECK(p && angles && f && nrhs >= 1, "dp_rhs_plane_wave: bad argument");
   DP_SETDEV(p->ctx);
+  DP_TRY(check_device_ptr(p->ctx, f, (size_t)p->n * nrhs * 16, "dp_rhs_plane_wave", "f"));
   DevBuf a;
   DP_TRY(a.reserve(nrhs * sizeof(double)));
   DP_HIP(hipMemcpyAsync(a.p, angles, nrhs * sizeof(double), hipMemcpyHostToDevice, p->ctx->stream));
@@ -212,8 +327,9 @@ int dp_rhs_plane_wave(dp_problem* p, int64_t nrhs, const double* angles, double*
 }
 
 int dp_matvec(dp_problem* p, int64_t nrhs, const double* q, double* y) {
-  DP_CHECK(p && q && y && nrhs >= 1 && q != y, "dp_matvec: bad argument");
+  DP_CHECK(p && q && y && nrhs >= 1, "dp_matvec: bad argument");
   DP_SETDEV(p->ctx);
+  DP_TRY(check_io(p, nrhs, q, y, "dp_matvec"));
   DP_TRY(matvec(p, (int)nrhs, reinterpret_cast<const cplx*>(q), reinterpret_cast<cplx*>(y)));
   DP_HIP(hipStreamSynchronize(p->ctx->stream));
   p->clock.collect();
@@ -221,8 +337,9 @@ int dp_matvec(dp_problem* p, int64_t nrhs, const double* q, double* y) {
 }
 
 int dp_matvec_mixed(dp_problem* p, int64_t nrhs, const double* q, double* y) {
-  DP_CHECK(p && q && y && nrhs >= 1 && q != y, "dp_matvec_mixed: bad argument");
+  DP_CHECK(p && q && y && nrhs >= 1, "dp_matvec_mixed: bad argument");
   DP_SETDEV(p->ctx);
+  DP_TRY(check_io(p, nrhs, q, y, "dp_matvec_mixed"));
   DP_TRY(matvec(p, (int)nrhs, reinterpret_cast<const cplx*>(q), reinterpret_cast<cplx*>(y), 1));
   DP_HIP(hipStreamSynchronize(p->ctx->stream));
   p->clock.collect();
@@ -231,10 +348,11 @@ int dp_matvec_mixed(dp_problem* p, int64_t nrhs, const double* q, double* y) {
 }
 
 int dp_layer_apply(dp_problem* p, int op, int64_t nrhs, const double* q, double* y) {
-  DP_CHECK(p && q && y && nrhs >= 1 && q != y, "dp_layer_apply: bad argument");
+  DP_CHECK(p && q && y && nrhs >= 1, "dp_layer_apply: bad argument");
   DP_CHECK(op == DP_OP_S || op == DP_OP_D || op == DP_OP_DP || op == DP_OP_DS, "dp_layer_apply: op %d", op);
   DP_CHECK(op != DP_OP_DS || is_pow2(p->n), "dp_layer_apply: D_s needs a power-of-two n");
   DP_SETDEV(p->ctx);
+  DP_TRY(check_io(p, nrhs, q, y, "dp_layer_apply"));
   if (op == DP_OP_DS) {
     DP_TRY(spectral_derivative(p, (int)nrhs, reinterpret_cast<const cplx*>(q), reinterpret_cast<cplx*>(y)));
   } else {
@@ -265,24 +383,26 @@ int dp_precond_build(dp_problem* p, const dp_precond_opts* opts) {
 }
 
 int dp_precond_apply(dp_problem* p, int64_t nrhs, const double* v, double* z) {
-  DP_CHECK(p && v && z && nrhs >= 1 && v != z, "dp_precond_apply: bad argument");
+  DP_CHECK(p && v && z && nrhs >= 1, "dp_precond_apply: bad argument");
   if (!p->pc) {
     set_error("dp_precond_apply: call dp_precond_build first");
     return DP_ESTATE;
   }
   DP_SETDEV(p->ctx);
+  DP_TRY(check_io(p, nrhs, v, z, "dp_precond_apply"));
   DP_TRY(precond_apply(p, (int)nrhs, reinterpret_cast<const cplx*>(v), reinterpret_cast<cplx*>(z)));
   DP_HIP(hipStreamSynchronize(p->ctx->stream));
   return DP_OK;
 }
 
 int dp_precond_apply_mixed(dp_problem* p, int64_t nrhs, const double* v, double* z) {
-  DP_CHECK(p && v && z && nrhs >= 1 && v != z, "dp_precond_apply_mixed: bad argument");
+  DP_CHECK(p && v && z && nrhs >= 1, "dp_precond_apply_mixed: bad argument");
   if (!p->pc) {
     set_error("dp_precond_apply_mixed: call dp_precond_build first");
     return DP_ESTATE;
   }
   DP_SETDEV(p->ctx);
+  DP_TRY(check_io(p, nrhs, v, z, "dp_precond_apply_mixed"));
   DP_TRY(precond_apply(p, (int)nrhs, reinterpret_cast<const cplx*>(v), reinterpret_cast<cplx*>(z), 1));
   DP_HIP(hipStreamSynchronize(p->ctx->stream));
   return DP_OK;
@@ -308,7 +428,7 @@ int dp_precond_export(dp_problem* p, int64_t* seg_off, int64_t* seg_len, int64_t
 
 int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_solve_opts* opts,
              dp_solve_info* info, int64_t* iters, double* relres) {
-  DP_CHECK(p && f && q && nrhs >= 1 && f != q, "dp_solve: bad argument");
+  DP_CHECK(p && f && q && nrhs >= 1, "dp_solve: bad argument");
   dp_solve_opts o = {1e-8, 80, 2000, 0, DP_PREC_FP64, 1e-5};
   if (opts) o = *opts;
   if (o.inner_tol <= 0) o.inner_tol = 1e-5;
@@ -319,6 +439,7 @@ int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_s
     return DP_ESTATE;
   }
   DP_SETDEV(p->ctx);
+  DP_TRY(check_io(p, nrhs, f, q, "dp_solve"));
   return solve(p, (int)nrhs, reinterpret_cast<const cplx*>(f), reinterpret_cast<cplx*>(q), &o, info, iters,
                relres);
 }
@@ -326,6 +447,9 @@ int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_s
 int dp_hankel_dev(dp_ctx* ctx, int64_t m, const double* z, double* out) {
   DP_CHECK(ctx && z && out && m >= 0, "dp_hankel_dev: bad argument");
   DP_SETDEV(ctx);
+  if (m == 0) return DP_OK;
+  DP_TRY(check_device_ptr(ctx, z, (size_t)m * 8, "dp_hankel_dev", "z"));
+  DP_TRY(check_device_ptr(ctx, out, (size_t)m * 32, "dp_hankel_dev", "out"));
   DP_TRY(hankel_eval_dev(m, z, out, ctx->stream));
   DP_HIP(hipStreamSynchronize(ctx->stream));
   return DP_OK;

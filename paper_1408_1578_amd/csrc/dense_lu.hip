@@ -485,12 +485,14 @@ int DenseLU::block_inverses(hipStream_t st) {
 // matrix-core launches; t and y are workspaces, so no product reads what
 // another writes.
 int DenseLU::solve(hipStream_t st, const cplx* z, cplx* u, int nrhs) {
-  const cplx* A = a.as<cplx>();
   const size_t bytes = (size_t)n * nrhs * sizeof(cplx);
   DP_TRY(tws.reserve(bytes));
   DP_TRY(yws.reserve(bytes));
-  cplx* t = tws.as<cplx>();
-  cplx* y = yws.as<cplx>();
+  return solve_ws(st, z, u, nrhs, tws.as<cplx>(), yws.as<cplx>());
+}
+
+int DenseLU::solve_ws(hipStream_t st, const cplx* z, cplx* u, int nrhs, cplx* t, cplx* y) const {
+  const cplx* A = a.as<cplx>();
   const size_t per = (size_t)kSB * kSB;
   gather_perm<<<nblocks((int64_t)n * nrhs, 8192), 256, 0, st>>>(z, t, perm.as<int>(), n, nrhs);
   for (int bk = 0; bk < nsb; ++bk) {

@@ -24,8 +24,12 @@ struct DenseLU {
   // on a zero pivot column
   int factor(hipStream_t st);
   int block_inverses(hipStream_t st);
-  // u = A^{-1} z for nrhs columns (n x nrhs column-major, z and u distinct)
+  // u = A^{-1} z for nrhs columns (n x nrhs column-major, z and u distinct),
+  // with the workspaces tws / yws (grown here as needed)
   int solve(hipStream_t st, const cplx* z, cplx* u, int nrhs);
+  // the same with caller-provided workspaces t and y (n x nrhs each): kernel
+  // launches only, no allocation
+  int solve_ws(hipStream_t st, const cplx* z, cplx* u, int nrhs, cplx* t, cplx* y) const;
   void release();
 };
 

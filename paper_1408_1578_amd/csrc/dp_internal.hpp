@@ -4,8 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <string>
 #include <map>
+#include <mutex>
+#include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/dirprec.h"
@@ -31,14 +33,28 @@ void set_error(const char* fmt, ...);
     if (r_ < 0) return r_;      \
   } while (0)
 
-// Device buffer that grows on demand (hipMalloc'd, owned by the library).
+// Device buffer that grows on demand, owned by the library.  Allocation and
+// release are stream-ordered (hipMallocAsync / hipFreeAsync on the stream
+// current in the calling thread, see AllocStream): releasing a buffer does
+// not wait for the device, so one problem's set-up or teardown does not drain
+// the kernels that other streams (other server slots) have queued.  The
+// memory returns to the device's pool, which keeps it for later allocations.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  hipStream_t s = nullptr;  // stream of the allocation; the release is ordered on it
   int reserve(size_t want);
   void release();
   template <class T>
   T* as() const { return static_cast<T*>(p); }
+};
+
+// The stream on which DevBuf allocations of the calling thread are ordered,
+// for the lifetime of this object (each C-ABI entry sets its context's stream).
+struct AllocStream {
+  hipStream_t prev;
+  explicit AllocStream(hipStream_t s);
+  ~AllocStream();
 };
 
 // One boundary node (64 bytes): position, outward normal, speed |x'(t)| and
@@ -94,6 +110,10 @@ struct dp_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // pinned host staging buffers for the per-step Krylov readbacks, kept for
+  // the context's lifetime and lent to one solve at a time
+  std::mutex pin_mu;
+  std::vector<std::pair<void*, size_t>> pin_free;
 };
 
 struct dp_problem {
@@ -143,6 +163,11 @@ struct dp_problem {
 };
 
 namespace dp {
+// Pinned host memory of at least `bytes` bytes lent by the context (reused
+// across solves and requests; hipHostFree, which waits for the device, only
+// runs when the context is destroyed).  Returned with pinned_return.
+int pinned_borrow(dp_ctx* c, size_t bytes, void** out, size_t* got);
+void pinned_return(dp_ctx* c, void* p, size_t bytes);
 // tables.hip
 int build_tables(dp_problem* p);
 // sweep.hip

@@ -9,6 +9,7 @@
 // cycle when its Givens residual estimate reaches tol; at each restart the
 // true residual f - A x is recomputed and decides convergence.
 #include <chrono>
+#include <thread>
 #include <complex>
 #include <cstring>
 #include <vector>
@@ -155,16 +156,34 @@ struct OwnedEvent {
   }
 };
 
-// Pinned host memory, freed with its owner.
-struct PinnedHost {
+// Pinned host memory lent by the context for the duration of one solve.
+struct PinnedLoan {
+  dp_ctx* c = nullptr;
   void* p = nullptr;
-  PinnedHost() = default;
-  PinnedHost(const PinnedHost&) = delete;
-  PinnedHost& operator=(const PinnedHost&) = delete;
-  ~PinnedHost() {
-    if (p) (void)hipHostFree(p);
+  size_t bytes = 0;
+  PinnedLoan() = default;
+  PinnedLoan(const PinnedLoan&) = delete;
+  PinnedLoan& operator=(const PinnedLoan&) = delete;
+  ~PinnedLoan() {
+    if (p) pinned_return(c, p, bytes);
   }
 };
+
+// Wait for `e` without holding a core: poll it, yielding the thread between
+// polls, for at most `spin_us` microseconds (the short tail of a step), then
+// block on it (the event is created with hipEventBlockingSync).
+static int wait_event(hipEvent_t e, int spin_us) {
+  const auto t0 = std::chrono::steady_clock::now();
+  while (true) {
+    const hipError_t q = hipEventQuery(e);
+    if (q == hipSuccess) return DP_OK;
+    if (q != hipErrorNotReady) DP_HIP(q);
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(spin_us)) break;
+    std::this_thread::yield();
+  }
+  DP_HIP(hipEventSynchronize(e));
+  return DP_OK;
+}
 
 // out[i * nrhs + c] = sum_bx partial[...]  (fixed order)
 __global__ void gram_reduce(const cplx* __restrict__ partial, int nbx, int kp1, int nrhs, cplx* out) {
@@ -369,13 +388,15 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
       g((size_t)(m + 1) * nrhs);
   std::vector<int> kc(nrhs);
   std::vector<char> active(nrhs), conv_est(nrhs);
-  OwnedEvent ev_mv;  // after each step's matrix-vector product
-  DP_HIP(hipEventCreateWithFlags(&ev_mv.e, hipEventDisableTiming));
+  OwnedEvent ev_mv, ev_rb;  // after each step's matrix-vector product / readback
+  DP_HIP(hipEventCreateWithFlags(&ev_mv.e, hipEventDisableTiming | hipEventBlockingSync));
+  DP_HIP(hipEventCreateWithFlags(&ev_rb.e, hipEventDisableTiming | hipEventBlockingSync));
   // pinned host copy of h1 | h2 | norm^2 | scale (the layout of `small`):
   // the per-step readback is one asynchronous copy, with no staging through
   // pageable memory
-  PinnedHost hpin;
-  DP_HIP(hipHostMalloc(&hpin.p, (2 * hsz + 2 * (size_t)nrhs) * sizeof(cplx), hipHostMallocDefault));
+  PinnedLoan hpin;
+  hpin.c = p->ctx;
+  DP_TRY(pinned_borrow(p->ctx, (2 * hsz + 2 * (size_t)nrhs) * sizeof(cplx), &hpin.p, &hpin.bytes));
   cplx* hbuf = static_cast<cplx*>(hpin.p);
   double* nbuf = reinterpret_cast<double*>(hbuf + 2 * hsz);
   double* sbuf = nbuf + nrhs;
@@ -429,16 +450,13 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
       }
       // h1, h2 and the norms in one copy (h2 and the norms sit at fixed offsets)
       DP_HIP(hipMemcpyAsync(hbuf, h1, 2 * hsz * sizeof(cplx) + nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      // wait (blocking) for the matrix-vector product, then poll the stream
-      // through the short orthogonalisation tail: a blocking wait for the
-      // readback itself adds the host thread's wake-up to every step
-      DP_HIP(hipEventSynchronize(ev_mv.e));
-      {
-        hipError_t q;
-        while ((q = hipStreamQuery(st)) == hipErrorNotReady) {
-        }
-        DP_HIP(q);
-      }
+      DP_HIP(hipEventRecord(ev_rb.e, st));
+      // sleep through the matrix-vector product, then poll the readback
+      // through the short orthogonalisation tail (a blocking wait there would
+      // add the thread's wake-up to every step), yielding the core between
+      // polls and blocking after 2 ms
+      DP_TRY(wait_event(ev_mv.e, 0));
+      DP_TRY(wait_event(ev_rb.e, 2000));
       tm.collect();
       ta.collect();
       p->clock.collect();

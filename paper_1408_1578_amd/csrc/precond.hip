@@ -28,6 +28,7 @@
 #include <map>
 #include <system_error>
 #include <thread>
+#include <mutex>
 #include <vector>
 
 #include "dp_internal.hpp"
@@ -1775,17 +1776,18 @@ static int run_seg_gemm(dp_problem* p, int which, int mrows, int kin, int yoff, 
 
 // u = floor(W)^{-1} z in FP64 (dense device LU, LDS-resident sparse solve, or
 // the level-scheduled sparse solve)
-static int w_solve(dp_problem* p, int nrhs, const cplx* z, cplx* u) {
+// with the workspaces t (level-scheduled solve) and dt, dy (dense solve),
+// each NW x nrhs; kernel launches only
+static int w_solve_ws(dp_problem* p, int nrhs, const cplx* z, cplx* u, cplx* t, cplx* dt, cplx* dy) {
   Precond* P = p->pc;
   hipStream_t st = p->ctx->stream;
   const int NW = P->NW;
-  if (P->dense_w) return P->dlu.solve(st, z, u, nrhs);
+  if (P->dense_w) return P->dlu.solve_ws(st, z, u, nrhs, dt, dy);
   if (P->lds_solve) {
     tri_solve_wave<cplx><<<nrhs, 64, (size_t)(NW + 1) * sizeof(cplx), st>>>(
         z, u, NW, P->pin.as<int>(), P->pout.as<int>(), P->slots.as<Slot<cplx>>(), P->nsteps);
     return DP_OK;
   }
-  cplx* t = P->wt.as<cplx>();
   gather_rows<<<grid1((size_t)NW * nrhs), 256, 0, st>>>(z, t, P->pin.as<int>(), NW, nrhs);
   const int cpb = nrhs < 16 ? nrhs : 16;
   const int nb = (nrhs + cpb - 1) / cpb;
@@ -1797,13 +1799,27 @@ static int w_solve(dp_problem* p, int nrhs, const cplx* z, cplx* u) {
   return DP_OK;
 }
 
+// u = floor(W)^{-1} z with the preconditioner's own workspaces (the dense
+// solve grows its workspaces as needed)
+static int w_solve(dp_problem* p, int nrhs, const cplx* z, cplx* u) {
+  Precond* P = p->pc;
+  if (P->dense_w) return P->dlu.solve(p->ctx->stream, z, u, nrhs);
+  return w_solve_ws(p, nrhs, z, u, P->wt.as<cplx>(), nullptr, nullptr);
+}
+
+// Workspaces of one FP64 apply for nrhs columns: y, un (n x nrhs); g, z, u,
+// t, and for a dense floor(W) dt, dy (NW x nrhs)
+struct ApplyWs {
+  cplx *y, *un, *g, *z, *u, *t, *dt, *dy;
+};
+
 // eq. (19) on nrhs columns, kernels only (no allocation, no host sync): the
-// sequence that is captured into a graph.  Workspaces must hold nrhs columns.
-static int apply_core(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
+// sequence that is captured into a graph, and the apply of the entry point
+// that allocates nothing.
+static int apply_core_ws(dp_problem* p, int nrhs, const cplx* v, cplx* q, const ApplyWs& w) {
   Precond* P = p->pc;
   const int n = (int)p->n, NW = P->NW;
-  cplx *y = P->wy.as<cplx>(), *g = P->wg.as<cplx>(), *z = P->wz.as<cplx>(), *u = P->wu.as<cplx>(),
-       *un = P->wn.as<cplx>();
+  cplx *y = w.y, *g = w.g, *z = w.z, *u = w.u, *un = w.un;
   enum { BINV = 0, UU = 1, UT = 2, TT = 3 };
   // y = B^{-1} v
   DP_TRY(run_seg_gemm<cplx>(p, BINV, 0, 0, 0, 0, v, n, nullptr, y, n, nrhs));
@@ -1812,7 +1828,7 @@ static int apply_core(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
   // z = floor(T) g
   DP_TRY(run_seg_gemm<cplx>(p, TT, 1, 1, 1, 0, g, NW, nullptr, z, NW, nrhs));
   // u = floor(W)^{-1} z
-  DP_TRY(w_solve(p, nrhs, z, u));
+  DP_TRY(w_solve_ws(p, nrhs, z, u, w.t, w.dt, w.dy));
   // h = z - floor(T) u  (into g)
   DP_TRY(run_seg_gemm<cplx>(p, TT, 1, 1, 1, 1, u, NW, z, g, NW, nrhs));
   // un = U h
@@ -1821,6 +1837,14 @@ static int apply_core(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
   DP_TRY(run_seg_gemm<cplx>(p, BINV, 0, 0, 0, 1, un, n, y, q, n, nrhs));
   DP_HIP(hipGetLastError());
   return DP_OK;
+}
+
+// The FP64 apply on the preconditioner's workspaces (sized by precond_apply)
+static int apply_core(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
+  Precond* P = p->pc;
+  const ApplyWs w{P->wy.as<cplx>(), P->wn.as<cplx>(), P->wg.as<cplx>(), P->wz.as<cplx>(),
+                  P->wu.as<cplx>(), P->wt.as<cplx>(), P->dlu.tws.as<cplx>(), P->dlu.yws.as<cplx>()};
+  return apply_core_ws(p, nrhs, v, q, w);
 }
 
 // The same sequence with single-precision tables and vectors (FP64 in and
@@ -1891,6 +1915,10 @@ int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q, int prec) {
   DP_TRY(P->wz.reserve(bw));
   DP_TRY(P->wu.reserve(bw));
   DP_TRY(P->wt.reserve(bw));
+  if (P->dense_w) {
+    DP_TRY(P->dlu.tws.reserve(bw));
+    DP_TRY(P->dlu.yws.reserve(bw));
+  }
   if (prec) {
     const size_t sn = bn / 2, sw = bw / 2;
     DP_TRY(P->sv.reserve(sn));

@@ -103,6 +103,10 @@ namespace {
 // One request on the worker's context (every call below is synchronous).
 void run_request(dp_ctx* ctx, Request& r) {
   dp_problem* p = nullptr;
+  // data and solution: stream-ordered device buffers, released without a
+  // wait for the device (other slots' kernels keep running)
+  dp::AllocStream alloc_guard(ctx->stream);
+  dp::DevBuf fdb, qdb;
   void* fd = nullptr;
   void* qd = nullptr;
   const size_t bytes = (size_t)r.n * r.nrhs * 16;
@@ -118,10 +122,12 @@ void run_request(dp_ctx* ctx, Request& r) {
   }
   hipStream_t st = ctx->stream;
   if (r.opts.use_precond) rc = dp_precond_build(p, nullptr);
-  if (rc == DP_OK && (hipMalloc(&fd, bytes) != hipSuccess || hipMalloc(&qd, bytes) != hipSuccess)) {
+  if (rc == DP_OK && (fdb.reserve(bytes) != DP_OK || qdb.reserve(bytes) != DP_OK)) {
     dp::set_error("request %lld: device allocation of %zu bytes failed", (long long)r.id, 2 * bytes);
     rc = DP_ENOMEM;
   }
+  fd = fdb.p;
+  qd = qdb.p;
   if (rc == DP_OK) {
     if (!r.angles.empty()) {
       rc = dp_rhs_plane_wave(p, r.nrhs, r.angles.data(), static_cast<double*>(fd));
@@ -145,8 +151,8 @@ void run_request(dp_ctx* ctx, Request& r) {
   }
   if (rc < 0) fail(rc);
   else r.rc = rc;
-  if (fd) (void)hipFree(fd);
-  if (qd) (void)hipFree(qd);
+  fdb.release();
+  qdb.release();
   dp_problem_destroy(p);
 }
 

@@ -101,3 +101,47 @@ def test_random_star_131072_mixed_single_rhs():
     Arow = 0.5 * np.eye(b.n)[rows] + lay["D"] - 1j * eta * lay["S"]
     res = np.abs(Arow @ Q - f[rows]) / np.linalg.norm(f) * np.sqrt(b.n)
     assert np.max(res) < 1e-6
+
+
+def test_star_mixed_solve_4096_vs_dense_oracle():
+    # the five-petal star at n = 4096 (10 points per wavelength, sound-soft),
+    # one plane wave at a seeded angle: FP32 preconditioner and single-precision
+    # corrections inside FP64 refinement, against the oracle's dense solve
+    b, om, eta, kind = config_boundary("star", 4096)
+    ang = plane_wave_angles(1, "random", seed=0)
+    A = ny.soft_matrix(b, om, eta)
+    F = ny.plane_wave_rhs(b, om, ang, kind)
+    Q = np.linalg.solve(A, F)
+    p = problem(b, om, eta, kind)
+    dp.dp_precond_build(p)
+    q = empty(b.n, 1)
+    info = dp.dp_solve(p, to_dev(F), q, tol=1e-8, use_precond=True, precision=dp.DP_PREC_MIXED)
+    assert info["converged"] and info["relres_max"] <= 1e-8 and info["refinements"] >= 2
+    Qg = to_host(q)
+    assert relerr(Qg, Q) < 1e-6
+    res = np.linalg.norm(F - A @ Qg) / np.linalg.norm(F)
+    assert res < 2e-8
+
+
+def test_star_mixed_solve_16384_sampled_oracle_rows():
+    # the star at n = 16384: no dense oracle solve, so the FP64 residual
+    # f - A q of the mixed solve is recomputed by the oracle at 64 sampled rows
+    # (root-mean-square residual <= 1e-8 ||f||/sqrt(n) allows rows a few times
+    # that; 1e-7 leaves a margin of ten)
+    b, om, eta, kind = config_boundary("star", 16384)
+    ang = plane_wave_angles(1, "random", seed=0)
+    F = ny.plane_wave_rhs(b, om, ang, kind)
+    p = problem(b, om, eta, kind)
+    dp.dp_precond_build(p)
+    q = empty(b.n, 1)
+    info = dp.dp_solve(p, to_dev(F), q, tol=1e-8, use_precond=True, precision=dp.DP_PREC_MIXED)
+    assert info["converged"] and info["relres_max"] <= 1e-8
+    Qg = to_host(q)[:, 0]
+    rows = np.concatenate([[0, 1, b.n - 1], np.sort(np.random.default_rng(2).choice(b.n, 61, replace=False))])
+    r = ny.soft_matrix(b, om, eta, rows) @ Qg - F[rows, 0]
+    rms_f = np.linalg.norm(F) / np.sqrt(b.n)
+    assert np.max(np.abs(r)) < 1e-7 * rms_f, np.max(np.abs(r)) / rms_f
+    # and the FP64 solver reaches the same density
+    q64 = empty(b.n, 1)
+    dp.dp_solve(p, to_dev(F), q64, tol=1e-8, use_precond=True)
+    assert relerr(Qg, to_host(q64)[:, 0]) < 1e-6

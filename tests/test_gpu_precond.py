@@ -96,13 +96,18 @@ def test_full_size_kite_hard_apply():
     z = empty(b.n, 2)
     dp.dp_precond_apply(p, to_dev(v), z)
     assert relerr(to_host(z), pc.apply(P, v)) < 1e-10
+    # the FP64 apply with the bench's 64 columns
+    v64 = random_density(b.n, 64, seed=10)
+    ref64 = pc.apply(P, v64)
+    z64 = empty(b.n, 64)
+    dp.dp_precond_apply(p, to_dev(v64), z64)
+    assert relerr(to_host(z64), ref64) < 1e-10
     # the single-precision apply of the correction solves with the bench's
     # 64 columns (matrix-core segment products, one wave per column in the
     # triangular solves): FP32 tables and vectors, checked at 2e-5
-    v64 = random_density(b.n, 64, seed=10)
     z64 = empty(b.n, 64)
     dp.dp_precond_apply_mixed(p, to_dev(v64), z64)
-    err = relerr(to_host(z64), pc.apply(P, v64))
+    err = relerr(to_host(z64), ref64)
     assert 1e-12 < err < 2e-5
 
 
