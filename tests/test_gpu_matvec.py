@@ -174,8 +174,7 @@ def test_disk_eigenfunctions_large_n(kind, prec):
     # moduli of its terms, not to the result.  With c = sum_j |S_0j| those
     # are eta c (soft: S-part) and (m^2 + omega^2) c / eta (hard, Maue: the
     # S-sweeps of D_s q and omega^2 nu q), which near |m| = omega exceed
-    # |lambda_m| 10-30x; measured errors stay below 1e-6 of that scale, and
-    # are ~1e-6 |lambda_m| for the typical mode
+    # |lambda_m| 10-30x; measured errors stay below 1e-6 of that scale
     j = np.arange(1, n)
     c = np.sum(np.abs(sps.hankel1(0, om * 2 * np.sin(np.pi * j / n)))) / 4 * b.ds
     if kind == 0:
@@ -183,7 +182,9 @@ def test_disk_eigenfunctions_large_n(kind, prec):
     else:
         scale = np.abs(lam) + (m.astype(float) ** 2 + om ** 2) * c / om
     assert np.all(err < 2e-6 * scale), (err / scale).max()
-    assert np.median(err / np.abs(lam)) < 3e-6, np.median(err / np.abs(lam))
+    # typical mode: ~6e-7 |lambda_m| soft, ~5e-6 hard (D_s multiplies by |m|
+    # twice around the S-sweep)
+    assert np.median(err / np.abs(lam)) < (3e-6 if kind == 0 else 1e-5), np.median(err / np.abs(lam))
     assert (err / np.abs(lam)).max() > 1e-12      # it really is the single-precision operator
 
 
