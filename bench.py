@@ -1,21 +1,26 @@
 """Benchmark: directional-preconditioned CFIE solves on one MI355X.
 
-Workload (one step): the sound-hard kite x = cos t + 0.65 cos 2t - 0.65,
-y = 1.5 sin t, n = 32768 arclength-equispaced nodes at 10 points per
-wavelength (omega = 2208.1), eta = omega, 64 incident plane waves at angles
-2 pi k/64, all solved to FP64 relative residual 1e-8 with the directional
+Workload: the sound-hard kite x = cos t + 0.65 cos 2t - 0.65, y = 1.5 sin t,
+n = 32768 arclength-equispaced nodes at 10 points per wavelength
+(omega = 2208.1), eta = omega, 64 incident plane waves at angles 2 pi k/64,
+all solved to FP64 relative residual 1e-8 with the directional
 preconditioner.  Two solvers are timed on the same workload: mixed precision
 (iterative refinement: FP64 residuals, corrections from right-preconditioned
-GMRES(80) on the single-precision operator) and plain FP64 GMRES(80).  A step
-= preconditioner setup + plane-wave data + the batched solve (the problem's
-geometry, Kress table and near-field list are resident on the device before
-the timed region).  value = solved right-hand sides per second of the mixed
-solver; the FP64 solver's figures are reported beside it.
+GMRES(80) on the single-precision operator) and plain FP64 GMRES(80).
+
+A step is the whole job: problem creation from the host geometry (upload,
+Kress and diagonal tables, near-field list) -> preconditioner setup ->
+plane-wave data -> the batched solve -> q copied to host memory; the problem
+is destroyed after each step.  value = solved right-hand sides per second of
+the mixed solver over the timed steps; the FP64 solver's figures, and both
+solvers on a problem that stays resident (setup-excluded: preconditioner,
+data and solve only), are reported beside it.
 
 Prints one JSON line (metric, value, roofline of the dominant pair-sweep kernel
 from HIP events recorded by the library around each of its launches, both
-solvers' throughput and latency, and the CPU oracle's extrapolated rate on a
-bounded sample).
+solvers' throughput and latency, GMRES iterations with and without the
+preconditioner, the serving stream, and the CPU oracle's extrapolated rate on
+a bounded sample).
 """
 import argparse
 import json
@@ -67,10 +72,12 @@ def cpu_baseline(b, om, eta, nrhs, budget_s=25.0):
     """The oracle (dense Nystrom assembly + LU) timed on the host, on a sample.
 
     Sample: (a) oracle S and D' rows for 256 target rows at the full n (pair
-    evaluations scale with n^2 -> x n/256); (b) the oracle's dense hard matrix at
-    n0 = 2048 on the same curve and its LU + 64 triangular solves (cubic parts
-    scale with (n/n0)^3).  The extrapolated time of one 64-RHS dense solve at n
-    gives solves/s = nrhs / T.
+    evaluations scale with n^2 -> x n/256); (b) the oracle's dense hard matrix
+    at n0 = 1024 and 2048 on the same curve, its LU and 64 triangular solves;
+    the cubic parts (Maue products, LU) are extrapolated from n0 = 2048 with
+    (n/n0)^3, and the exponent measured between 1024 and 2048 is reported
+    beside it.  The extrapolated time of one 64-RHS dense solve at n gives
+    solves/s = nrhs / T.
     """
     import oracle.nystrom as ny
     from synth import sample_boundary, omega_for_ppw
@@ -82,33 +89,42 @@ def cpu_baseline(b, om, eta, nrhs, budget_s=25.0):
     ny.layer_rows(b, om, rows)
     t_rows = time.perf_counter() - t0
     t_pairs = t_rows * n / len(rows)
+    cubic = {}
+    for n0 in (1024, 2048):
+        b0 = sample_boundary(b.name, n0)
+        om0 = omega_for_ppw(n0, b0.L, 10.0)
+        t1 = time.perf_counter()
+        ny.layer_rows(b0, om0)
+        t_pairs0 = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        A0 = ny.hard_matrix(b0, om0, om0)                  # includes the pair work again
+        t_asm0 = time.perf_counter() - t1
+        F0 = ny.plane_wave_rhs(b0, om0, 2 * np.pi * np.arange(nrhs) / nrhs, 1)
+        t1 = time.perf_counter()
+        lu = sla.lu_factor(A0)
+        sla.lu_solve(lu, F0)
+        t_lu0 = time.perf_counter() - t1
+        cubic[n0] = max(t_asm0 - t_pairs0, 0.0) + t_lu0  # Maue products + LU + solves
     n0 = 2048
-    b0 = sample_boundary(b.name, n0)
-    om0 = omega_for_ppw(n0, b0.L, 10.0)
-    t1 = time.perf_counter()
-    lay = ny.layer_rows(b0, om0)
-    t_pairs0 = time.perf_counter() - t1
-    t1 = time.perf_counter()
-    A0 = ny.hard_matrix(b0, om0, om0)                  # includes the pair work again
-    t_asm0 = time.perf_counter() - t1
-    t_cubic_asm0 = max(t_asm0 - t_pairs0, 0.0)         # dense products of Maue's identity
-    F0 = ny.plane_wave_rhs(b0, om0, 2 * np.pi * np.arange(nrhs) / nrhs, 1)
-    t1 = time.perf_counter()
-    lu = sla.lu_factor(A0)
-    sla.lu_solve(lu, F0)
-    t_lu0 = time.perf_counter() - t1
-    scale3 = (n / n0) ** 3
-    T = t_pairs + (t_cubic_asm0 + t_lu0) * scale3
+    expo = float(np.log(cubic[2048] / cubic[1024]) / np.log(2.0)) if cubic[1024] > 0 else None
+    T = t_pairs + cubic[n0] * (n / n0) ** 3
     used = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    hi = host_info()
+    threads = hi["blas_threads"] or int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": nrhs / T,
         "unit": "solves/s",
         "cores": threads,
         "kind": "oracle",
+        "cpu_model": hi["cpu_model"],
+        "logical_cpus": hi["logical_cpus"],
+        "blas": hi["blas"],
+        "blas_threads": hi["blas_threads"],
+        "cubic_exponent_measured_1024_2048": expo,
         "sample": (f"extrapolated: oracle pair work on {len(rows)} of {n} rows (x{n // len(rows)}), "
-                   f"dense Maue assembly + LU + {nrhs} solves at n={n0} (x(n/{n0})^3); "
-                   f"{used:.1f} s of CPU wall time, projected {T:.0f} s per {nrhs}-RHS solve"),
+                   f"dense Maue assembly + LU + {nrhs} solves at n={n0} (x(n/{n0})^3; measured exponent "
+                   f"between n=1024 and 2048: {expo:.2f}); {used:.1f} s of CPU wall time, projected "
+                   f"{T:.0f} s per {nrhs}-RHS solve"),
     }
 
 
@@ -197,6 +213,31 @@ def serve_stream(dp, nreq, rate, slots, seed=7):
     return out
 
 
+def host_info():
+    """CPU model, BLAS library and its thread count of the host running the oracle."""
+    import platform
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas, blas_threads = "unknown", None
+    try:
+        import scipy.linalg  # noqa: F401  (loads LAPACK/BLAS)
+        from threadpoolctl import threadpool_info
+        pools = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        if pools:
+            blas = f"{pools[0].get('internal_api')} {pools[0].get('version')} ({os.path.basename(pools[0].get('filepath', ''))})"
+            blas_threads = pools[0].get("num_threads")
+    except Exception:  # threadpoolctl missing: report what is known
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "blas": blas, "blas_threads": blas_threads}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,8 +255,13 @@ def main():
                     help="also serve a stream of N independent requests (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2.5, help="mean arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=4)
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default sweep launch configuration (2048-block grid)")
+    ap.add_argument("--no-iteration-study", action="store_true",
+                    help="skip the unpreconditioned solves that give n_n beside n_p")
+    ap.add_argument("--resident-only", action="store_true",
+                    help="time only steps on a resident problem (no problem creation per step)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="also time the sweep tuner on a resident problem (informational; the "
+                         "timed steps create their problem and use the default launch configuration)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -231,10 +277,10 @@ def main():
     b, om, eta, kind = config_boundary("kite", args.n)
     nrhs = args.nrhs
     ctx = dp.Context(0)
-    prob = dp.Problem.from_boundary(ctx, b, om, eta, kind)
     angles = plane_wave_angles(nrhs)
     f = torch.empty((nrhs, b.n), dtype=torch.complex128, device="cuda:0")
     q = torch.empty_like(f)
+    q_host = torch.empty(q.shape, dtype=q.dtype, pin_memory=True)
     use_pc = not args.no_precond
     if args.copy_calibration:
         a = torch.empty(args.copy_calibration * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
@@ -246,33 +292,51 @@ def main():
         log(f"copy calibration: {args.copy_calibration} MiB read + written")
         del a, bb
 
-    def run(precision):
+    def run(precision, full):
+        """W + K steps of the whole job.  full: a step is problem creation (host
+        geometry in) -> preconditioner -> plane-wave data -> batched solve -> q in
+        host memory, the problem destroyed after it; otherwise the problem stays
+        resident and a step is preconditioner -> data -> solve (q on the device)."""
         prec = dp.DP_PREC_MIXED if precision == "mixed" else dp.DP_PREC_FP64
+        resident = None if full else dp.Problem.from_boundary(ctx, b, om, eta, kind)
+        tag = f"{precision}{'' if full else ', resident'}"
 
         def step():
             t0 = time.perf_counter()
+            prob = dp.Problem.from_boundary(ctx, b, om, eta, kind) if full else resident
             if use_pc:
                 dp.dp_precond_build(prob)
             dp.dp_rhs_plane_wave(prob, angles, f)
             info = dp.dp_solve(prob, f, q, tol=1e-8, restart=80, use_precond=use_pc, precision=prec)
-            return info, time.perf_counter() - t0
+            if full:
+                q_host.copy_(q)          # synchronous: q is in host memory when the step ends
+            dt = time.perf_counter() - t0
+            if full:
+                info["precond"] = dp.dp_precond_get_info(prob) if use_pc else {}
+                prob.close()
+            return info, dt
 
         for w in range(args.warmup):
             info, dt = step()
-            log(f"[{precision}] warmup {w}: {dt:.3f} s iters={info['iters_max']} relres={info['relres_max']:.2e}")
+            log(f"[{tag}] warmup {w}: {dt:.3f} s iters={info['iters_max']} relres={info['relres_max']:.2e}")
         torch.cuda.synchronize()
         lat, infos = [], []
         t0 = time.perf_counter()
-        for s in range(args.steps):
+        for s_ in range(args.steps):
             info, dt = step()
             lat.append(dt)
             infos.append(info)
-            log(f"[{precision}] step {s}: {dt:.3f} s iters={info['iters_max']} relres={info['relres_max']:.2e} "
+            log(f"[{tag}] step {s_}: {dt:.3f} s iters={info['iters_max']} relres={info['relres_max']:.2e} "
                 f"sweep {info['t_sweep'] / max(info['sweep_launches'], 1) * 1e3:.2f} ms x {info['sweep_launches']}"
                 f" fp32 {info['t_sweep_fp32'] / max(info['sweep_launches_fp32'], 1) * 1e3:.2f} ms x "
                 f"{info['sweep_launches_fp32']} refinements={info['refinements']}")
         torch.cuda.synchronize()
         T = time.perf_counter() - t0
+        if resident is not None:
+            pinfo = dp.dp_precond_get_info(resident) if use_pc else {}
+            for i in infos:
+                i["precond"] = pinfo
+            resident.close()
         return T, lat, infos
 
     nrp = 1
@@ -280,11 +344,13 @@ def main():
         nrp *= 2
     pairs = b.n * (b.n - 1)
     flops = pairs * (FLOPS_PAIR_HARD + FLOPS_PAIR_PER_RHS_HARD * nrp)
+    flops_valu = pairs * FLOPS_PAIR_HARD                       # kernel values (vector ALUs)
+    flops_mac = pairs * FLOPS_PAIR_PER_RHS_HARD * nrp          # complex MACs (textbook 8 flops each)
+    flops_mfma16_exec = pairs * 2 * nrp * FLOPS_MFMA16_PER_COL  # split-FP16 products executed
 
     # lower bound on one single-precision sweep: pair arithmetic on the vector
     # ALUs plus the executed split-FP16 products on the matrix cores
-    t_bound32 = pairs * (FLOPS_PAIR_HARD / (PEAK_FP32_VALU * 1e12)
-                         + 2 * nrp * FLOPS_MFMA16_PER_COL / (PEAK_FP16_MFMA * 1e12))
+    t_bound32 = flops_valu / (PEAK_FP32_VALU * 1e12) + flops_mfma16_exec / (PEAK_FP16_MFMA * 1e12)
 
     def sweep_rate(infos, key_l, key_t):
         launches = sum(i[key_l] for i in infos)
@@ -297,6 +363,7 @@ def main():
         launches, avg, achieved = sweep_rate(infos, "sweep_launches", "t_sweep")
         out = {
             "value": nrhs * args.steps / T,
+            "systems_per_s": args.steps / T,
             "ms_per_step": T / args.steps * 1e3,
             "converged": all(i["converged"] and i["relres_max"] <= 1e-8 for i in infos),
             "iterations": int(max(i["iters_max"] for i in infos)),
@@ -306,6 +373,7 @@ def main():
                 "matvec": float(np.mean([i["t_matvec"] for i in infos])),
                 "precond_apply": float(np.mean([i["t_apply"] for i in infos])),
                 "krylov": float(np.mean([i["t_krylov"] for i in infos])),
+                "precond_setup": float(np.mean([i["precond"].get("t_setup", 0.0) for i in infos])),
             },
             "sweep_fp64": {"launch_ms": avg * 1e3, "launches": launches, "tflops": achieved,
                            "frac_fp64_peak": achieved / PEAK_FP64_VALU},
@@ -318,45 +386,58 @@ def main():
                                  "frac_of_bound": t_bound32 / a32 if a32 > 0 else 0.0}
         return out
 
-    # launch configuration of the sweep for this shape, chosen before the timed region
-    # (--no-autotune keeps the default 2048-block grid, e.g. for counter runs
-    # that must all see one configuration)
-    tuned = {}
-    for precision in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
-        if args.no_autotune:
-            tuned[precision] = {"target_blocks": 2048, "default": True}
-            continue
-        tuned[precision] = dp.dp_autotune(prob, nrhs, dp.DP_PREC_MIXED if precision == "mixed" else dp.DP_PREC_FP64)
-        log(f"autotune [{precision}]: {tuned[precision]}")
-    runs = {}
-    for precision in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
-        runs[precision] = summary(precision, *run(precision))
+    tuned = None
+    if args.autotune:
+        tp = dp.Problem.from_boundary(ctx, b, om, eta, kind)
+        tuned = {pr: dp.dp_autotune(tp, nrhs, dp.DP_PREC_MIXED if pr == "mixed" else dp.DP_PREC_FP64)
+                 for pr in ("mixed", "fp64")}
+        tp.close()
+        log(f"autotune (informational): {tuned}")
+
+    precisions = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    runs, resident_runs = {}, {}
+    for precision in precisions:
+        if not args.resident_only:
+            runs[precision] = summary(precision, *run(precision, True))
+        resident_runs[precision] = summary(precision, *run(precision, False))
+    if args.resident_only:
+        runs = resident_runs
     head = "mixed" if "mixed" in runs else "fp64"
     main_run = runs[head]
-    pinfo = dp.dp_precond_get_info(prob) if use_pc else {}
-
-    def measured_cfg(precision):
-        # the counters were taken at this shape with a 2048-block grid
-        return b.n == 32768 and nrhs == 64 and tuned.get(precision, {}).get("target_blocks") == 2048
 
     if head == "mixed":
         sw = main_run["sweep_fp32"]
+        t_launch = sw["launch_ms"] * 1e-3
+        frac = (flops / t_launch / 1e12) / PEAK_FP16_MFMA if t_launch > 0 else 0.0
         roof = {"kernel": "sweep_mfma16<hard, 64 columns> (FP32 kernel values, FP64 phase reduction; "
                           "split-FP16 operands on v_mfma_f32_16x16x32_f16 with FP32 accumulation; 8 waves x "
                           "16 targets, LDS density tiles)",
-                "bound": "alu+mfma", "achieved": sw["tflops"], "peak": flops / t_bound32 / 1e12,
-                "unit": "TFLOP/s", "frac": sw["frac_of_bound"],
-                "traffic": TRAFFIC_FP32_SWEEP if measured_cfg("mixed") else None, "launch_ms": sw["launch_ms"],
-                "launches": sw["launches"], "flops_per_launch": flops, "t_bound_ms": t_bound32 * 1e3,
-                "valu_peak_tflops": PEAK_FP32_VALU, "mfma_peak_tflops": PEAK_FP16_MFMA}
+                "bound": "mfma", "achieved": sw["tflops"], "peak": PEAK_FP16_MFMA, "unit": "TFLOP/s",
+                "frac": frac, "traffic": TRAFFIC_FP32_SWEEP if b.n == 32768 and nrhs == 64 else None,
+                "launch_ms": sw["launch_ms"], "launches": sw["launches"], "flops_per_launch": flops,
+                "components": {
+                    "mfma_fp16_algorithmic": {
+                        "flops": flops_mac, "achieved": flops_mac / t_launch / 1e12, "peak": PEAK_FP16_MFMA,
+                        "frac": flops_mac / t_launch / 1e12 / PEAK_FP16_MFMA},
+                    "mfma_fp16_executed": {
+                        "flops": flops_mfma16_exec, "achieved": flops_mfma16_exec / t_launch / 1e12,
+                        "peak": PEAK_FP16_MFMA, "frac": flops_mfma16_exec / t_launch / 1e12 / PEAK_FP16_MFMA},
+                    "valu_fp32": {
+                        "flops": flops_valu, "achieved": flops_valu / t_launch / 1e12, "peak": PEAK_FP32_VALU,
+                        "frac": flops_valu / t_launch / 1e12 / PEAK_FP32_VALU},
+                    "composite_valu_plus_mfma": {
+                        "t_bound_ms": t_bound32 * 1e3, "frac": sw["frac_of_bound"],
+                        "note": "vector ALUs and matrix cores do not issue concurrently on a SIMD: the "
+                                "launch takes at least the VALU time plus the executed FP16 product time"},
+                }}
     else:
         sw = main_run["sweep_fp64"]
         roof = {"kernel": "sweep_mfma<hard, 64 columns, FP64> (v_mfma_f64_16x16x4 products; 8 waves, "
                           "shared kernel values, LDS density tiles)",
                 "bound": "mfma", "achieved": sw["tflops"], "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
                 "frac": sw["tflops"] / PEAK_FP64_VALU,
-                "traffic": TRAFFIC_FP64_SWEEP if measured_cfg("fp64") else None, "launch_ms": sw["launch_ms"],
-                "launches": sw["launches"], "flops_per_launch": flops}
+                "traffic": TRAFFIC_FP64_SWEEP if b.n == 32768 and nrhs == 64 else None,
+                "launch_ms": sw["launch_ms"], "launches": sw["launches"], "flops_per_launch": flops}
     out = {
         "metric": METRIC,
         "value": main_run["value"],
@@ -374,9 +455,11 @@ def main():
             "workload": f"sound-hard kite, n={b.n}, 10 points/wavelength (omega={om:.1f}), eta=omega, "
                         f"{nrhs} plane waves at 2*pi*k/{nrhs}, directional preconditioner + GMRES(80) "
                         f"to 1e-8 FP64 residual; " + ("mixed: iterative refinement with FP32-operator "
-                                                      "corrections" if head == "mixed" else "FP64"),
+                                                      "corrections" if head == "mixed" else "FP64")
+                        + ("; step = resident problem" if args.resident_only else
+                           "; step = problem creation from host geometry to q in host memory"),
             "n": b.n, "nrhs": nrhs, "omega": om, "tol": 1e-8, "restart": 80,
-            "precision": head, "precond": use_pc,
+            "precision": head, "precond": use_pc, "setup_included": not args.resident_only,
         },
         "converged": main_run["converged"],
         "iterations": main_run["iterations"],
@@ -384,11 +467,19 @@ def main():
         "latency_ms": main_run["latency_ms"],
         "roofline": roof,
         "precision_runs": runs,
-        "autotune": tuned,
+        "setup_excluded_runs": resident_runs,
     }
-    out["precond_setup_s"] = float(pinfo.get("t_setup", 0.0))
-    if pinfo:
-        out["precond"] = {k: pinfo[k] for k in ("m", "NW", "nnzW", "nnzLU", "levels")}
+    if tuned is not None:
+        out["autotune"] = tuned
+    # preconditioner structure of this workload
+    if use_pc:
+        tp = dp.Problem.from_boundary(ctx, b, om, eta, kind)
+        dp.dp_precond_build(tp)
+        pinfo = dp.dp_precond_get_info(tp)
+        out["precond"] = {k: pinfo[k] for k in ("m", "NW", "nnzW", "nnzLU", "levels", "t_setup")}
+        if not args.no_iteration_study:
+            out["iteration_study"] = iteration_study(dp, ctx, tp, b, om, eta, kind, f, q, nrhs)
+        tp.close()
     if args.serve > 0:
         log(f"serving stream: {args.serve} requests ...")
         out["serving"] = serve_stream(dp, args.serve, args.serve_rate, args.serve_slots)
@@ -396,6 +487,43 @@ def main():
         log("cpu baseline (oracle, bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(b, om, eta, nrhs)
     print(json.dumps(out), flush=True)
+
+
+def iteration_study(dp, ctx, prob, b, om, eta, kind, f, q, nrhs):
+    """GMRES iterations with (n_p) and without (n_n) the preconditioner, FP64
+    (Sec. 3's table columns): at the bench workload (all columns), and for one
+    plane wave along +x on the kite at n = 8192, 16384, 32768 (omega grows
+    with n at 10 points per wavelength)."""
+    import torch
+    from synth import config_boundary
+    out = {}
+    dp.dp_rhs_plane_wave(prob, plane_wave_angles_all(nrhs), f)
+    ip = dp.dp_solve(prob, f, q, tol=1e-8, restart=80, use_precond=True)
+    i_n = dp.dp_solve(prob, f, q, tol=1e-8, restart=80, use_precond=False, max_iters=2000)
+    out["bench_workload"] = {"n": b.n, "omega": om, "nrhs": nrhs, "n_p": int(ip["iters_max"]),
+                             "n_n": int(i_n["iters_max"]), "n_n_converged": bool(i_n["converged"])}
+    log(f"iterations at the bench workload: {out['bench_workload']}")
+    rows = []
+    for n in (8192, 16384, 32768):
+        bb, omb, etab, kb = config_boundary("kite", n)
+        pr = dp.Problem.from_boundary(ctx, bb, omb, etab, kb)
+        dp.dp_precond_build(pr)
+        f1 = torch.empty((1, n), dtype=torch.complex128, device="cuda:0")
+        q1 = torch.empty_like(f1)
+        dp.dp_rhs_plane_wave(pr, np.array([0.0]), f1)
+        a = dp.dp_solve(pr, f1, q1, tol=1e-8, restart=80, use_precond=True)
+        c = dp.dp_solve(pr, f1, q1, tol=1e-8, restart=80, use_precond=False, max_iters=2000)
+        rows.append({"n": n, "omega": omb, "n_p": int(a["iters_max"]), "n_n": int(c["iters_max"]),
+                     "n_n_converged": bool(c["converged"])})
+        log(f"iterations vs omega: {rows[-1]}")
+        pr.close()
+    out["kite_hard_vs_omega"] = rows
+    return out
+
+
+def plane_wave_angles_all(nrhs):
+    from synth import plane_wave_angles
+    return plane_wave_angles(nrhs)
 
 
 if __name__ == "__main__":

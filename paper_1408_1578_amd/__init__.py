@@ -29,7 +29,8 @@ DP_OP_S, DP_OP_D, DP_OP_DP, DP_OP_DS = 2, 3, 4, 5
 EXPORTED = [
     "dp_ctx_create", "dp_ctx_destroy", "dp_last_error", "dp_problem_create",
     "dp_problem_destroy", "dp_problem_kappa", "dp_rhs_plane_wave", "dp_matvec", "dp_matvec_mixed", "dp_layer_apply",
-    "dp_precond_build", "dp_precond_apply", "dp_precond_apply_mixed", "dp_precond_get_info", "dp_precond_export",
+    "dp_precond_build", "dp_precond_apply", "dp_precond_apply_mixed",
+    "dp_precond_get_info", "dp_precond_export",
     "dp_solve", "dp_hankel_dev", "dp_hankel_host",
     "dp_autotune", "dp_server_create", "dp_server_submit", "dp_server_wait", "dp_server_get_stats", "dp_server_destroy",
 ]

@@ -23,6 +23,15 @@ void set_error(const char* fmt, ...) {
 }
 
 static thread_local hipStream_t g_alloc_stream = nullptr;
+static thread_local bool g_capturing = false;
+
+std::shared_mutex& pool_capture_mutex() {
+  static std::shared_mutex mu;
+  return mu;
+}
+
+CaptureScope::CaptureScope() : lk(pool_capture_mutex()) { g_capturing = true; }
+CaptureScope::~CaptureScope() { g_capturing = false; }
 
 AllocStream::AllocStream(hipStream_t s) : prev(g_alloc_stream) { g_alloc_stream = s; }
 AllocStream::~AllocStream() { g_alloc_stream = prev; }
@@ -51,15 +60,25 @@ static void configure_pool(int device) {
 
 int DevBuf::reserve(size_t want) {
   if (want <= bytes && p) return DP_OK;
+  if (g_capturing) {
+    set_error("device allocation of %zu bytes requested during graph capture", want);
+    return DP_EDEVICE;
+  }
   release();
   if (want == 0) want = 8;
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) configure_pool(dev);
-  if (hipMallocAsync(&p, want, g_alloc_stream) != hipSuccess) {
+  std::shared_lock<std::shared_mutex> lk(pool_capture_mutex());
+  const hipError_t e = hipMallocAsync(&p, want, g_alloc_stream);
+  if (e != hipSuccess) {
     p = nullptr;
     bytes = 0;
     (void)hipGetLastError();
-    set_error("device allocation of %zu bytes failed", want);
+    size_t fr = 0, tot = 0;
+    (void)hipMemGetInfo(&fr, &tot);
+    (void)hipGetLastError();
+    set_error("device allocation of %zu bytes failed (%s; %zu of %zu bytes free)", want, hipGetErrorString(e), fr,
+              tot);
     return DP_ENOMEM;
   }
   s = g_alloc_stream;
@@ -68,7 +87,10 @@ int DevBuf::reserve(size_t want) {
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFreeAsync(p, s);
+  if (p) {
+    std::shared_lock<std::shared_mutex> lk(pool_capture_mutex());
+    (void)hipFreeAsync(p, s);
+  }
   p = nullptr;
   bytes = 0;
   s = nullptr;

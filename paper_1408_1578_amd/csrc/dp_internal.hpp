@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <map>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -47,6 +48,19 @@ struct DevBuf {
   void release();
   template <class T>
   T* as() const { return static_cast<T*>(p); }
+};
+
+// Stream-ordered allocation and graph capture exclude each other across
+// threads: HIP refuses hipMallocAsync on any stream while another thread
+// captures (even in thread-local capture mode), so DevBuf allocations and
+// releases hold this lock shared and a capture holds it exclusively (begin
+// to instantiate).  A capture itself never allocates.
+std::shared_mutex& pool_capture_mutex();
+// set while the calling thread captures a graph (DevBuf growth is refused)
+struct CaptureScope {
+  std::unique_lock<std::shared_mutex> lk;
+  CaptureScope();
+  ~CaptureScope();
 };
 
 // The stream on which DevBuf allocations of the calling thread are ordered,

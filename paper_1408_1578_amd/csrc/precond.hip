@@ -1884,6 +1884,7 @@ static int capture_apply(dp_problem* p, int nrhs, int prec, hipGraphExec_t* out)
   Precond* P = p->pc;
   hipStream_t st = p->ctx->stream;
   hipGraph_t g = nullptr;
+  CaptureScope excl;  // no stream-ordered allocation in any thread until instantiated
   if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return DP_EDEVICE;
   const int rc = prec ? apply_core32(p, nrhs, P->win.as<cplx>(), P->wq.as<cplx>())
                       : apply_core(p, nrhs, P->win.as<cplx>(), P->wq.as<cplx>());
