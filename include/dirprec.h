@@ -170,6 +170,20 @@ int dp_precond_apply(dp_problem* p, int64_t nrhs, const double* v, double* z);
  * DP_PREC_MIXED.  Relative difference from dp_precond_apply ~1e-6. */
 int dp_precond_apply_mixed(dp_problem* p, int64_t nrhs, const double* v, double* z);
 
+/* dp_precond_apply for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * FP64 apply and the same kernels, with every workspace taken from a device
+ * array of 128 MiB that the library holds on each GPU it runs on (set up by
+ * dp_ctx_create, resident until the process ends); no allocation, no graph.
+ * The workspaces need 16 bytes x nrhs x (2 n + 4 NW), and 2 NW more when
+ * floor(W) was factored densely (each rounded up to 256 bytes); beyond
+ * 128 MiB the call returns DP_EINVAL and names the size.  v, z: device
+ * n x nrhs complex, must not overlap.  All calls on one GPU share that array:
+ * calls that overlap in time on one GPU (several threads, contexts or
+ * problems) race and must be serialised by the caller.  DP_ESTATE before
+ * dp_precond_build. */
+int dp_precond_apply_noalloc(dp_problem* p, int64_t nrhs, const double* v, double* z);
+
 int dp_precond_get_info(dp_problem* p, dp_precond_info* info);
 
 /* Structure export for tests (host arrays, caller-allocated):

@@ -29,7 +29,7 @@ DP_OP_S, DP_OP_D, DP_OP_DP, DP_OP_DS = 2, 3, 4, 5
 EXPORTED = [
     "dp_ctx_create", "dp_ctx_destroy", "dp_last_error", "dp_problem_create",
     "dp_problem_destroy", "dp_problem_kappa", "dp_rhs_plane_wave", "dp_matvec", "dp_matvec_mixed", "dp_layer_apply",
-    "dp_precond_build", "dp_precond_apply", "dp_precond_apply_mixed",
+    "dp_precond_build", "dp_precond_apply", "dp_precond_apply_mixed", "dp_precond_apply_noalloc",
     "dp_precond_get_info", "dp_precond_export",
     "dp_solve", "dp_hankel_dev", "dp_hankel_host",
     "dp_autotune", "dp_server_create", "dp_server_submit", "dp_server_wait", "dp_server_get_stats", "dp_server_destroy",
@@ -135,6 +135,7 @@ def lib():
         "dp_precond_build": (ci, [vp, ctypes.POINTER(PrecondOpts)]),
         "dp_precond_apply": (ci, [vp, i64, vp, vp]),
         "dp_precond_apply_mixed": (ci, [vp, i64, vp, vp]),
+        "dp_precond_apply_noalloc": (ci, [vp, i64, vp, vp]),
         "dp_precond_get_info": (ci, [vp, ctypes.POINTER(PrecondInfo)]),
         "dp_precond_export": (ci, [vp, vp, vp, vp, vp]),
         "dp_solve": (ci, [vp, i64, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp, vp]),
@@ -312,6 +313,13 @@ def dp_precond_apply_mixed(p, v, z):
     if _cols(z, p.n) != nr:
         raise ValueError("shape mismatch")
     _check("dp_precond_apply_mixed", lib().dp_precond_apply_mixed(p.h, nr, _ptr(v, p.ctx), _ptr(z, p.ctx)))
+
+
+def dp_precond_apply_noalloc(p, v, z):
+    nr = _cols(v, p.n)
+    if _cols(z, p.n) != nr:
+        raise ValueError("shape mismatch")
+    _check("dp_precond_apply_noalloc", lib().dp_precond_apply_noalloc(p.h, nr, _ptr(v, p.ctx), _ptr(z, p.ctx)))
 
 
 def dp_precond_get_info(p):

@@ -215,6 +215,13 @@ int dp_ctx_create(int device, void* stream, dp_ctx** out) {
     }
     c->own_stream = true;
   }
+  // the scratch array of dp_precond_apply_noalloc on this device
+  const int src = scratch_init(device);
+  if (src != DP_OK) {
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return src;
+  }
   *out = c;
   return DP_OK;
 }
@@ -426,6 +433,19 @@ int dp_precond_apply_mixed(dp_problem* p, int64_t nrhs, const double* v, double*
   DP_SETDEV(p->ctx);
   DP_TRY(check_io(p, nrhs, v, z, "dp_precond_apply_mixed"));
   DP_TRY(precond_apply(p, (int)nrhs, reinterpret_cast<const cplx*>(v), reinterpret_cast<cplx*>(z), 1));
+  DP_HIP(hipStreamSynchronize(p->ctx->stream));
+  return DP_OK;
+}
+
+int dp_precond_apply_noalloc(dp_problem* p, int64_t nrhs, const double* v, double* z) {
+  DP_CHECK(p && v && z && nrhs >= 1 && nrhs <= (1 << 20), "dp_precond_apply_noalloc: bad argument");
+  if (!p->pc) {
+    set_error("dp_precond_apply_noalloc: call dp_precond_build first");
+    return DP_ESTATE;
+  }
+  DP_HIP(hipSetDevice(p->ctx->device));
+  DP_TRY(check_io(p, nrhs, v, z, "dp_precond_apply_noalloc"));
+  DP_TRY(precond_apply_noalloc(p, (int)nrhs, reinterpret_cast<const cplx*>(v), reinterpret_cast<cplx*>(z)));
   DP_HIP(hipStreamSynchronize(p->ctx->stream));
   return DP_OK;
 }

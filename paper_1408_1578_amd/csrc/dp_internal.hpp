@@ -215,4 +215,10 @@ int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* z, int prec = 0)
 void precond_destroy(Precond* pc);
 int precond_info(dp_problem* p, dp_precond_info* info);
 int precond_export(dp_problem* p, int64_t* seg_off, int64_t* seg_len, int64_t* e_idx, double* e_val);
+// The device scratch array of the apply that allocates nothing: look up its
+// address on `device` (that device current; once per device), its size, and
+// the FP64 apply on it (DP_EINVAL beyond the size)
+int scratch_init(int device);
+size_t scratch_bytes();
+int precond_apply_noalloc(dp_problem* p, int nrhs, const cplx* v, cplx* q);
 }  // namespace dp

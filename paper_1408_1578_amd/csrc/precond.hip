@@ -1965,6 +1965,75 @@ int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q, int prec) {
   return DP_OK;
 }
 
+// ------------------------------------------------------------------ apply without allocation
+// Device scratch of dp_precond_apply_noalloc: one array on every GPU the
+// library runs on, resident until the process ends.  In host code `scratch`
+// names a host-side stand-in, never the device memory: kernels receive the
+// address that hipGetSymbolAddress returned for the device (scratch_base).
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_base;  // per device ordinal, nullptr until looked up
+
+int scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_base.size() <= device) g_scratch_base.resize(device + 1, nullptr);
+  if (g_scratch_base[device]) return DP_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    set_error("scratch address on device %d: %s", device, hipGetErrorString(e));
+    return DP_EDEVICE;
+  }
+  g_scratch_base[device] = ptr;
+  return DP_OK;
+}
+
+static void* scratch_base(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device < (int)g_scratch_base.size() ? g_scratch_base[device] : nullptr;
+}
+
+size_t scratch_bytes() { return kScratchBytes; }
+
+// The FP64 apply of precond_apply with every workspace carved from the
+// device's scratch array: kernel launches only, no allocation, no graph.
+// Each workspace is written before it is read, so nothing is cleared.
+int precond_apply_noalloc(dp_problem* p, int nrhs, const cplx* v, cplx* q) {
+  Precond* P = p->pc;
+  char* base = static_cast<char*>(scratch_base(p->ctx->device));
+  if (!base) {
+    set_error("dp_precond_apply_noalloc: no scratch address for device %d", p->ctx->device);
+    return DP_EDEVICE;
+  }
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t bn = al((size_t)p->n * nrhs * sizeof(cplx)), bw = al((size_t)P->NW * nrhs * sizeof(cplx));
+  const size_t need = 2 * bn + (P->dense_w ? 6 : 4) * bw;
+  if (need > kScratchBytes) {
+    set_error("dp_precond_apply_noalloc: %d columns at n = %lld, NW = %d need %zu bytes of scratch; the maximum "
+              "is %zu",
+              nrhs, (long long)p->n, P->NW, need, kScratchBytes);
+    return DP_EINVAL;
+  }
+  ApplyWs w{};
+  char* c = base;
+  for (cplx** slot : {&w.y, &w.un}) {
+    *slot = reinterpret_cast<cplx*>(c);
+    c += bn;
+  }
+  for (cplx** slot : {&w.g, &w.z, &w.u, &w.t}) {
+    *slot = reinterpret_cast<cplx*>(c);
+    c += bw;
+  }
+  if (P->dense_w) {
+    w.dt = reinterpret_cast<cplx*>(c);
+    w.dy = reinterpret_cast<cplx*>(c + bw);
+  }
+  return apply_core_ws(p, nrhs, v, q, w);
+}
+
 void precond_destroy(Precond* P) {
   if (!P) return;
   for (auto& c : P->classes) {
