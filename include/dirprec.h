@@ -79,15 +79,17 @@ const char* dp_last_error(void);
  *   nrm   n x 2 row-major outward unit normals;
  *   w     n quadrature weights w_j = (2*pi/n)|x'(t_j)| (trapezoid weights);
  *   kappa n signed curvatures (positive where convex); needed by the
- *         diagonal of D and D'.  May be NULL when n is a power of two: the
- *         library then computes kappa = (x' y'' - y' x'') / |x'|^3 from the
- *         FFT t-derivatives of the node positions (the same trigonometric
+ *         diagonal of D and D'.  May be NULL: the library then computes
+ *         kappa = (x' y'' - y' x'') / |x'|^3 from the t-derivatives of the
+ *         trigonometric interpolant of the node positions (the same
  *         interpolation as D_s), exact for band-limited curves up to
  *         rounding that grows like n^2 * 1e-16 relative to max|x''|.
  * omega > 0 frequency, eta > 0 coupling (typically omega), kind DP_SOFT or
- * DP_HARD.  Errors (DP_EINVAL): n odd or n < 16, DP_HARD or kappa == NULL
- * with n not a power of two (the spectral derivative uses a radix-2 FFT),
- * a non-finite entry,
+ * DP_HARD.  The spectral derivative (DP_HARD, kappa == NULL) uses radix-2/4
+ * FFTs of length n when n is a power of two, else Bluestein's chirp-z DFT
+ * with FFTs of the next power of two >= 2n - 1.  Errors (DP_EINVAL): n odd
+ * or n < 16, n > 2^26, or (DP_HARD or kappa == NULL) with n > 2^24 (a power
+ * of two) or n > 2^23 (other n), a non-finite entry,
  * |nrm_j| differing from 1 by more than 1e-10, w_j <= 0, omega <= 0,
  * eta <= 0.  The problem keeps device copies of the geometry and the Kress
  * correction table C_k (k = 0..n-1). */
@@ -117,7 +119,10 @@ int dp_matvec(dp_problem* p, int64_t nrhs, const double* q, double* y);
 int dp_matvec_mixed(dp_problem* p, int64_t nrhs, const double* q, double* y);
 
 /* y = OP q for one operator (DP_OP_S, DP_OP_D, DP_OP_DP, DP_OP_DS); device
- * n x nrhs complex arrays.  Exposed for parity tests of the single layers. */
+ * n x nrhs complex arrays.  Exposed for parity tests of the single layers.
+ * DP_OP_DS of a sound-soft problem created with given curvatures needs a
+ * power-of-two n (the Bluestein tables are built only when a problem needs
+ * the derivative); DP_EINVAL otherwise. */
 int dp_layer_apply(dp_problem* p, int op, int64_t nrhs, const double* q, double* y);
 
 /* ------------------------------------------------------------------ preconditioner */

@@ -238,12 +238,15 @@ void dp_ctx_destroy(dp_ctx* c) {
 int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nrm, const double* w,
                       const double* kappa, double omega, double eta, int kind, dp_problem** out) {
   DP_CHECK(ctx && out && xy && nrm && w, "dp_problem_create: NULL argument");
-  DP_CHECK(kappa || is_pow2(n), "dp_problem_create: kappa == NULL needs a power-of-two n (got %lld)",
-           (long long)n);
   DP_CHECK(n >= 16 && n % 2 == 0 && n <= (1LL << 26), "dp_problem_create: n = %lld must be even, >= 16",
            (long long)n);
   DP_CHECK(kind == DP_SOFT || kind == DP_HARD, "dp_problem_create: kind %d", kind);
-  DP_CHECK(kind == DP_SOFT || is_pow2(n), "dp_problem_create: sound-hard needs a power-of-two n (got %lld)",
+  // the spectral derivative (sound-hard, or curvature from the nodes) runs
+  // FFTs of length n (a power of two) or >= 2n - 1 (Bluestein), at most 2^24
+  const bool fft = kind == DP_HARD || !kappa;
+  DP_CHECK(!fft || n <= (is_pow2(n) ? (1LL << 24) : (1LL << 23)),
+           "dp_problem_create: n = %lld too large for the spectral derivative (sound-hard or kappa == NULL: "
+           "at most 2^24, 2^23 unless a power of two)",
            (long long)n);
   DP_CHECK(std::isfinite(omega) && omega > 0, "dp_problem_create: omega must be > 0");
   DP_CHECK(std::isfinite(eta) && eta > 0, "dp_problem_create: eta must be > 0");
@@ -295,6 +298,7 @@ int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nr
     rc = DP_EDEVICE;
   }
   if (rc == DP_OK) rc = build_tables(p);
+  if (rc == DP_OK && fft && !is_pow2(n)) rc = bluestein_init(p);
   if (rc == DP_OK && !kappa) rc = curvature_spectral(p, p->hkap.data());
   if (rc == DP_OK) rc = build_diag(p);
   if (rc == DP_OK) rc = near_build(p);
@@ -318,6 +322,10 @@ void dp_problem_destroy(dp_problem* p) {
   p->src.release();
   p->C.release();
   p->twiddle.release();
+  p->blu_tw.release();
+  p->blu_chirp.release();
+  p->blu_B.release();
+  p->blu_ws.release();
   p->dens.release();
   p->partial.release();
   p->dens16.release();
@@ -379,7 +387,8 @@ int dp_matvec_mixed(dp_problem* p, int64_t nrhs, const double* q, double* y) {
 int dp_layer_apply(dp_problem* p, int op, int64_t nrhs, const double* q, double* y) {
   DP_CHECK(p && q && y && nrhs >= 1, "dp_layer_apply: bad argument");
   DP_CHECK(op == DP_OP_S || op == DP_OP_D || op == DP_OP_DP || op == DP_OP_DS, "dp_layer_apply: op %d", op);
-  DP_CHECK(op != DP_OP_DS || is_pow2(p->n), "dp_layer_apply: D_s needs a power-of-two n");
+  DP_CHECK(op != DP_OP_DS || is_pow2(p->n) || p->blu_M > 0,
+           "dp_layer_apply: D_s of a sound-soft problem with given curvatures needs a power-of-two n");
   DP_SETDEV(p->ctx);
   DP_TRY(check_io(p, nrhs, q, y, "dp_layer_apply"));
   if (op == DP_OP_DS) {

@@ -141,7 +141,12 @@ struct dp_problem {
   dp::DevBuf C;         // double[n]
   dp::DevBuf C32;       // float[n], C_k / (pi dt) (single-precision sweep)
   dp::DevBuf diag;      // double4[n]: S_ii (re, im), D_ii
-  dp::DevBuf twiddle;   // cplx[n]   (e^{-2 pi i l/n})
+  dp::DevBuf twiddle;   // cplx[n]   (e^{-2 pi i l/n}), power-of-two n
+  // Bluestein (chirp-z) DFT of length n for n not a power of two, through
+  // power-of-two FFTs of length blu_M >= 2n - 1: chirp c_j = e^{i pi j^2/n},
+  // FFT_M of the circular chirp sequence b, M twiddles, workspace M x columns
+  int blu_M = 0;
+  dp::DevBuf blu_tw, blu_chirp, blu_B, blu_ws;
   dp::DevBuf dens;      // sweep operands
   dp::DevBuf partial;   // sweep partial sums
   dp::DevBuf dens16;    // split-FP16 density tiles
@@ -195,8 +200,10 @@ int near_apply_group(dp_problem* p, int op, int nrp, const void* dens, bool dens
 int matvec(dp_problem* p, int nrhs, const cplx* q, cplx* y, int prec = 0);
 // fft.hip
 int spectral_derivative(dp_problem* p, int nrhs, const cplx* in, cplx* out);
-// Curvature from the spectral t-derivatives of the node positions (power-of-two
-// n, twiddles built): written into the source records and into hkap (host, n).
+// Chirp, twiddles and chirp spectrum of the Bluestein DFT (n not a power of two).
+int bluestein_init(dp_problem* p);
+// Curvature from the spectral t-derivatives of the node positions (FFT
+// tables built): written into the source records and into hkap (host, n).
 int curvature_spectral(dp_problem* p, double* hkap);
 // Per-node diagonal table (after the curvature and C_k are in place).
 int build_diag(dp_problem* p);

@@ -1,7 +1,8 @@
 // Arclength derivative of the trigonometric interpolant (Nyquist mode
 // dropped), used by Maue's form of the hypersingular operator:
 //   (D_s phi)_i = (1/|x'(t_i)|) * IDFT( i m DFT(phi) )_i,  m in (-n/2, n/2).
-// Radix-2 FFT for power-of-two n, batched over columns.  n <= 4096: one
+// Radix-2 FFT for power-of-two lengths, batched over columns; any other even
+// n goes through Bluestein's chirp-z identity (below).  Length <= 4096: one
 // line per column, transformed in LDS.  Larger n: four-step with
 // n = n1 * n2 (n1, n2 <= 4096): length-n1 transforms over the stride-n2
 // index with the twiddle e^{-+2 pi i j2 k1/n}, then length-n2 transforms of
@@ -211,19 +212,19 @@ static int ilog2(int v) {
   return l;
 }
 
-static void fft_passes(dp_problem* p, cplx* d, int nb, int dir) {
-  const int n = (int)p->n;
-  const int logn = ilog2(n);
+// In-place transform of nb contiguous columns of length N (a power of two,
+// at most 2^24) with the twiddle table tw[l] = e^{-2 pi i l/N}: dir = -1
+// forward, +1 inverse (unnormalised).
+static void fft_run(cplx* d, int N, const cplx* tw, int nb, int dir, hipStream_t st) {
+  const int logn = ilog2(N);
   const int log1 = logn <= 12 ? logn : (logn + 1) / 2;
   const int log2n = logn - log1;
   const int n1 = 1 << log1, n2 = 1 << log2n;
-  const cplx* tw = p->twiddle.as<cplx>();
-  hipStream_t st = p->ctx->stream;
   auto col = [&](int dirc) {
     int lines = kFftLds / n1;
     if (lines > n2) lines = n2;
     dim3 g(n2 / lines, nb);
-    fft_col_pass<<<g, 256, (size_t)n1 * lines * sizeof(cplx), st>>>(d, d, n, n1, n2, log1, lines, tw, dirc,
+    fft_col_pass<<<g, 256, (size_t)n1 * lines * sizeof(cplx), st>>>(d, d, N, n1, n2, log1, lines, tw, dirc,
                                                                      n2 > 1, nullptr);
   };
   auto row = [&](int dirc) {
@@ -231,7 +232,7 @@ static void fft_passes(dp_problem* p, cplx* d, int nb, int dir) {
     int lines = kFftLds / n2;
     if (lines > n1) lines = n1;
     dim3 g(n1 / lines, nb);
-    fft_row_pass<<<g, 256, (size_t)n2 * lines * sizeof(cplx), st>>>(d, n, n2, log2n, lines, tw, dirc);
+    fft_row_pass<<<g, 256, (size_t)n2 * lines * sizeof(cplx), st>>>(d, N, n2, log2n, lines, tw, dirc);
   };
   if (dir < 0) {
     col(-1);
@@ -242,9 +243,147 @@ static void fft_passes(dp_problem* p, cplx* d, int nb, int dir) {
   }
 }
 
+static void fft_passes(dp_problem* p, cplx* d, int nb, int dir) {
+  fft_run(d, (int)p->n, p->twiddle.as<cplx>(), nb, dir, p->ctx->stream);
+}
+
 static int grid_for(size_t tot) {
   const size_t g = (tot + 255) / 256;
   return (int)(g > 8192 ? 8192 : g);
+}
+
+// ------------------------------------------------------------------ Bluestein
+// For n not a power of two the length-n DFT X_k = sum_j phi_j e^{-2 pi i jk/n}
+// follows from jk = (j^2 + k^2 - (k - j)^2)/2 as a convolution:
+//   X_k = conj(c_k) sum_j (phi_j conj(c_j)) c_{k-j},   c_j = e^{i pi j^2/n},
+// evaluated by power-of-two FFTs of length M >= 2n - 1 of the zero-padded
+// sequence and of b (c_l at l and M - l, l < n).  The inverse DFT is the
+// same with the chirp conjugated: u_j = c_j sum_k (U_k c_k) conj(c)_{j-k};
+// as b is symmetric (b_l = b_{M-l}), FFT_M(conj b) = conj(FFT_M(b)).  The
+// chirp phase is reduced exactly, pi (j^2 mod 2n)/n, before sincospi.
+
+__global__ void blu_tables(cplx* chirp, cplx* b, cplx* tw, int n, int M) {
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < M; l += gridDim.x * blockDim.x) {
+    double s, c;
+    sincospi(2.0 * l / M, &s, &c);
+    tw[l] = {c, -s};
+    const int j = l < n ? l : (l > M - n ? M - l : -1);
+    cplx v = {0.0, 0.0};
+    if (j >= 0) {
+      const long long r = ((long long)j * j) % (2LL * n);
+      sincospi((double)r / n, &s, &c);
+      v = {c, s};
+      if (l < n) chirp[l] = v;
+    }
+    b[l] = v;
+  }
+}
+
+// a[col][j] = in[col][j] conj(c_j) (j < n), 0 up to M
+__global__ void blu_premul(const cplx* __restrict__ in, cplx* __restrict__ a, const cplx* __restrict__ chirp,
+                           int n, int M, int nb) {
+  const size_t tot = (size_t)M * nb;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx % (size_t)M);
+    const size_t col = idx / (size_t)M;
+    cplx v = {0.0, 0.0};
+    if (j < n) {
+      const cplx x = in[col * n + j], c = chirp[j];
+      v = {x.re * c.re + x.im * c.im, x.im * c.re - x.re * c.im};
+    }
+    a[idx] = v;
+  }
+}
+
+// a *= B (or conj B) / M
+__global__ void blu_mul(cplx* a, const cplx* __restrict__ B, int M, int nb, int conjB) {
+  const size_t tot = (size_t)M * nb;
+  const double s = 1.0 / M;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    cplx w = B[idx % (size_t)M];
+    if (conjB) w.im = -w.im;
+    const cplx v = cmul(a[idx], w);
+    a[idx] = {v.re * s, v.im * s};
+  }
+}
+
+// Between the two convolutions: X_k = conj(c_k) a_k; U_k = i m_k X_k / n
+// (m_k the signed frequency, Nyquist zeroed); a_k = U_k c_k (k < n), 0 up to M.
+__global__ void blu_mid(cplx* a, const cplx* __restrict__ chirp, int n, int M, int nb) {
+  const size_t tot = (size_t)M * nb;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx % (size_t)M);
+    cplx v = {0.0, 0.0};
+    if (k < n) {
+      const cplx c = chirp[k], y = a[idx];
+      const cplx X = {y.re * c.re + y.im * c.im, y.im * c.re - y.re * c.im};
+      const int m = (k < n / 2) ? k : ((k == n / 2) ? 0 : k - n);
+      const double f = (double)m / n;
+      const cplx U = {-f * X.im, f * X.re};
+      v = cmul(U, c);
+    }
+    a[idx] = v;
+  }
+}
+
+// out[col][j] = c_j a[col][j] (divided by the speed of node j with `src`)
+__global__ void blu_post(const cplx* __restrict__ a, cplx* __restrict__ out, const cplx* __restrict__ chirp,
+                         const SrcRec* __restrict__ src, int n, int M, int nb) {
+  const size_t tot = (size_t)n * nb;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx % (size_t)n);
+    const size_t col = idx / (size_t)n;
+    cplx v = cmul(chirp[j], a[col * M + j]);
+    if (src) {
+      const double r = 1.0 / src[j].sp;
+      v = {v.re * r, v.im * r};
+    }
+    out[idx] = v;
+  }
+}
+
+int bluestein_init(dp_problem* p) {
+  const int n = (int)p->n;
+  int M = 1;
+  while (M < 2 * n - 1) M <<= 1;
+  p->blu_M = M;
+  hipStream_t st = p->ctx->stream;
+  DP_TRY(p->blu_tw.reserve((size_t)M * sizeof(cplx)));
+  DP_TRY(p->blu_chirp.reserve((size_t)n * sizeof(cplx)));
+  DP_TRY(p->blu_B.reserve((size_t)M * sizeof(cplx)));
+  blu_tables<<<(M + 255) / 256, 256, 0, st>>>(p->blu_chirp.as<cplx>(), p->blu_B.as<cplx>(), p->blu_tw.as<cplx>(), n,
+                                             M);
+  fft_run(p->blu_B.as<cplx>(), M, p->blu_tw.as<cplx>(), 1, -1, st);
+  DP_HIP(hipGetLastError());
+  return DP_OK;
+}
+
+// out = d/dt in (trigonometric interpolant), or d/ds with `divide` (speed),
+// for nb columns by Bluestein; in may equal out.
+static int bluestein_derivative(dp_problem* p, const cplx* in, cplx* out, int nb, bool divide) {
+  const int n = (int)p->n, M = p->blu_M;
+  hipStream_t st = p->ctx->stream;
+  DP_TRY(p->blu_ws.reserve((size_t)M * nb * sizeof(cplx)));
+  cplx* a = p->blu_ws.as<cplx>();
+  const cplx* c = p->blu_chirp.as<cplx>();
+  const cplx* B = p->blu_B.as<cplx>();
+  const cplx* tw = p->blu_tw.as<cplx>();
+  const int gM = grid_for((size_t)M * nb);
+  blu_premul<<<gM, 256, 0, st>>>(in, a, c, n, M, nb);
+  fft_run(a, M, tw, nb, -1, st);
+  blu_mul<<<gM, 256, 0, st>>>(a, B, M, nb, 0);
+  fft_run(a, M, tw, nb, +1, st);
+  blu_mid<<<gM, 256, 0, st>>>(a, c, n, M, nb);
+  fft_run(a, M, tw, nb, -1, st);
+  blu_mul<<<gM, 256, 0, st>>>(a, B, M, nb, 1);
+  fft_run(a, M, tw, nb, +1, st);
+  blu_post<<<grid_for((size_t)n * nb), 256, 0, st>>>(a, out, c, divide ? p->src.as<SrcRec>() : nullptr, n, M, nb);
+  DP_HIP(hipGetLastError());
+  return DP_OK;
 }
 
 // In place: d <- d/dt of each of nb columns (trigonometric interpolant).
@@ -258,6 +397,7 @@ static void t_derivative(dp_problem* p, cplx* d, int nb) {
 }
 
 int spectral_derivative(dp_problem* p, int nrhs, const cplx* in, cplx* out) {
+  if (p->blu_M) return bluestein_derivative(p, in, out, nrhs, true);
   const int n = (int)p->n;
   const size_t tot = (size_t)n * nrhs;
   hipStream_t st = p->ctx->stream;
@@ -323,8 +463,13 @@ int curvature_spectral(dp_problem* p, double* hkap) {
   double* kap = reinterpret_cast<double*>(zc + 2 * (size_t)n);
   const int grid = grid_for((size_t)n);
   pack_position<<<grid, 256, 0, st>>>(p->src.as<SrcRec>(), zc, n);
-  t_derivative(p, zc, 2);   // both columns: z'
-  t_derivative(p, zc + n, 1);  // second column: z''
+  if (p->blu_M) {
+    DP_TRY(bluestein_derivative(p, zc, zc, 2, false));       // both columns: z'
+    DP_TRY(bluestein_derivative(p, zc + n, zc + n, 1, false));  // second column: z''
+  } else {
+    t_derivative(p, zc, 2);   // both columns: z'
+    t_derivative(p, zc + n, 1);  // second column: z''
+  }
   curvature_from_derivs<<<grid, 256, 0, st>>>(zc, p->src.as<SrcRec>(), kap, n);
   DP_HIP(hipGetLastError());
   DP_HIP(hipMemcpyAsync(hkap, kap, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));

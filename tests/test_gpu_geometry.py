@@ -1,4 +1,5 @@
-"""Curvature computed by the library from the node positions (kappa == NULL).
+"""Curvature computed by the library from the node positions (kappa == NULL),
+for power-of-two n (radix-2/4 FFT) and any other even n (Bluestein).
 
 The reference curvature is the analytic one of each curve, evaluated at the
 nodes by the input generator: (x' y'' - y' x'') / |x'|^3 with exact
@@ -29,7 +30,8 @@ def _no_kappa(b):
 
 
 @pytest.mark.parametrize("name,n", [("disk", 16), ("disk", 1024), ("kite", 1024), ("star", 1024),
-                                    ("randstar0", 2048), ("kite", 32768), ("randstar3", 131072)])
+                                    ("randstar0", 2048), ("kite", 32768), ("randstar3", 131072),
+                                    ("disk", 18), ("kite", 1000), ("star", 3008), ("randstar1", 64 * 1021)])
 def test_curvature_from_nodes(name, n):
     b = sample_boundary(name, n)
     om = omega_for_ppw(n, b.L, 10.0)
@@ -41,19 +43,13 @@ def test_curvature_from_nodes(name, n):
 
 
 def test_given_curvature_is_kept():
-    b = sample_boundary("kite", 1000)  # not a power of two: kappa must be given
+    b = sample_boundary("kite", 1000)
     p = problem(b, 20.0, 20.0, 0)
     assert np.array_equal(dp.dp_problem_kappa(p), b.kappa)
 
 
-def test_null_curvature_needs_power_of_two():
-    b = sample_boundary("star", 1000)
-    with pytest.raises(dp.DpError) as e:
-        problem(_no_kappa(b), 20.0, 20.0, 0)
-    assert e.value.code == dp.DP_EINVAL
-
-
-@pytest.mark.parametrize("name,n,kind", [("kite", 1024, 1), ("star", 2048, 0), ("randstar2", 1024, 1)])
+@pytest.mark.parametrize("name,n,kind", [("kite", 1024, 1), ("star", 2048, 0), ("randstar2", 1024, 1),
+                                         ("kite", 1000, 1), ("star", 1536, 0)])
 def test_matvec_with_computed_curvature(name, n, kind):
     b = sample_boundary(name, n)
     om = omega_for_ppw(n, b.L, 10.0)

@@ -57,10 +57,11 @@ def test_soft_star_ragged_matvec(n):
     assert relerr(to_host(y), A @ q) < TOL
 
 
-@pytest.mark.parametrize("nrhs", [1, 16])
-def test_hard_kite_matvec(nrhs):
-    b = sample_boundary("kite", 1024)
-    om = omega_for_ppw(1024, b.L, 10.0)
+@pytest.mark.parametrize("n,nrhs", [(1024, 1), (1024, 16), (1000, 3), (1536, 64)])
+def test_hard_kite_matvec(n, nrhs):
+    # n = 1000, 1536: the spectral derivative of Maue's form by Bluestein's DFT
+    b = sample_boundary("kite", n)
+    om = omega_for_ppw(n, b.L, 10.0)
     A = ny.hard_matrix(b, om, om)
     q = random_density(b.n, nrhs, seed=7)
     p = problem(b, om, om, 1)
@@ -112,8 +113,10 @@ def test_layers(op, name):
 
 
 # n > 4096 takes the four-step path with n = n1 n2: 8192 = 128 x 64,
-# 32768 = 256 x 128, 65536 = 256 x 256.  The Nyquist mode n/2 is dropped.
-@pytest.mark.parametrize("n", [64, 4096, 8192, 32768, 65536])
+# 32768 = 256 x 128, 65536 = 256 x 256.  Other even n go through Bluestein's
+# chirp-z DFT with power-of-two FFTs of length M >= 2n - 1 (1000: 2048 in LDS,
+# 3008: 8192, 64 * 1021 = 65344: 131072).  The Nyquist mode n/2 is dropped.
+@pytest.mark.parametrize("n", [64, 4096, 8192, 32768, 65536, 1000, 3008, 64 * 1021])
 def test_spectral_derivative(n):
     b = sample_boundary("disk", n)
     t = 2 * np.pi * np.arange(n) / n

@@ -11,7 +11,8 @@ from tests.gpu_util import empty, problem, relerr, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-CASES = [("disk", 1024, 0), ("disk", 1024, 1), ("star", 4096, 0), ("kite", 4096, 1), ("kite", 2048, 0)]
+CASES = [("disk", 1024, 0), ("disk", 1024, 1), ("star", 4096, 0), ("kite", 4096, 1), ("kite", 2048, 0),
+         ("kite", 1000, 1)]
 
 
 def _setup(cfg, n, kind):
@@ -62,7 +63,7 @@ def test_apply_parity_gauss_jordan_panels(gj_steps):
     assert relerr(to_host(z), pc.apply(P, v)) < 1e-10
 
 
-@pytest.mark.parametrize("cfg,n,kind", [("star", 4096, 0), ("kite", 4096, 1)])
+@pytest.mark.parametrize("cfg,n,kind", [("star", 4096, 0), ("kite", 4096, 1), ("kite", 1000, 1), ("kite", 3008, 1)])
 def test_preconditioned_solve(cfg, n, kind):
     b, om, eta, P, p = _setup(cfg, n, kind)
     A = ny.cfie_matrix(b, om, eta, kind)
