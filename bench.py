@@ -48,11 +48,12 @@ PEAK_FP16_MFMA = 2500.0
 FLOPS_MFMA16_PER_COL = 24
 # HBM bytes per launch of the two 64-column hard sweeps at n = 32768 with the
 # default 2048-block grid (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the
-# counts of a 512 MiB device copy in the same run).  They describe the current
-# kernels in that configuration; another configuration or a changed kernel
-# must be measured again before they are reported.
-TRAFFIC_FP64_SWEEP = 1.4011e9
-TRAFFIC_FP32_SWEEP = 0.5774e9
+# counts of a 512 MiB device copy in the same run; FETCH_SIZE counts half the
+# bytes the copy moves).  They describe the current kernels in that
+# configuration; another configuration or a changed kernel must be measured
+# again before they are reported.
+TRAFFIC_FP64_SWEEP = 1.1276e9 + 0.2734e9
+TRAFFIC_FP32_SWEEP = 0.3025e9 + 0.2684e9
 
 # Algorithmic FP64 flops of one ordered pair in the sound-hard sweep (far-field
 # evaluation path; an FMA counts 2): geometry 5, 1/r 8, r and z 2, H0/H1 142,
@@ -128,88 +129,118 @@ def cpu_baseline(b, om, eta, nrhs, budget_s=25.0):
     }
 
 
-def serve_stream(dp, nreq, rate, slots, seed=7):
-    """Serving stream: Poisson arrivals of independent solve requests on the
-    seeded random-star family, n = 2^k log-uniform in [2048, 65536], soft and
-    hard 50/50, 1-16 plane waves each, 10 points per wavelength, eta = omega,
-    preconditioned, tolerance 1e-8 (FP64 residual).  The same stream (same
-    arrival times) is served by the mixed-precision and by the FP64 solver."""
-    import threading
+def _stream_request(k, seed):
+    """Request k of the serving stream: n = 64 round(e^U(ln 2048, ln 65536) / 64),
+    the seeded random star with seed k (geometry seed = request id), sound-soft
+    or sound-hard with probability 1/2, 1-16 plane waves at U(0, 2 pi) angles,
+    10 points per wavelength, eta = omega."""
     from synth import omega_for_ppw, sample_boundary
+    rng = np.random.default_rng([seed, k])
+    n = int(64 * round(np.exp(rng.uniform(np.log(2048), np.log(65536))) / 64))
+    kind = int(rng.integers(0, 2))
+    nrhs = int(rng.integers(1, 17))
+    ang = rng.uniform(0, 2 * np.pi, nrhs)
+    b = sample_boundary(f"randstar{k}", n)
+    return b, omega_for_ppw(n, b.L, 10.0), kind, ang
 
-    rng = np.random.default_rng(seed)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
-    arrivals -= arrivals[0]
-    geo = {}
-    reqs = []
-    t0 = time.perf_counter()
-    for k in range(nreq):
-        n = int(2 ** int(np.rint(rng.uniform(11, 16))))
-        gs = int(rng.integers(0, 4))
-        kind = int(rng.integers(0, 2))
-        nrhs = int(rng.integers(1, 17))
-        ang = rng.uniform(0, 2 * np.pi, nrhs)
-        if (gs, n) not in geo:
-            geo[(gs, n)] = sample_boundary(f"randstar{gs}", n)
-        b = geo[(gs, n)]
-        om = omega_for_ppw(n, b.L, 10.0)
-        reqs.append((b, om, kind, ang))
-    t_geo = time.perf_counter() - t0
 
-    def run(precision):
-        srv = dp.Server(slots=slots)
-        # warm-up: one small request (kernel loading)
-        b, om, kind, ang = reqs[0]
-        srv.wait(srv.submit(b, om, om, kind, angles=ang, precision=precision))
-        ids = [None] * nreq
-        start = time.perf_counter()
+def make_stream(nreq, seed=7, workers=None):
+    """The requests of the serving stream, sampled on host worker processes
+    (started before the GPU is touched)."""
+    import multiprocessing as mp
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        return pool.starmap(_stream_request, [(k, seed) for k in range(nreq)])
 
-        def submitter():
+
+def run_stream(dp, reqs, arrivals, precision, slots):
+    """Serve reqs (arrival offsets in seconds) on a fresh server; per-request
+    latency = completion - arrival (submission at the arrival time)."""
+    import threading
+    nreq = len(reqs)
+    srv = dp.Server(slots=slots)
+    # warm-up: one small request (kernel loading)
+    b, om, kind, ang = min(reqs, key=lambda r: r[0].n)
+    srv.wait(srv.submit(b, om, om, kind, angles=ang, precision=precision))
+    ids = [None] * nreq
+    failed = []
+    start = time.perf_counter()
+
+    def submitter():
+        try:
             for k, (b, om, kind, ang) in enumerate(reqs):
                 d = start + arrivals[k] - time.perf_counter()
                 if d > 0:
                     time.sleep(d)
                 ids[k] = srv.submit(b, om, om, kind, angles=ang, precision=precision)
+        except Exception as e:  # reported by the waiting loop below
+            failed.append(e)
 
-        th = threading.Thread(target=submitter)
-        th.start()
-        res = []
-        for k in range(nreq):
-            while ids[k] is None:
-                time.sleep(0.001)
-            res.append(srv.wait(ids[k]))
-        th.join()
-        st = srv.stats()
-        srv.close()
-        lat = np.array([t["t_done"] - t["t_submit"] for _, _, t, _ in res])
-        qw = np.array([t["t_admit"] - t["t_submit"] for _, _, t, _ in res])
-        t_first = min(t["t_submit"] for _, _, t, _ in res)
-        t_last = max(t["t_done"] for _, _, t, _ in res)
-        ev = sorted([(t["t_admit"], 1) for _, _, t, _ in res] + [(t["t_done"], -1) for _, _, t, _ in res])
-        conc = peak = 0
-        for _, d in ev:
-            conc += d
-            peak = max(peak, conc)
-        solves = sum(r[3].size for r in reqs)
-        return {
-            "solves_per_s": solves / (t_last - t_first),
-            "requests_per_s": nreq / (t_last - t_first),
-            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
-                           "max": float(lat.max() * 1e3)},
-            "queue_wait_ms_mean": float(qw.mean() * 1e3),
-            "makespan_s": t_last - t_first,
-            "peak_concurrent": peak,
-            "converged": all(r[3] == dp.DP_OK for r in res),
-            "relres_max": float(max(r[1]["relres_max"] for r in res)),
-            "mem_peak_gb": st["mem_peak"] / 1e9,
-        }
+    th = threading.Thread(target=submitter)
+    th.start()
+    res = []
+    for k in range(nreq):
+        while ids[k] is None:
+            if failed:
+                th.join()
+                srv.close()
+                raise failed[0]
+            time.sleep(0.001)
+        res.append(srv.wait(ids[k]))
+        if (k + 1) % 25 == 0:
+            log(f"  served {k + 1}/{nreq}")
+    th.join()
+    st = srv.stats()
+    srv.close()
+    lat = np.array([t["t_done"] - t["t_submit"] for _, _, t, _ in res])
+    qw = np.array([t["t_admit"] - t["t_submit"] for _, _, t, _ in res])
+    t_first = min(t["t_submit"] for _, _, t, _ in res)
+    t_last = max(t["t_done"] for _, _, t, _ in res)
+    ev = sorted([(t["t_admit"], 1) for _, _, t, _ in res] + [(t["t_done"], -1) for _, _, t, _ in res])
+    conc = peak = 0
+    for _, d in ev:
+        conc += d
+        peak = max(peak, conc)
+    solves = sum(r[3].size for r in reqs)
+    return {
+        "requests": nreq,
+        "solves_per_s": solves / (t_last - t_first),
+        "requests_per_s": nreq / (t_last - t_first),
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+                       "max": float(lat.max() * 1e3)},
+        "queue_wait_ms": {"mean": float(qw.mean() * 1e3), "p99": float(np.percentile(qw, 99) * 1e3)},
+        "makespan_s": t_last - t_first,
+        "peak_concurrent": peak,
+        "converged": all(r[3] == dp.DP_OK for r in res),
+        "relres_max": float(max(r[1]["relres_max"] for r in res)),
+        "mem_peak_gb": st["mem_peak"] / 1e9,
+    }
 
-    out = {"requests": nreq, "arrival_rate_per_s": rate, "slots": slots, "rhs_total": int(sum(r[3].size for r in reqs)),
+
+def serve_stream(dp, reqs, slots, load=0.8, ncap=100, seed=11):
+    """The serving stream of independent solve requests (see _stream_request),
+    preconditioned, tolerance 1e-8 (FP64 residual), for each solver:
+    capacity = completed requests per second when the first `ncap` requests
+    all arrive at once (every slot kept busy); then all requests with Poisson
+    arrivals at `load` x that capacity, with p50/p99 latency from arrival to
+    completion."""
+    out = {"requests": len(reqs), "slots": slots, "load": load,
+           "rhs_total": int(sum(r[3].size for r in reqs)),
            "n_range": [int(min(r[0].n for r in reqs)), int(max(r[0].n for r in reqs))],
-           "hard_fraction": float(np.mean([r[2] for r in reqs])), "geometry_prep_s": t_geo}
+           "hard_fraction": float(np.mean([r[2] for r in reqs]))}
     for name, prec in (("mixed", dp.DP_PREC_MIXED), ("fp64", dp.DP_PREC_FP64)):
-        out[name] = run(prec)
-        log(f"serve [{name}]: {json.dumps(out[name])}")
+        cap = run_stream(dp, reqs[:ncap], np.zeros(ncap), prec, slots)
+        log(f"serve [{name}] capacity: {json.dumps(cap)}")
+        rate = load * cap["requests_per_s"]
+        rng = np.random.default_rng(seed)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
+        arrivals -= arrivals[0]
+        loaded = run_stream(dp, reqs, arrivals, prec, slots)
+        loaded["arrival_rate_per_s"] = rate
+        log(f"serve [{name}] at {load:.0%} of capacity: {json.dumps(loaded)}")
+        out[name] = {"capacity_requests_per_s": cap["requests_per_s"], "capacity_solves_per_s": cap["solves_per_s"],
+                     "capacity_run": cap, "loaded": loaded}
     return out
 
 
@@ -251,10 +282,13 @@ def main():
                     help="fp64: GMRES on the FP64 operator; mixed: iterative refinement with "
                          "FP32-operator corrections and FP64 residuals (same 1e-8 FP64 residual); "
                          "both (default): mixed is the reported value, FP64 is reported beside it")
-    ap.add_argument("--serve", type=int, default=32, metavar="N",
+    ap.add_argument("--serve", type=int, default=200, metavar="N",
                     help="also serve a stream of N independent requests (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=2.5, help="mean arrivals per second")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="Poisson arrival rate as a fraction of the measured capacity")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving stream (e.g. under a kernel trace of the slots' streams)")
     ap.add_argument("--no-iteration-study", action="store_true",
                     help="skip the unpreconditioned solves that give n_n beside n_p")
     ap.add_argument("--resident-only", action="store_true",
@@ -270,9 +304,23 @@ def main():
               "a multi-GPU split of the sweep by target rows is not built", file=sys.stderr)
         sys.exit(2)
 
+    stream = None
+    if args.serve > 0:
+        t0 = time.perf_counter()
+        stream = make_stream(args.serve)     # host processes, before the GPU is touched
+        log(f"serving stream: {args.serve} requests sampled in {time.perf_counter() - t0:.1f} s")
+
     import torch
     import paper_1408_1578_amd as dp
     from synth import config_boundary, plane_wave_angles
+
+    if args.serve_only:
+        if not stream:
+            sys.exit("bench.py: --serve-only needs --serve N > 0")
+        out = {"serving": serve_stream(dp, stream, args.serve_slots, load=args.serve_load,
+                                       ncap=min(100, len(stream)))}
+        print(json.dumps(out), flush=True)
+        return
 
     b, om, eta, kind = config_boundary("kite", args.n)
     nrhs = args.nrhs
@@ -304,13 +352,20 @@ def main():
         def step():
             t0 = time.perf_counter()
             prob = dp.Problem.from_boundary(ctx, b, om, eta, kind) if full else resident
+            t_create = time.perf_counter() - t0
             if use_pc:
                 dp.dp_precond_build(prob)
             dp.dp_rhs_plane_wave(prob, angles, f)
+            t1 = time.perf_counter()
             info = dp.dp_solve(prob, f, q, tol=1e-8, restart=80, use_precond=use_pc, precision=prec)
+            t2 = time.perf_counter()
             if full:
                 q_host.copy_(q)          # synchronous: q is in host memory when the step ends
             dt = time.perf_counter() - t0
+            info["t_create"] = t_create
+            info["t_build_rhs"] = t1 - t0 - t_create
+            info["t_solve"] = t2 - t1
+            info["t_readback"] = time.perf_counter() - t2
             if full:
                 info["precond"] = dp.dp_precond_get_info(prob) if use_pc else {}
                 prob.close()
@@ -374,6 +429,10 @@ def main():
                 "precond_apply": float(np.mean([i["t_apply"] for i in infos])),
                 "krylov": float(np.mean([i["t_krylov"] for i in infos])),
                 "precond_setup": float(np.mean([i["precond"].get("t_setup", 0.0) for i in infos])),
+                "problem_create": float(np.mean([i["t_create"] for i in infos])),
+                "precond_build_and_rhs_wall": float(np.mean([i["t_build_rhs"] for i in infos])),
+                "solve_wall": float(np.mean([i["t_solve"] for i in infos])),
+                "q_to_host": float(np.mean([i["t_readback"] for i in infos])),
             },
             "sweep_fp64": {"launch_ms": avg * 1e3, "launches": launches, "tflops": achieved,
                            "frac_fp64_peak": achieved / PEAK_FP64_VALU},
@@ -480,9 +539,10 @@ def main():
         if not args.no_iteration_study:
             out["iteration_study"] = iteration_study(dp, ctx, tp, b, om, eta, kind, f, q, nrhs)
         tp.close()
-    if args.serve > 0:
+    if stream:
         log(f"serving stream: {args.serve} requests ...")
-        out["serving"] = serve_stream(dp, args.serve, args.serve_rate, args.serve_slots)
+        out["serving"] = serve_stream(dp, stream, args.serve_slots, load=args.serve_load,
+                                      ncap=min(100, len(stream)))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(b, om, eta, nrhs)

@@ -331,6 +331,7 @@ void dp_problem_destroy(dp_problem* p) {
   p->dens16.release();
   p->C32.release();
   p->diag.release();
+  p->srcblk.release();
   p->sc16.release();
   p->near_ptr.release();
   p->near_col.release();

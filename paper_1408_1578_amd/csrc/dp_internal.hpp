@@ -92,6 +92,7 @@ struct SweepParams {
   const cplxf* dens32;     // FP32 copies (near field and the few-column FP32 sweep)
   cplxf* partial32;
   const uint4* dens16;     // split-FP16 density tiles of the many-column FP32 sweep
+  const uint4* srcblk;     // per block of 32 sources: (x, y) FP64 pairs, then (nx, ny, w/4, 0) FP32
   const float* unscale16;  // [nd][nrp]: 1 / (kernel scale x density scale)
   float ksc[2];            // power-of-two scales of the FP32 kernel values, per density
   int n, nrp, nd, chunk_len, nchunks;
@@ -141,6 +142,7 @@ struct dp_problem {
   dp::DevBuf C;         // double[n]
   dp::DevBuf C32;       // float[n], C_k / (pi dt) (single-precision sweep)
   dp::DevBuf diag;      // double4[n]: S_ii (re, im), D_ii
+  dp::DevBuf srcblk;    // source blocks of the single-precision sweep (1 KB per 32 sources)
   dp::DevBuf twiddle;   // cplx[n]   (e^{-2 pi i l/n}), power-of-two n
   // Bluestein (chirp-z) DFT of length n for n not a power of two, through
   // power-of-two FFTs of length blu_M >= 2n - 1: chirp c_j = e^{i pi j^2/n},
@@ -200,12 +202,18 @@ int near_apply_group(dp_problem* p, int op, int nrp, const void* dens, bool dens
 int matvec(dp_problem* p, int nrhs, const cplx* q, cplx* y, int prec = 0);
 // fft.hip
 int spectral_derivative(dp_problem* p, int nrhs, const cplx* in, cplx* out);
+// In-place DFT of nb contiguous length-n columns (power-of-two n, twiddles
+// built): dir -1 forward, +1 inverse (unnormalised).  With n = n1 n2 (n2 = 1
+// up to 4096), the forward transform leaves X_k at position
+// n2 (k mod n1) + k / n1 and the inverse expects that order.
+void fft_inplace(dp_problem* p, cplx* d, int nb, int dir, int* n1, int* n2);
 // Chirp, twiddles and chirp spectrum of the Bluestein DFT (n not a power of two).
 int bluestein_init(dp_problem* p);
 // Curvature from the spectral t-derivatives of the node positions (FFT
 // tables built): written into the source records and into hkap (host, n).
 int curvature_spectral(dp_problem* p, double* hkap);
-// Per-node diagonal table (after the curvature and C_k are in place).
+// Per-node diagonal table (after the curvature and C_k are in place), and
+// the source blocks of the single-precision sweep.
 int build_diag(dp_problem* p);
 // rhs
 int rhs_plane_wave(dp_problem* p, int nrhs, const double* angles_dev, cplx* f);

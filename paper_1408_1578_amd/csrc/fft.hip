@@ -247,6 +247,14 @@ static void fft_passes(dp_problem* p, cplx* d, int nb, int dir) {
   fft_run(d, (int)p->n, p->twiddle.as<cplx>(), nb, dir, p->ctx->stream);
 }
 
+void fft_inplace(dp_problem* p, cplx* d, int nb, int dir, int* n1, int* n2) {
+  const int logn = ilog2((int)p->n);
+  const int log1 = logn <= 12 ? logn : (logn + 1) / 2;
+  *n1 = 1 << log1;
+  *n2 = 1 << (logn - log1);
+  fft_passes(p, d, nb, dir);
+}
+
 static int grid_for(size_t tot) {
   const size_t g = (tot + 255) / 256;
   return (int)(g > 8192 ? 8192 : g);

@@ -19,45 +19,63 @@ namespace dp {
 
 namespace {
 
-constexpr int kNearThreads = 256;
 
-// Per-row count (pass 0) or fill (pass 1) of the near-field sources: thread t
-// scans the contiguous source range [t per, (t + 1) per), so a block-wide
-// exclusive scan of the per-thread counts gives each thread its output slot
-// and the row comes out in ascending source order.
+// Per-row count (pass 0) or fill (pass 1) of the near-field sources.  One
+// thread per target row and source chunk (blockIdx.y: kScanChunks contiguous
+// source ranges, so that n/64 x kScanChunks blocks fill the chip); the block
+// streams its chunk's source positions through LDS in tiles of kScanTile
+// (16 bytes each, read once per block instead of the 64-byte record once per
+// pair), and every thread tests its row against the whole tile, so the
+// entries of a (row, chunk) come out in ascending source order at the
+// offset the host computed from the pass-0 counts.  The test is the sweep's
+// own FP64 expression (pair_r2), so both agree on every pair.
+constexpr int kScanRows = 64;     // rows (threads) per block
+constexpr int kScanChunks = 8;    // source chunks per row
+constexpr int kScanTile = 1024;   // sources per LDS tile (16 KB)
 template <int PASS>
-__global__ __launch_bounds__(kNearThreads) void near_scan(const SrcRec* __restrict__ src, int n, double r2near,
-                                                          int* __restrict__ cnt, const int* __restrict__ ptr,
-                                                          int* __restrict__ col) {
-  __shared__ int sc[kNearThreads];
-  const int i = blockIdx.x;
-  const int t = threadIdx.x;
-  const int per = (n + kNearThreads - 1) / kNearThreads;
-  const int ja = min(n, t * per), jb = min(n, ja + per);
-  const SrcRec ti = src[i];
+__global__ __launch_bounds__(kScanRows) void near_scan(const SrcRec* __restrict__ src, int n, double r2near,
+                                                       int* __restrict__ cnt, const int* __restrict__ off,
+                                                       int* __restrict__ col) {
+  __shared__ double2 tile[kScanTile];
+  const int i = blockIdx.x * kScanRows + threadIdx.x;
+  const int chunk = blockIdx.y;
+  const int per = (n + kScanChunks - 1) / kScanChunks;
+  const int cb = min(n, chunk * per), ce = min(n, cb + per);
+  const bool live = i < n;
+  const double xi = live ? src[i].x : 0.0, yi = live ? src[i].y : 0.0;
   int c = 0;
-  for (int j = ja; j < jb; ++j) {
-    const SrcRec s = src[j];
-    c += (j != i && pair_r2(ti.x, ti.y, s.x, s.y) < r2near) ? 1 : 0;
-  }
-  sc[t] = c;
-  __syncthreads();
-  // Hillis-Steele inclusive scan over the block
-  for (int off = 1; off < kNearThreads; off <<= 1) {
-    const int v = t >= off ? sc[t - off] : 0;
+  int o = (PASS == 1 && live) ? off[(size_t)chunk * n + i] : 0;
+  for (int j0 = cb; j0 < ce; j0 += kScanTile) {
+    const int len = min(kScanTile, ce - j0);
+    __syncthreads();  // the previous tile has been read by every thread
+    for (int k = threadIdx.x; k < len; k += kScanRows) tile[k] = make_double2(src[j0 + k].x, src[j0 + k].y);
     __syncthreads();
-    sc[t] += v;
-    __syncthreads();
+    if (!live) continue;
+    int k = 0;
+    for (; k + 4 <= len; k += 4) {  // four independent tests in flight
+      bool hit[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 s = tile[k + u];
+        hit[u] = (j0 + k + u != i) && pair_r2(xi, yi, s.x, s.y) < r2near;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (hit[u]) {
+          if (PASS == 0) ++c;
+          else col[o++] = j0 + k + u;
+        }
+      }
+    }
+    for (; k < len; ++k) {
+      const double2 s = tile[k];
+      if (j0 + k != i && pair_r2(xi, yi, s.x, s.y) < r2near) {
+        if (PASS == 0) ++c;
+        else col[o++] = j0 + k;
+      }
+    }
   }
-  if (PASS == 0) {
-    if (t == kNearThreads - 1) cnt[i] = sc[t];
-    return;
-  }
-  int o = ptr[i] + sc[t] - c;
-  for (int j = ja; j < jb; ++j) {
-    const SrcRec s = src[j];
-    if (j != i && pair_r2(ti.x, ti.y, s.x, s.y) < r2near) col[o++] = j;
-  }
+  if (PASS == 0 && live) cnt[(size_t)chunk * n + i] = c;
 }
 
 struct NearParams {
@@ -260,20 +278,32 @@ int near_build(dp_problem* p) {
   const int n = (int)p->n;
   const double zr = DP_HANKEL_ZA / p->omega;
   p->r2near = zr * zr;
-  DevBuf cnt;
-  DP_TRY(cnt.reserve((size_t)n * sizeof(int)));
-  near_scan<0><<<n, kNearThreads, 0, st>>>(p->src.as<SrcRec>(), n, p->r2near, cnt.as<int>(), nullptr, nullptr);
+  DevBuf cnt, off;
+  struct Release {
+    DevBuf &a, &b;
+    ~Release() {
+      a.release();
+      b.release();
+    }
+  } release{cnt, off};
+  const size_t nc = (size_t)kScanChunks * n;
+  DP_TRY(cnt.reserve(nc * sizeof(int)));
+  const dim3 grid((n + kScanRows - 1) / kScanRows, kScanChunks);
+  near_scan<0><<<grid, kScanRows, 0, st>>>(p->src.as<SrcRec>(), n, p->r2near, cnt.as<int>(), nullptr, nullptr);
   DP_HIP(hipGetLastError());
-  std::vector<int> hc(n);
-  DP_HIP(hipMemcpyAsync(hc.data(), cnt.p, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
+  std::vector<int> hc(nc);
+  DP_HIP(hipMemcpyAsync(hc.data(), cnt.p, nc * sizeof(int), hipMemcpyDeviceToHost, st));
   DP_HIP(hipStreamSynchronize(st));
-  std::vector<int> hp(n + 1);
+  // row pointers and, per (chunk, row), the offset of its first entry
+  std::vector<int> hp(n + 1), ho(nc);
   int64_t tot = 0;
   for (int i = 0; i < n; ++i) {
     hp[i] = (int)tot;
-    tot += hc[i];
+    for (int c = 0; c < kScanChunks; ++c) {
+      ho[(size_t)c * n + i] = (int)tot;
+      tot += hc[(size_t)c * n + i];
+    }
     if (tot > 0x7fffffff) {
-      cnt.release();
       set_error("near field too large: more than 2^31 pairs have omega r < 25 (frequency too low for n)");
       return DP_EINVAL;
     }
@@ -284,12 +314,13 @@ int near_build(dp_problem* p) {
   DP_TRY(p->near_col.reserve((size_t)(tot > 0 ? tot : 1) * sizeof(int)));
   DP_HIP(hipMemcpyAsync(p->near_ptr.p, hp.data(), (size_t)(n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
   if (tot > 0) {
-    near_scan<1><<<n, kNearThreads, 0, st>>>(p->src.as<SrcRec>(), n, p->r2near, nullptr, p->near_ptr.as<int>(),
-                                            p->near_col.as<int>());
+    DP_TRY(off.reserve(nc * sizeof(int)));
+    DP_HIP(hipMemcpyAsync(off.p, ho.data(), nc * sizeof(int), hipMemcpyHostToDevice, st));
+    near_scan<1><<<grid, kScanRows, 0, st>>>(p->src.as<SrcRec>(), n, p->r2near, nullptr, off.as<int>(),
+                                             p->near_col.as<int>());
     DP_HIP(hipGetLastError());
   }
   DP_HIP(hipStreamSynchronize(st));
-  cnt.release();
   return DP_OK;
 }
 

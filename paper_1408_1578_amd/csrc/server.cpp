@@ -62,6 +62,11 @@ int64_t estimate_bytes(const Request& r) {
   const double cplx = 16.0;
   double b = 0;
   b += n * (64 + 8 + 16);                                  // source records, Kress table, twiddles
+  if ((r.kind == DP_HARD || r.kappa.empty()) && (r.n & (r.n - 1))) {
+    double M = 1;
+    while (M < 2 * n - 1) M *= 2;
+    b += cplx * M * (2.0 + std::max(nrhs, 2.0)) + cplx * n;  // Bluestein twiddles, chirp spectrum, workspace
+  }
   double L = 0;
   for (double wi : r.w) L += wi;
   const double near_per_row = 2.0 * 25.0 / (r.omega * (L / n)) + 2.0;
@@ -247,9 +252,14 @@ int dp_server_submit(dp_server* s, const dp_request* rq, int64_t* id) {
     return DP_EINVAL;
   }
   const int64_t n = rq->n;
-  if (!rq->xy || !rq->nrm || !rq->w || (!rq->kappa && (n & (n - 1))) || n < 16 || n % 2 || n > (1LL << 26) || rq->nrhs < 1 ||
-      rq->nrhs > (1LL << 20) || (rq->kind != DP_SOFT && rq->kind != DP_HARD) ||
-      (rq->kind == DP_HARD && (n & (n - 1))) || (!rq->angles && !rq->f) || !(rq->omega > 0) || !(rq->eta > 0)) {
+  // the limits of dp_problem_create (spectral derivative: at most 2^24
+  // points, 2^23 unless a power of two)
+  const bool fft = rq->kind == DP_HARD || !rq->kappa;
+  const bool pow2 = (n & (n - 1)) == 0;
+  if (!rq->xy || !rq->nrm || !rq->w || n < 16 || n % 2 || n > (1LL << 26) ||
+      (fft && n > (pow2 ? (1LL << 24) : (1LL << 23))) || rq->nrhs < 1 || rq->nrhs > (1LL << 20) ||
+      (rq->kind != DP_SOFT && rq->kind != DP_HARD) || (!rq->angles && !rq->f) || !(rq->omega > 0) ||
+      !(rq->eta > 0)) {
     dp::set_error("dp_server_submit: invalid request (n = %lld, nrhs = %lld, kind = %d)", (long long)n,
                   (long long)rq->nrhs, rq->kind);
     return DP_EINVAL;

@@ -439,16 +439,18 @@ __device__ __forceinline__ flt4 mma16(const uint32_t (&a)[4], const uint4& b, fl
 // Block: 8 waves, each 16 targets x all nrp columns; per 32-source step
 // every lane evaluates 8 pairs (target lane % 16, sources 4 e + lane / 16),
 // which is exactly its A fragment; the four lane groups then read adjacent
-// source records, on distinct LDS banks.  The step's density tile, its 32 source
-// records and the C_k window of the block (FP32 table of C_k / (pi dt)) reach LDS
+// 16-byte records of the step's source block (positions, then FP32 normal
+// and weight), on distinct LDS banks.  The step's density tile, its source
+// block and the C_k window of the block (FP32 table of C_k / (pi dt)) reach LDS
 // by direct global-to-LDS loads issued two steps ahead; the steps cycle
 // through four separate sets of LDS arrays, so that reads of one set never
 // wait for the loads into another, and the block synchronises after every
 // second step (the loads for the next two steps are then complete, and the
 // two sets they overwrite have been read).  In LDS the
 // tile row (d, part, c) holds its four 16-byte chunks g at positions
-// g ^ ((row / 4) % 4), which keeps the 16 lanes reading one chunk of 16
-// consecutive rows on distinct banks.
+// g ^ ((row / 4 ^ (row & 2)) % 4): the 16 lanes that read one chunk of 16
+// consecutive rows land on 16 distinct 16-byte bank groups of 256 bytes,
+// and each 8 consecutive lanes on 8 distinct ones of 128 bytes.
 template <int OP, int NCB>
 __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
   constexpr int ND = Nd<OP>::v;
@@ -456,7 +458,7 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
   constexpr int TQ = ND * 4 * NC * 4;      // uint4 per tile
   constexpr int NQ = TQ / 64;              // wave loads per tile
   __shared__ uint4 Bt0[TQ], Bt1[TQ], Bt2[TQ], Bt3[TQ];
-  __shared__ uint4 Ss0[128], Ss1[128], Ss2[128], Ss3[128];  // 32 source records (64 bytes each)
+  __shared__ uint4 Ss0[64], Ss1[64], Ss2[64], Ss3[64];  // source block: 32 (x, y), 32 (nx, ny, w/4, 0)
   __shared__ float Cs0[192], Cs1[192], Cs2[192], Cs3[192];  // C_k for k = kb .. kb + 159 (mod n)
   const int n = p.n;
   const int tid = threadIdx.x;
@@ -474,8 +476,7 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
   const int j0 = blockIdx.y * p.chunk_len;  // multiple of 32
   const int j1 = min(n, j0 + p.chunk_len);
   const int nsteps = (j1 - j0 + 31) / 32;
-  const uint4* srcq = reinterpret_cast<const uint4*>(p.src);
-  const int gsw = lk ^ (li >> 2);          // swizzled chunk of this lane's B fragments
+  const int gsw = lk ^ (((li >> 2) ^ (li & 2)) & 3);  // swizzled chunk of this lane's B fragments
   // wave-uniform direct loads of step st into one buffer set
   auto dma = [&](int st, uint4* Bt, uint4* Ss, float* Cs) {
     const int jb = j0 + 32 * st;
@@ -483,13 +484,12 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
     for (int q = wv; q < NQ; q += 8) {
       const int P = 64 * q + lane;
       const int row = P >> 2;
-      __builtin_amdgcn_global_load_lds(tile + row * 4 + ((P & 3) ^ ((row >> 2) & 3)), &Bt[64 * q], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(tile + row * 4 + ((P & 3) ^ (((row >> 2) ^ (row & 2)) & 3)), &Bt[64 * q], 16,
+                                       0, 0);
     }
-    if (wv >= 6) {
-      const int P = 64 * (wv - 6) + lane;
-      const int js = min(jb + (P >> 2), n - 1);
-      __builtin_amdgcn_global_load_lds(srcq + (size_t)js * 4 + (P & 3), &Ss[64 * (wv - 6)], 16, 0, 0);
-    } else if (wv >= 3) {
+    if (wv == 7) {
+      __builtin_amdgcn_global_load_lds(p.srcblk + (size_t)(jb / 32) * 64 + lane, Ss, 16, 0, 0);
+    } else if (wv >= 3 && wv < 6) {
       const int P = 64 * (wv - 3) + lane;
       int k = (i0 - jb - 31 + min(P, 159)) % n;
       k += (k < 0) ? n : 0;
@@ -526,7 +526,8 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
     __builtin_amdgcn_sched_barrier(0);
     // A fragments: this lane's 8 pairs, hi and lo parts of Re K and Im K
     uint32_t arh[ND][4], arl[ND][4], aih[ND][4], ail[ND][4];
-    const SrcRec* ss = reinterpret_cast<const SrcRec*>(Ss);
+    const double2* sxy = reinterpret_cast<const double2*>(Ss);
+    const float4* snw = reinterpret_cast<const float4*>(Ss + 32);
 #pragma unroll
     for (int e2 = 0; e2 < 4; ++e2) {
       cplxf K[2][ND];
@@ -534,7 +535,9 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
       for (int h = 0; h < 2; ++h) {
         const int jj = 4 * (2 * e2 + h) + lk;  // k-index 8 lk + e holds source 4 e + lk
         const int j = jb + jj;
-        pair_kernel_far32<OP>(t, tf, ss[jj], Cs[31 + ti - jj], j >= j1, f, K[h]);
+        const double2 xy = sxy[jj];
+        const float4 nw = snw[jj];
+        pair_kernel_far32v<OP>(t, tf, xy.x, xy.y, nw.x, nw.y, nw.z, Cs[31 + ti - jj], j >= j1, f, K[h]);
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
@@ -789,7 +792,7 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   const int n = (int)p->n;
   const int nd = op == OP_HARD ? 2 : 1;
   int nrp = pad_cols(nrhs);
-  dp_problem::SweepCfg cfg;
+  dp_problem::SweepCfg cfg;  // default grid: about 2048 blocks
   {
     const auto it = p->tuned.find(tune_key(prec, op, nrp));
     if (it != p->tuned.end()) cfg = it->second;
@@ -832,6 +835,7 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   }
   SweepParams sp;
   sp.src = p->src.as<SrcRec>();
+  sp.srcblk = p->srcblk.as<uint4>();
   sp.C = p->C.as<double>();
   sp.C32 = p->C32.as<float>();
   sp.dens = p->dens.as<cplx>();
@@ -1021,11 +1025,30 @@ __global__ void diag_table(const SrcRec* __restrict__ src, double4* __restrict__
   }
 }
 
+// Source blocks of the single-precision sweep: for each block of 32 sources,
+// their positions as 32 FP64 pairs (512 bytes), then 32 FP32 quadruples
+// (nx, ny, w/4, 0) (512 bytes).  A step of the sweep loads one block (one
+// 16-byte chunk per lane of a wave), and the four lane groups of a wave read
+// records 16 bytes apart.  Sources past n repeat the last node with zero
+// weight.
+__global__ void src_blocks(const SrcRec* __restrict__ src, uint4* blk, int n, int nb) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nb * 32; j += gridDim.x * blockDim.x) {
+    const SrcRec s = src[j < n ? j : n - 1];
+    double2* xy = reinterpret_cast<double2*>(blk + (size_t)(j / 32) * 64);
+    float4* nw = reinterpret_cast<float4*>(blk + (size_t)(j / 32) * 64 + 32);
+    xy[j % 32] = make_double2(s.x, s.y);
+    nw[j % 32] = make_float4(s.nxf, s.nyf, j < n ? s.wf : 0.0f, 0.0f);
+  }
+}
+
 int build_diag(dp_problem* p) {
   const int n = (int)p->n;
   DP_TRY(p->diag.reserve((size_t)n * sizeof(double4)));
   diag_table<<<grid1d(n), 256, 0, p->ctx->stream>>>(p->src.as<SrcRec>(), p->diag.as<double4>(), n, p->R0,
                                                     2.0 * kPi / n, p->omega);
+  const int nb = (n + 31) / 32;
+  DP_TRY(p->srcblk.reserve((size_t)nb * 64 * sizeof(uint4)));
+  src_blocks<<<grid1d((size_t)nb * 32), 256, 0, p->ctx->stream>>>(p->src.as<SrcRec>(), p->srcblk.as<uint4>(), n, nb);
   DP_HIP(hipGetLastError());
   return DP_OK;
 }

@@ -166,18 +166,20 @@ __device__ __forceinline__ double max_f64(double a, double b) {
 // included: r = 0) get wf = 0 and hence K = 0; their squared distance is
 // raised to at least r2near, which keeps every value finite and the argument
 // of the asymptotic branch at or above DP_HANKEL_ZA.
+// The source enters as its position (sx, sy) and the FP32 normal and weight.
 template <int OP>
-__device__ __forceinline__ void pair_kernel_far32(const Tgt& t, const Tgt32& tf, const SrcRec& s, float rho,
-                                                  bool zero, const Far32& f, cplxf* K) {
-  const double dx = t.x - s.x, dy = t.y - s.y;
-  const double r2p = pair_r2(t.x, t.y, s.x, s.y);
+__device__ __forceinline__ void pair_kernel_far32v(const Tgt& t, const Tgt32& tf, double sx, double sy, float snx,
+                                                   float sny, float swf, float rho, bool zero, const Far32& f,
+                                                   cplxf* K) {
+  const double dx = t.x - sx, dy = t.y - sy;
+  const double r2p = pair_r2(t.x, t.y, sx, sy);
   zero = zero || r2p < f.r2near;
   const double r2 = max_f64(r2p, f.r2near);
   const float y0 = dp_rsqrtf((float)r2);
   const double yd = (double)y0;
   const double r0 = r2 * yd;
   const double w = fma(yd * f.qh, fma(-r0, r0, r2), r0 * f.qt);  // (2 omega / pi) r
-  const float wq = zero ? 0.0f : s.wf;
+  const float wq = zero ? 0.0f : swf;
   const H01f h = hankel01_far32w(w, f.sc0 * wq);
   const float dxf = (float)dx, dyf = (float)dy;
   const float A0 = fmaf(rho, h.h0.re, h.h0.im);
@@ -189,7 +191,7 @@ __device__ __forceinline__ void pair_kernel_far32(const Tgt& t, const Tgt32& tf,
   const float B1 = fmaf(rho, h.h1.re, h.h1.im);
   const float T1 = h.h1.re;
   if constexpr (OP == OP_SOFT || OP == OP_D) {
-    const float on = fmaf(s.nxf, dxf, s.nyf * dyf) * (y0 * f.om);  // omega nu_j.rhat
+    const float on = fmaf(snx, dxf, sny * dyf) * (y0 * f.om);  // omega nu_j.rhat
     if constexpr (OP == OP_SOFT) K[0] = {fmaf(f.eta, Sr, -on * B1), fmaf(f.eta, A0, on * T1)};
     else K[0] = {-on * B1, on * T1};
   } else if constexpr (OP == OP_DP) {
@@ -197,10 +199,16 @@ __device__ __forceinline__ void pair_kernel_far32(const Tgt& t, const Tgt32& tf,
     K[0] = {on * B1, -on * T1};
   } else {  // OP_HARD: S and G = -i (omega^2/eta)(nu_i.nu_j) S - D'
     const float on = fmaf(tf.nxo, dxf, tf.nyo * dyf) * y0;           // omega nu_i.rhat sc1/sc0
-    const float g = fmaf(tf.nxg, s.nxf, tf.nyg * s.nyf);              // (omega^2/eta) nu_i.nu_j sc1/sc0
+    const float g = fmaf(tf.nxg, snx, tf.nyg * sny);                  // (omega^2/eta) nu_i.nu_j sc1/sc0
     K[0] = {-A0, Sr};
     K[1] = {fmaf(g, Sr, -on * B1), fmaf(g, A0, on * T1)};
   }
+}
+
+template <int OP>
+__device__ __forceinline__ void pair_kernel_far32(const Tgt& t, const Tgt32& tf, const SrcRec& s, float rho,
+                                                  bool zero, const Far32& f, cplxf* K) {
+  pair_kernel_far32v<OP>(t, tf, s.x, s.y, s.nxf, s.nyf, s.wf, rho, zero, f, K);
 }
 
 // ------------------------------------------------------------ epilogue

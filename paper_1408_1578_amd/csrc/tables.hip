@@ -6,7 +6,9 @@
 //   C_k = R_k - (2 pi/n) log(4 sin^2(pi k/n)),  k = 1..n-1;  C_0 := R_0.
 // The sweep uses A_ij = (2 pi/n)|x'_j| K + C_{(i-j) mod n} |x'_j| K1 off the
 // diagonal, which equals R_{|i-j|} K1 + (pi/N) K2 with K2 = K - K1 log(...)
-// without forming the cancelling difference.
+// without forming the cancelling difference.  The cosine sums of R_k are the
+// real part of the DFT of the sequence 1/m (m = 1..N-1): one FFT for
+// power-of-two n, else a fixed-order block reduction per k.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -55,6 +57,29 @@ __global__ __launch_bounds__(256) void kress_table(const double* __restrict__ ct
   }
 }
 
+// a_m = 1/m for 1 <= m < N, 0 otherwise (length n = 2N): Re DFT(a)_k is the
+// sum in R_k.
+__global__ void kress_seq(cplx* a, int n) {
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n; m += gridDim.x * blockDim.x)
+    a[m] = {(m >= 1 && m < n / 2) ? 1.0 / m : 0.0, 0.0};
+}
+
+// R_k = -(2 pi/N) Re A_k - (pi/N^2) (-1)^k from A = DFT(a) as the FFT leaves
+// it (n = n1 n2: A_k at position n2 (k mod n1) + k / n1); then C_k.
+__global__ void kress_from_dft(const cplx* __restrict__ A, double* C, int n, int n1, int n2) {
+  const int N = n / 2;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const double Ak = A[(size_t)n2 * (k % n1) + k / n1].re;
+    const double R = -(2.0 * kPi / N) * Ak - (kPi / ((double)N * N)) * ((k & 1) ? -1.0 : 1.0);
+    if (k == 0) {
+      C[0] = R;
+    } else {
+      const double sn = sinpi((double)k / n);
+      C[k] = R - (2.0 * kPi / n) * log(4.0 * sn * sn);
+    }
+  }
+}
+
 int build_tables(dp_problem* p) {
   const int n = (int)p->n;
   hipStream_t st = p->ctx->stream;
@@ -67,7 +92,19 @@ int build_tables(dp_problem* p) {
     tw = p->twiddle.as<cplx>();
   }
   trig_tables<<<(n + 255) / 256, 256, 0, st>>>(ct.as<double>(), tw, n);
-  kress_table<<<n, 256, 0, st>>>(ct.as<double>(), p->C.as<double>(), n);
+  if (tw) {
+    // power-of-two n: the sums of R_k as one FFT of the sequence 1/m
+    DevBuf a;
+    DP_TRY(a.reserve((size_t)n * sizeof(cplx)));
+    kress_seq<<<(n + 255) / 256, 256, 0, st>>>(a.as<cplx>(), n);
+    int n1 = 0, n2 = 0;
+    fft_inplace(p, a.as<cplx>(), 1, -1, &n1, &n2);
+    kress_from_dft<<<(n + 255) / 256, 256, 0, st>>>(a.as<cplx>(), p->C.as<double>(), n, n1, n2);
+    DP_HIP(hipGetLastError());
+    a.release();
+  } else {
+    kress_table<<<n, 256, 0, st>>>(ct.as<double>(), p->C.as<double>(), n);
+  }
   DP_HIP(hipGetLastError());
   std::vector<double> hc(n);
   DP_HIP(hipMemcpyAsync(hc.data(), p->C.as<double>(), n * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -30,6 +30,9 @@ def _requests():
     b, om, eta, _ = config_boundary("disk", 1024)
     f = ny.point_source_data(b, om, np.array([0.2, -0.1]), 1)
     out.append((b, om, eta, 1, dict(f=f, use_precond=False)))
+    b = sample_boundary("randstar4", 1000)      # sound-hard, n not a power of two
+    om = omega_for_ppw(1000, b.L, 10.0)
+    out.append((b, om, om, 1, dict(angles=plane_wave_angles(3), precision=dp.DP_PREC_MIXED)))
     return out
 
 
