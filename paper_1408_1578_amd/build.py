@@ -29,8 +29,8 @@ def build(verbose=False, jobs=8):
             continue
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [HIPCC, *FLAGS, *lang, "-c", path, "-o", obj]
+        # the .cpp sources include the HIP runtime too: every file is compiled as HIP
+        cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -11,8 +11,8 @@
 //     economized on [0, 1/DP_HANKEL_ZA^2] (hankel_poly.hpp, error < 1e-17);
 //   * z < DP_HANKEL_ZA: J_0, J_1 by Miller's backward recurrence
 //     J_{k-1} = (2k/z) J_k - J_{k+1} normalised by J_0 + 2 sum J_{2k} = 1
-//     (DLMF 10.74(iv), 10.12.4), Y_0 by Neumann's series (DLMF 10.23.?:
-//     Y_0 = (2/pi)[(ln(z/2)+gamma) J_0 - 2 sum_{k>=1} (-1)^k J_{2k}/k]) and
+//     (DLMF 10.74(iv), 10.12.4), Y_0 by Neumann's expansion in the J_{2k}
+//     (Y_0 = (2/pi)[(ln(z/2)+gamma) J_0 - 2 sum_{k>=1} (-1)^k J_{2k}/k]) and
 //     Y_1 = -Y_0' from the same series differentiated term by term,
 //       Y_1 = (2/pi)[-J_0/z + (ln(z/2)+gamma) J_1 - J_1
 //              + sum_{m>=1} (-1)^{m+1} (2m+1)/(m(m+1)) J_{2m+1}].
