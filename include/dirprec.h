@@ -216,6 +216,9 @@ typedef struct {
   double inner_tol; /* mixed: relative tolerance of the correction solves, at least the one
                        that takes every column from its current FP64 residual r to
                        0.3 tol (0.3 tol/r for the worst column); default 1e-5 */
+  int eager;        /* 1: launch the kernels of each Arnoldi step's orthogonalisation
+                       and rotation update one by one instead of replaying their
+                       captured HIP graph (the same kernels and results); default 0 */
 } dp_solve_opts;
 
 typedef struct {
@@ -233,9 +236,13 @@ typedef struct {
 } dp_solve_info;
 
 /* Solve A q = f for nrhs right-hand sides by restarted GMRES (x0 = 0, CGS2
- * Arnoldi, Givens rotations), right-preconditioned when requested; the
+ * Arnoldi, Givens rotations; Sec. 3), right-preconditioned when requested; the
  * preconditioned vectors are stored (flexible form) so q = Z y needs no extra
- * apply.  With DP_PREC_MIXED the solve is q_{k+1} = q_k + GMRES_32(f - A q_k)
+ * apply.  Each Arnoldi step, its least-squares update and the per-column
+ * stopping test run on the device; the host queues step k + 1 while step k
+ * runs and reads the column states back one step late, so it does not wait
+ * for the device inside a restart cycle except where the residual estimates
+ * predict that a step may stop the last columns.  With DP_PREC_MIXED the solve is q_{k+1} = q_k + GMRES_32(f - A q_k)
  * until the FP64 residual meets tol.  f, q: device n x nrhs complex.
  * opts/info may be NULL.  iters, relres: optional host arrays of nrhs entries
  * (per-column iteration counts and true FP64 relative residuals).  The

@@ -60,7 +60,7 @@ DP_PREC_FP64, DP_PREC_MIXED = 0, 1
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int),
                 ("max_iters", ctypes.c_int), ("use_precond", ctypes.c_int),
-                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double), ("eager", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -342,11 +342,11 @@ def dp_precond_export(p):
 
 
 def dp_solve(p, f, q, tol=1e-8, restart=80, max_iters=2000, use_precond=False, precision=DP_PREC_FP64,
-             inner_tol=1e-5):
+             inner_tol=1e-5, eager=False):
     nr = _cols(f, p.n)
     if _cols(q, p.n) != nr:
         raise ValueError("shape mismatch")
-    o = SolveOpts(tol, restart, max_iters, 1 if use_precond else 0, int(precision), inner_tol)
+    o = SolveOpts(tol, restart, max_iters, 1 if use_precond else 0, int(precision), inner_tol, 1 if eager else 0)
     info = SolveInfo()
     its = np.zeros(nr, np.int64)
     rel = np.zeros(nr, np.float64)
@@ -408,7 +408,7 @@ class Server:
             fc, fp = _host(np.asfortranarray(fa).ravel(order="F").view(np.float64))
             anp = None
         r = Request(n, xyp, nup, wp, kap, float(omega), float(eta), int(kind), nrhs, anp, fp,
-                    SolveOpts(tol, restart, max_iters, 1 if use_precond else 0, int(precision), inner_tol))
+                    SolveOpts(tol, restart, max_iters, 1 if use_precond else 0, int(precision), inner_tol, 0))
         rid = ctypes.c_int64()
         _check("dp_server_submit", lib().dp_server_submit(self.h, ctypes.byref(r), ctypes.byref(rid)))
         self._n[rid.value] = (n, nrhs)

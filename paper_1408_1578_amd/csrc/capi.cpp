@@ -340,6 +340,7 @@ void dp_problem_destroy(dp_problem* p) {
   p->tmp1.release();
   p->tmp2.release();
   p->tmp3.release();
+  krylov_graphs_destroy(p);
   for (auto& b : p->krylov_ws) b.release();
   for (auto& b : p->refine_ws) b.release();
   delete p;
@@ -481,7 +482,7 @@ int dp_precond_export(dp_problem* p, int64_t* seg_off, int64_t* seg_len, int64_t
 int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_solve_opts* opts,
              dp_solve_info* info, int64_t* iters, double* relres) {
   DP_CHECK(p && f && q && nrhs >= 1, "dp_solve: bad argument");
-  dp_solve_opts o = {1e-8, 80, 2000, 0, DP_PREC_FP64, 1e-5};
+  dp_solve_opts o = {1e-8, 80, 2000, 0, DP_PREC_FP64, 1e-5, 0};
   if (opts) o = *opts;
   if (o.inner_tol <= 0) o.inner_tol = 1e-5;
   DP_CHECK(o.tol > 0 && o.restart >= 1 && o.restart <= 1000 && o.max_iters >= 1, "dp_solve: bad options");

@@ -95,6 +95,8 @@ struct SweepParams {
   const uint4* srcblk;     // per block of 32 sources: (x, y) FP64 pairs, then (nx, ny, w/4, 0) FP32
   const float* unscale16;  // [nd][nrp]: 1 / (kernel scale x density scale)
   float ksc[2];            // power-of-two scales of the FP32 kernel values, per density
+  const int* guard;        // null, or guard_n flags: the launch does nothing when all are 0
+  int guard_n;
   int n, nrp, nd, chunk_len, nchunks;
   double omega, eta, dt;   // dt = 2 pi / n
   double r2near;           // pairs with r^2 < r2near are left to the near-field pass
@@ -167,9 +169,21 @@ struct dp_problem {
   bool near_kv_ready[5] = {};
   dp::DevBuf tmp1, tmp2, tmp3;
   // GMRES workspaces (basis, preconditioned basis, w, r, partial sums, the
-  // small Hessenberg/norm block), kept between solves so that repeated
-  // solves (refinement corrections, serving) do not allocate and free them
-  dp::DevBuf krylov_ws[6];
+  // projection/norm block, the rotation state), kept between solves so that
+  // repeated solves (refinement corrections, serving) do not allocate and
+  // free them
+  dp::DevBuf krylov_ws[7];
+  // executable graphs of the Arnoldi step's orthogonalisation and rotation
+  // update (basis sizes up to 16, and beyond), the workspace addresses and
+  // sizes they were captured with, and whether capture works here
+  hipGraphExec_t kgraph[2] = {nullptr, nullptr};
+  std::vector<void*> kgraph_sig;
+  bool kgraph_ok = true;
+  // while set, sweeps launched for the operator skip their work when every
+  // flag of sweep_guard[0 .. sweep_guard_n) is 0 (a queued Arnoldi step after
+  // every column stopped)
+  const int* sweep_guard = nullptr;
+  int sweep_guard_n = 0;
   dp::DevBuf refine_ws[4];  // the same for the mixed-precision refinement (r, d, partial sums, flags)
   dp::Precond* pc = nullptr;
   // sweep launch configuration per (precision, operator, padded column count),
@@ -223,6 +237,8 @@ int hankel_eval_dev(int64_t m, const double* z, double* out, hipStream_t s);
 struct Gmres;
 int solve(dp_problem* p, int nrhs, const cplx* f, cplx* q, const dp_solve_opts* o, dp_solve_info* info,
           int64_t* iters, double* relres);
+// the executable graphs of the Arnoldi steps (problem teardown)
+void krylov_graphs_destroy(dp_problem* p);
 // precond
 int precond_build(dp_problem* p, const dp_precond_opts* o);
 // prec 1: single-precision tables and vectors (FP64 in and out)

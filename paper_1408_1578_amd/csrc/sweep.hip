@@ -36,8 +36,19 @@
 
 namespace dp {
 
+// A launch queued for an Arnoldi step after every column stopped does no
+// work: the guard flags are read once per block (uniform scalar loads), and
+// the whole block returns before any barrier.
+__device__ __forceinline__ bool sweep_skipped(const SweepParams& p) {
+  if (!p.guard) return false;
+  int any = 0;
+  for (int c = 0; c < p.guard_n; ++c) any |= p.guard[c];
+  return any == 0;
+}
+
 template <int OP, int NR>
 __global__ __launch_bounds__(256) void sweep_private(SweepParams p) {
+  if (sweep_skipped(p)) return;
   constexpr int ND = Nd<OP>::v;
   const int n = p.n;
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -79,6 +90,7 @@ __global__ __launch_bounds__(256) void sweep_private(SweepParams p) {
 
 template <int OP, int NRG, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void sweep_shared(SweepParams p) {
+  if (sweep_skipped(p)) return;
   constexpr int ND = Nd<OP>::v;
   constexpr int TJ = 32;
   constexpr int PER = TJ / WAVES;
@@ -181,6 +193,7 @@ struct Mfma64 {
 // T3 += (Kr + Ki)(Br + Bi); Re = T1 - T2, Im = T3 - T1 - T2.
 template <int OP, int NCBW, class M>
 __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
+  if (sweep_skipped(p)) return;
   using C = typename M::C;
   using V4 = typename M::V4;
   using R = decltype(C{}.re);
@@ -318,6 +331,7 @@ __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
 // accumulated in FP64 (FP64 and FP32 VALU issue at the same rate here).
 template <int OP, int NR>
 __global__ __launch_bounds__(256) void sweep_private32(SweepParams p) {
+  if (sweep_skipped(p)) return;
   constexpr int ND = Nd<OP>::v;
   const int n = p.n;
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -453,6 +467,7 @@ __device__ __forceinline__ flt4 mma16(const uint32_t (&a)[4], const uint4& b, fl
 // and each 8 consecutive lanes on 8 distinct ones of 128 bytes.
 template <int OP, int NCB>
 __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
+  if (sweep_skipped(p)) return;
   constexpr int ND = Nd<OP>::v;
   constexpr int NC = 16 * NCB;
   constexpr int TQ = ND * 4 * NC * 4;      // uint4 per tile
@@ -855,6 +870,8 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   sp.eta = p->eta;
   sp.dt = 2.0 * kPi / n;
   sp.r2near = p->r2near;
+  sp.guard = p->sweep_guard;
+  sp.guard_n = p->sweep_guard_n;
   SweepClock& clk = prec ? p->clock32 : p->clock;
   clk.start(st);
   if (prec) {
