@@ -49,10 +49,11 @@ def test_apply_parity(cfg, n, kind):
         assert relerr(to_host(z), pc.apply(P, v)) < 1e-10
 
 
-@pytest.mark.parametrize("gj_steps", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("gj_steps", [0, 1, 2, 3, 4, 8])
 def test_apply_parity_gauss_jordan_panels(gj_steps):
     # the size-class inverses with each panel width of the batched
-    # Gauss-Jordan elimination (1: one launch per step; 3: a ragged last panel)
+    # Gauss-Jordan elimination (0: automatic; 1: one launch per step; 3: a
+    # ragged last panel)
     b, om, eta, _ = config_boundary("kite", 4096)
     P = pc.build(b, om, eta, 1)
     p = problem(b, om, eta, 1)
