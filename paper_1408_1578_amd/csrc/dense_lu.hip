@@ -324,6 +324,101 @@ __global__ __launch_bounds__(256) void zgemm_sub(const cplx* __restrict__ A, int
       }
 }
 
+// C (M x N) -= A (M x K) B (K x N), or C = -A B with overwrite, for the
+// tall and skinny products of the triangular solves (N <= NB <= 16 columns,
+// K <= 256): the matrix-core tile above would leave three quarters of its 64
+// columns empty.  A block takes 16 rows and splits K into 16 groups: lane l of
+// wave w takes row l mod 16 and group 4 w + l / 16, with the NB columns in
+// registers, so that many blocks keep many short load chains in flight.  B's
+// rows sit in LDS, each group's run offset by 4 elements so that the four
+// groups of a wave read from different banks (within a group every lane reads
+// the same element: a broadcast).  The groups are added in a fixed order:
+// within the wave by lane exchanges, then over the waves through LDS.  Each
+// element of A is read once.
+template <int NB>
+__global__ __launch_bounds__(256) void zgemm_ts(const cplx* __restrict__ A, int lda, const cplx* __restrict__ B,
+                                                int ldb, cplx* C, int ldc, int M, int N, int K, int overwrite) {
+  constexpr int kPad = 4;
+  // B's rows, then (after the products) the partial sums [wave][column][row]
+  __shared__ cplx Bs[256 * NB + 16 * kPad];
+  cplx* red = Bs;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, kg = 4 * wv + (lane >> 4);
+  const int i = blockIdx.x * 16 + r;
+  const int kq = (K + 15) / 16;  // k per group
+  // B along its columns (K NB <= 256 NB elements, NB per thread), all loads
+  // issued before the first LDS store
+  {
+    cplx tb[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int j = e / K, k = e - j * K;
+      tb[q] = e < K * NB && j < N ? B[(size_t)j * ldb + k] : cplx{0.0, 0.0};
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < K * NB) {
+        const int j = e / K, k = e - j * K;
+        const int g = k / kq;
+        Bs[g * (kq * NB + kPad) + (k - g * kq) * NB + j] = tb[q];
+      }
+    }
+  }
+  // this lane's (at most 16) elements of A, all loads in flight together
+  const int k0 = kg * kq, nk = max(0, min(K, k0 + kq) - k0);
+  cplx av[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) av[t] = t < nk && i < M ? A[(size_t)(k0 + t) * lda + i] : cplx{0.0, 0.0};
+  __syncthreads();
+  cplx acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] = {0.0, 0.0};
+  const cplx* bg = Bs + kg * (kq * NB + kPad);
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    if (t < nk) {
+      const cplx* b = bg + t * NB;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const cplx bv = b[j];
+        acc[j].re = fma(av[t].re, bv.re, fma(-av[t].im, bv.im, acc[j].re));
+        acc[j].im = fma(av[t].re, bv.im, fma(av[t].im, bv.re, acc[j].im));
+      }
+    }
+  }
+  // the wave's four groups of this row: lanes l, l ^ 16, l ^ 32, l ^ 48
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    acc[j].re += __shfl_xor(acc[j].re, 16);
+    acc[j].im += __shfl_xor(acc[j].im, 16);
+    acc[j].re += __shfl_xor(acc[j].re, 32);
+    acc[j].im += __shfl_xor(acc[j].im, 32);
+  }
+  __syncthreads();  // B is no longer read
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) red[(wv * NB + j) * 16 + r] = acc[j];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 16 * NB; t += 256) {
+    const int rr = t & 15, j = t >> 4;
+    const int ii = blockIdx.x * 16 + rr;
+    if (j < N && ii < M) {
+      cplx v = red[j * 16 + rr];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        v.re += red[(w * NB + j) * 16 + rr].re;
+        v.im += red[(w * NB + j) * 16 + rr].im;
+      }
+      cplx& c = C[(size_t)j * ldc + ii];
+      const cplx c0 = overwrite ? cplx{0.0, 0.0} : c;
+      c = {c0.re - v.re, c0.im - v.im};
+    }
+  }
+}
+
 __global__ void dense_scatter(cplx* A, int n, const int* __restrict__ rows, const int* __restrict__ cols,
                               const cplx* __restrict__ vals, int nnz) {
   for (int q = blockIdx.x * 256 + threadIdx.x; q < nnz; q += gridDim.x * 256)
@@ -348,6 +443,13 @@ int nblocks(int64_t rows, int cap) {
 void launch_gemm_sub(hipStream_t st, const cplx* A, int lda, const cplx* B, int ldb, cplx* C, int ldc, int M, int N,
                      int K, int overwrite = 0) {
   if (M <= 0 || N <= 0 || K <= 0) return;
+  if (N <= 16 && K <= 256) {
+    const int g = (M + 15) / 16;
+    if (N <= 4) zgemm_ts<4><<<g, 256, 0, st>>>(A, lda, B, ldb, C, ldc, M, N, K, overwrite);
+    else if (N <= 8) zgemm_ts<8><<<g, 256, 0, st>>>(A, lda, B, ldb, C, ldc, M, N, K, overwrite);
+    else zgemm_ts<16><<<g, 256, 0, st>>>(A, lda, B, ldb, C, ldc, M, N, K, overwrite);
+    return;
+  }
   dim3 grid((M + 63) / 64, (N + 63) / 64);
   zgemm_sub<<<grid, 256, 0, st>>>(A, lda, B, ldb, C, ldc, M, N, K, overwrite);
 }
