@@ -799,6 +799,36 @@ static int pad_cols(int nrhs) {
 
 static int tune_key(int prec, int op, int nrp) { return prec * 1000 + op * 100 + nrp; }
 
+// Launch configuration without tuning, from autotuner runs on random stars
+// (n = 4096, 16384, 65536, soft and hard, 1-16 columns) and the 64-column
+// kite at n = 32768:
+//   <= 4 columns (one target row per lane): 8192 blocks from n = 16384 on
+//     (7-20% faster than 2048), 4096 below;
+//   FP64, 5-16 columns: the matrix-core kernel padded to 32 columns on 1024
+//     blocks for hard problems and for 16 columns up to n = 32768 (8-20%
+//     faster than the VALU kernel), else the VALU kernel on 8192 blocks;
+//   single precision, 5-16 columns: 1024 blocks up to n = 8192 (12%), 2048
+//     above;
+//   32-64 columns: 2048.
+static dp_problem::SweepCfg default_cfg(const dp_problem* p, int prec, int op, int nrp) {
+  dp_problem::SweepCfg c;
+  const int64_t n = p->n;
+  if (nrp <= 4) {
+    c.target_blocks = n >= 16384 ? 8192 : 4096;
+  } else if (nrp <= 16) {
+    if (prec) {
+      c.target_blocks = n <= 8192 ? 1024 : 2048;
+    } else if ((op == OP_HARD && (nrp == 16 || n <= 32768)) || (nrp == 16 && n <= 32768)) {
+      c.mfma = 1;
+      c.target_blocks = 1024;
+    } else {
+      c.mfma = 0;
+      c.target_blocks = 8192;
+    }
+  }
+  return c;
+}
+
 // Core sweep over one group of <= 64 columns.  a (and b for hard) are the
 // densities; results go to out0 (and out1).
 static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a, const cplx* b,
@@ -807,7 +837,7 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   const int n = (int)p->n;
   const int nd = op == OP_HARD ? 2 : 1;
   int nrp = pad_cols(nrhs);
-  dp_problem::SweepCfg cfg;  // default grid: about 2048 blocks
+  dp_problem::SweepCfg cfg = default_cfg(p, prec, op, nrp);
   {
     const auto it = p->tuned.find(tune_key(prec, op, nrp));
     if (it != p->tuned.end()) cfg = it->second;
@@ -967,7 +997,10 @@ int autotune(dp_problem* p, int nrhs, int prec, dp_tune_info* info) {
       if (rep > 0) t = std::min(t, (double)ms);  // the first run also allocates
     }
     if (rc != DP_OK) break;
-    if (c.target_blocks == 2048 && c.mfma <= 0) t_default = t;
+    {
+      const dp_problem::SweepCfg d = default_cfg(p, prec, op, nrp);
+      if (c.target_blocks == d.target_blocks && (modes == 1 || c.mfma == (d.mfma == 1 ? 1 : 0))) t_default = t;
+    }
     if (t < best) {
       best = t;
       bestc = c;
