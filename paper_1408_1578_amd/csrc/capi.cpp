@@ -337,6 +337,7 @@ void dp_problem_destroy(dp_problem* p) {
   p->near_col.release();
   p->near_out.release();
   for (auto& b : p->near_kv) b.release();
+  for (auto& b : p->near_bv) b.release();
   p->tmp1.release();
   p->tmp2.release();
   p->tmp3.release();

@@ -167,6 +167,13 @@ struct dp_problem {
   dp::DevBuf near_out;  // near-field sums [nd][nrp][n]
   dp::DevBuf near_kv[5];       // kernel values of the entries, per sweep operator ([q][nd])
   bool near_kv_ready[5] = {};
+  // when every near pair lies within circular index distance near_band of
+  // its row (a smooth curve sampled evenly: about 25/(omega h)), the same
+  // values as a band [offset + near_band][d][row] (zero where a pair in the
+  // band is not near), for the 64-column apply; -1: no band form
+  int near_band = -1;
+  dp::DevBuf near_bv[5];
+  bool near_bv_ready[5] = {};
   dp::DevBuf tmp1, tmp2, tmp3;
   // GMRES workspaces (basis, preconditioned basis, w, r, partial sums, the
   // projection/norm block, the rotation state), kept between solves so that

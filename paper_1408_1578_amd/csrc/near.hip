@@ -13,6 +13,7 @@
 // "near" with pair_r2, so every off-diagonal pair is applied exactly once.
 #include "sweep_pair.hpp"
 
+#include <algorithm>
 #include <vector>
 
 namespace dp {
@@ -248,6 +249,154 @@ __global__ __launch_bounds__(256) void near_apply64(NearParams p) {
   }
 }
 
+// ---- the band form of the 64-column apply
+// Largest circular index distance between a row and its near sources.
+__global__ __launch_bounds__(256) void near_bandwidth(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                      int n, int* out) {
+  __shared__ int red[256];
+  int m = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    for (int q = ptr[i]; q < ptr[i + 1]; ++q) {
+      int d = col[q] - i;
+      d = d < 0 ? -d : d;
+      d = min(d, n - d);
+      m = max(m, d);
+    }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, red[0]);
+}
+
+__global__ void zero_fill(cplx* x, size_t tot) {
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot; q += (size_t)gridDim.x * blockDim.x)
+    x[q] = {0.0, 0.0};
+}
+
+// The entries' values in the band layout bv[((o nd + d) n + i)], o = the
+// circular offset of the source plus B (one wave per row)
+__global__ __launch_bounds__(256) void near_band_scatter(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                         const cplx* __restrict__ kv, cplx* bv, int n, int B, int nd) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  for (int q = ptr[i] + (threadIdx.x & 63); q < ptr[i + 1]; q += 64) {
+    int d = col[q] - i;
+    if (d > n / 2) d -= n;
+    if (d < -n / 2) d += n;
+    const int o = d + B;
+    for (int e = 0; e < nd; ++e) bv[((size_t)o * nd + e) * n + i] = kv[(size_t)q * nd + e];
+  }
+}
+
+// Near sums of 64 consecutive rows over a band of half-width B: the block
+// stages the densities of its 64 + 2B source rows (mod n) in LDS, stored by
+// (density, column) with the rows contiguous so that the lanes (one row each)
+// read consecutive elements, and wave w accumulates CPT columns.  The values
+// are stored offset by offset, [o][d][row], so that a wave reads them as 1 KB
+// runs.  Every density element is loaded once per block instead of once per
+// entry of every row that uses it.
+constexpr int kBandRows = 64;
+
+template <int OP, class DT, int CPT>
+__global__ __launch_bounds__(512) void near_band64(NearParams p, const cplx* __restrict__ bv, int B) {
+  constexpr int ND = Nd<OP>::v;
+  constexpr int CB = 8 * CPT;  // columns of this block
+  extern __shared__ unsigned char band_smem[];
+  DT* ls = reinterpret_cast<DT*>(band_smem);  // [(d CB + c) LR + t]
+  const int n = p.n;
+  const int LR = kBandRows + 2 * B;
+  const int lane = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * kBandRows;
+  const int cb0 = blockIdx.y * CB;
+  const DT* dens = static_cast<const DT*>(p.dens);
+  // the tile, kTileBatch loads per thread in flight before their stores
+  constexpr int kTileBatch = sizeof(DT) == sizeof(cplxf) ? 12 : 6;
+  const int tot = LR * ND * CB;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 512 * kTileBatch) {
+    DT v[kTileBatch];
+    int dst[kTileBatch];
+#pragma unroll
+    for (int u = 0; u < kTileBatch; ++u) {
+      const int e = e0 + 512 * u;
+      dst[u] = -1;
+      v[u] = DT{0, 0};
+      if (e < tot) {
+        const int c = e % CB, rest = e / CB;
+        const int d = rest % ND, t = rest / ND;
+        int j = i0 - B + t;
+        j += j < 0 ? n : 0;
+        j -= j >= n ? n : 0;
+        v[u] = dens[((size_t)j * ND + d) * 64 + cb0 + c];
+        dst[u] = (d * CB + c) * LR + t;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kTileBatch; ++u)
+      if (dst[u] >= 0) ls[dst[u]] = v[u];
+  }
+  __syncthreads();
+  const int i = i0 + lane;
+  if (i >= n) return;  // no barriers below
+  cplx acc[ND][CPT];
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) acc[d][u] = {0.0, 0.0};
+  const DT* lrow = ls + cg * CPT * LR + lane;
+  // offsets in groups of kOffBatch: the group's values are requested
+  // together (the eight waves read the same ones, from the caches: staging
+  // them in LDS for the block cost two barriers per group and was slower)
+  constexpr int kOffBatch = 8;
+  for (int o0 = 0; o0 <= 2 * B; o0 += kOffBatch) {
+    cplx K[kOffBatch][ND];
+#pragma unroll
+    for (int t = 0; t < kOffBatch; ++t)
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+        K[t][d] = o0 + t <= 2 * B ? bv[((size_t)(o0 + t) * ND + d) * n + i] : cplx{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < kOffBatch; ++t) {
+      if (o0 + t <= 2 * B) {  // source row i - B + o: tile row lane + o
+        const int o = o0 + t;
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+          for (int u = 0; u < CPT; ++u) {
+            const DT v = lrow[(d * CB + u) * LR + o];
+            cfma(acc[d][u], K[t][d], cplx{(double)v.re, (double)v.im});
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) p.out[((size_t)d * 64 + cb0 + cg * CPT + u) * n + i] = acc[d][u];
+}
+
+// LDS of near_band64 for one block, bytes
+template <class DT>
+size_t band_lds(int nd, int B) {
+  const int cb = sizeof(DT) == sizeof(cplxf) ? 64 : 32;
+  return (size_t)(kBandRows + 2 * B) * nd * cb * sizeof(DT);
+}
+
+constexpr size_t kBandLdsMax = 158 * 1024;  // of the 160 KB of a CU
+
+template <int OP, class DT>
+void launch_band(const NearParams& np, const cplx* bv, int B, hipStream_t st) {
+  constexpr int ND = Nd<OP>::v;
+  constexpr int CPT = sizeof(DT) == sizeof(cplxf) ? 8 : 4;
+  const size_t lds = band_lds<DT>(ND, B);
+  (void)hipFuncSetAttribute((const void*)near_band64<OP, DT, CPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  const dim3 grid((np.n + kBandRows - 1) / kBandRows, 64 / (8 * CPT));
+  near_band64<OP, DT, CPT><<<grid, 512, lds, st>>>(np, bv, B);
+}
+
 template <class DT>
 void launch_near(int op, const NearParams& np, hipStream_t st) {
   if (np.nrp == 64) {
@@ -320,6 +469,20 @@ int near_build(dp_problem* p) {
                                              p->near_col.as<int>());
     DP_HIP(hipGetLastError());
   }
+  // band form: every near source within B rows (circularly) of its target,
+  // and B small against n (no source row reached by two offsets)
+  p->near_band = -1;
+  for (auto& b : p->near_bv_ready) b = false;
+  if (tot > 0) {
+    DP_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), st));
+    near_bandwidth<<<std::min(1024, (n + 255) / 256), 256, 0, st>>>(p->near_ptr.as<int>(), p->near_col.as<int>(), n,
+                                                                    cnt.as<int>());
+    DP_HIP(hipGetLastError());
+    int B = 0;
+    DP_HIP(hipMemcpyAsync(&B, cnt.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    DP_HIP(hipStreamSynchronize(st));
+    if (B >= 1 && (int64_t)4 * (kBandRows + 2 * B) <= n) p->near_band = B;
+  }
   DP_HIP(hipStreamSynchronize(st));
   return DP_OK;
 }
@@ -347,8 +510,33 @@ int near_apply_group(dp_problem* p, int op, int nrp, const void* dens, bool dens
     p->near_kv_ready[op] = true;
   }
   np.kv = p->near_kv[op].as<cplx>();
-  if (dens32) launch_near<cplxf>(op, np, p->ctx->stream);
-  else launch_near<cplx>(op, np, p->ctx->stream);
+  const int B = p->near_band;
+  const bool band = nrp == 64 && B > 0 &&
+                    (dens32 ? band_lds<cplxf>(nd, B) : band_lds<cplx>(nd, B)) <= kBandLdsMax;
+  if (band) {
+    hipStream_t st = p->ctx->stream;
+    if (!p->near_bv_ready[op]) {
+      const size_t tot = (size_t)(2 * B + 1) * nd * p->n;
+      DP_TRY(p->near_bv[op].reserve(tot * sizeof(cplx)));
+      zero_fill<<<(int)std::min<size_t>(8192, (tot + 255) / 256), 256, 0, st>>>(p->near_bv[op].as<cplx>(), tot);
+      near_band_scatter<<<(np.n + 3) / 4, 256, 0, st>>>(np.ptr, np.col, np.kv, p->near_bv[op].as<cplx>(), np.n, B,
+                                                       nd);
+      DP_HIP(hipGetLastError());
+      p->near_bv_ready[op] = true;
+    }
+    const cplx* bv = p->near_bv[op].as<cplx>();
+    switch (op) {
+      case OP_SOFT: dens32 ? launch_band<OP_SOFT, cplxf>(np, bv, B, st) : launch_band<OP_SOFT, cplx>(np, bv, B, st); break;
+      case OP_HARD: dens32 ? launch_band<OP_HARD, cplxf>(np, bv, B, st) : launch_band<OP_HARD, cplx>(np, bv, B, st); break;
+      case OP_S: dens32 ? launch_band<OP_S, cplxf>(np, bv, B, st) : launch_band<OP_S, cplx>(np, bv, B, st); break;
+      case OP_D: dens32 ? launch_band<OP_D, cplxf>(np, bv, B, st) : launch_band<OP_D, cplx>(np, bv, B, st); break;
+      default: dens32 ? launch_band<OP_DP, cplxf>(np, bv, B, st) : launch_band<OP_DP, cplx>(np, bv, B, st); break;
+    }
+  } else if (dens32) {
+    launch_near<cplxf>(op, np, p->ctx->stream);
+  } else {
+    launch_near<cplx>(op, np, p->ctx->stream);
+  }
   DP_HIP(hipGetLastError());
   return DP_OK;
 }

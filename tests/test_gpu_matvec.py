@@ -85,7 +85,7 @@ def test_near_field_heavy_disk(kind, omega, nrhs):
     assert relerr(to_host(y), A @ q) < TOL
 
 
-@pytest.mark.parametrize("nrhs", [2, 32])
+@pytest.mark.parametrize("nrhs", [2, 32, 64])
 def test_near_field_dense_bands_kite(nrhs):
     b = sample_boundary("kite", 2048)
     om = omega_for_ppw(2048, b.L, 40.0)
@@ -98,6 +98,27 @@ def test_near_field_dense_bands_kite(nrhs):
     y32 = empty(b.n, nrhs)
     dp.dp_matvec_mixed(p, to_dev(q), y32)
     assert relerr(to_host(y32), A @ q) < 1e-5
+
+
+# At 10 points per wavelength every near pair of an evenly sampled smooth
+# curve lies within about 25/(omega h) = 40 rows of its target: the
+# 64-column apply then stages each block's band of source densities in LDS
+# (at 40 points per wavelength, above, the band is too wide and the entry
+# list is used).  Soft and hard, FP64 and single-precision densities.
+@pytest.mark.parametrize("kind", [0, 1])
+def test_near_field_band_64_columns(kind):
+    b = sample_boundary("kite", 4096)
+    om = omega_for_ppw(4096, b.L, 10.0)
+    A = ny.cfie_matrix(b, om, om, kind)
+    q = random_density(b.n, 64, seed=19)
+    p = problem(b, om, om, kind)
+    y = empty(b.n, 64)
+    dp.dp_matvec(p, to_dev(q), y)
+    ref = A @ q
+    assert relerr(to_host(y), ref) < TOL
+    y32 = empty(b.n, 64)
+    dp.dp_matvec_mixed(p, to_dev(q), y32)
+    assert relerr(to_host(y32), ref) < 1e-5
 
 
 @pytest.mark.parametrize("op,name", [(dp.DP_OP_S, "S"), (dp.DP_OP_D, "D"), (dp.DP_OP_DP, "Dp")])
