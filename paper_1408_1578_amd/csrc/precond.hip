@@ -1107,7 +1107,7 @@ __global__ __launch_bounds__(1024) void level_solve(cplx* x, const int* __restri
 // 4, 16 or 64 lanes (chosen per level, coded in the top bits of col) works
 // through rows of a dependency level one after another, one entry per lane
 // per step, and the step that ends a row (row >= 0) writes x[row] = sum of
-// value * x[col] over the row's slots.  A row's slots
+// value * x[col] over the row's slots (lane sums by DPP moves only).  A row's slots
 // hold its own diagonal term (x[row] times 1 or 1/U_rr) and the negated,
 // scaled off-diagonal entries, so every row is a plain dot product; rows of
 // one level are independent, and a level's steps come after all steps of the
@@ -1117,16 +1117,17 @@ constexpr int kSlotAhead = 32;  // steps the slot loads run ahead (one wave per 
 
 // Value of the lane given by a DPP control: quad permutations 0xB1 (l ^ 1)
 // and 0x4E (l ^ 2), rotations within a row of 16 lanes 0x124 (by 4) and
-// 0x128 (by 8).
-template <int CTRL>
+// 0x128 (by 8), and the row broadcasts 0x142 (lane 15 of the row below, in
+// the rows of ROWS) and 0x143 (lane 31, rows of ROWS); rows outside ROWS get 0.
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ float dpp_sum(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xF, false));
 }
-template <int CTRL>
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ double dpp_sum(double v) {
   const int2 h = __builtin_bit_cast(int2, v);
-  return __builtin_bit_cast(double, int2{__builtin_amdgcn_update_dpp(0, h.x, CTRL, 0xF, 0xF, false),
-                                         __builtin_amdgcn_update_dpp(0, h.y, CTRL, 0xF, 0xF, false)});
+  return __builtin_bit_cast(double, int2{__builtin_amdgcn_update_dpp(0, h.x, CTRL, ROWS, 0xF, false),
+                                         __builtin_amdgcn_update_dpp(0, h.y, CTRL, ROWS, 0xF, false)});
 }
 
 template <class C>
@@ -1171,17 +1172,19 @@ __global__ __launch_bounds__(64) void tri_solve_wave(const C* __restrict__ z, C*
         tot.im += dpp_sum<0x124>(tot.im);
         tot.re += dpp_sum<0x128>(tot.re);
         tot.im += dpp_sum<0x128>(tot.im);
-        if (wcode > 1) {                  // 64 lanes
-          tot.re += __shfl_xor(tot.re, 16);
-          tot.im += __shfl_xor(tot.im, 16);
-          tot.re += __shfl_xor(tot.re, 32);
-          tot.im += __shfl_xor(tot.im, 32);
+        if (wcode > 1) {                  // 64 lanes: rows 1, 3 += rows 0, 2; then rows 2, 3 += row 1
+          tot.re += dpp_sum<0x142, 0xA>(tot.re);
+          tot.im += dpp_sum<0x142, 0xA>(tot.im);
+          tot.re += dpp_sum<0x143, 0xC>(tot.re);
+          tot.im += dpp_sum<0x143, 0xC>(tot.im);
         }
       }
-      const int wmask = wcode == 0 ? 3 : (wcode == 1 ? 15 : 63);
+      // the lane holding the row's total: the first of its group of 4 or 16
+      // lanes, or lane 48 (row 3) for a 64-lane row
+      const int wlane = wcode == 0 ? (lane & 3) : (wcode == 1 ? (lane & 15) : (lane == 48 ? 0 : 1));
       // branch-free: lanes that do not finish a row write the spare element xs[NW]
       const bool fin = r.row >= 0;
-      xs[fin && (lane & wmask) == 0 ? r.row : NW] = tot;
+      xs[fin && wlane == 0 ? r.row : NW] = tot;
       acc.re = fin ? 0 : acc.re;
       acc.im = fin ? 0 : acc.im;
     }
