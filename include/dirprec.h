@@ -266,7 +266,7 @@ typedef struct {
 /* Time the problem's operator sweep (nrhs columns, up to 64, in the given
  * precision: DP_PREC_FP64 or DP_PREC_MIXED) over its candidate launch
  * configurations (grid sizes; for FP64 with 5-16 columns also the VALU kernel
- * against the matrix-core kernel padded to 32 columns) and keep the fastest
+ * against the 16-column matrix-core kernel) and keep the fastest
  * for later calls on this problem with the same column count.  A
  * configuration fixes the order of the partial sums, so results are
  * reproducible once it is chosen; they may differ in the last bits from

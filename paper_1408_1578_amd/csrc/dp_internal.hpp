@@ -197,7 +197,7 @@ struct dp_problem {
   // chosen by dp_autotune; absent keys use the default rule
   struct SweepCfg {
     int target_blocks = 2048;  // blocks of the sweep grid the source chunking aims at
-    int mfma = -1;             // FP64, 8-16 columns: 0 VALU kernel, 1 matrix cores (padded to 32), -1 default
+    int mfma = -1;             // FP64, 5-16 columns: 0 VALU kernel, 1 matrix cores (16 columns split over the k steps), -1 default
   };
   std::map<int, SweepCfg> tuned;
   dp::SweepClock clock;    // FP64 sweep launches

@@ -191,14 +191,19 @@ struct Mfma64 {
 // The source record and C_k of a wave's next step are prefetched the same way.
 // Complex products take three real MFMAs: T1 += Kr Br, T2 += Ki Bi,
 // T3 += (Kr + Ki)(Br + Bi); Re = T1 - T2, Im = T3 - T1 - T2.
-template <int OP, int NCBW, class M>
+// SPLITK (16 columns): both waves of a row group take all 16 columns but only
+// the steps they evaluate themselves (no kernel values change hands), and
+// their sums are added through LDS at the end: half the products of the
+// 32-column shape padded from 16.
+template <int OP, int NCBW, class M, bool SPLITK = false>
 __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
   if (sweep_skipped(p)) return;
   using C = typename M::C;
   using V4 = typename M::V4;
   using R = decltype(C{}.re);
   constexpr int ND = Nd<OP>::v;
-  constexpr int NC = 32 * NCBW;            // columns of the block = nrp (two waves per row group)
+  static_assert(!SPLITK || NCBW == 1, "the split-k shape has one 16-column tile per wave");
+  constexpr int NC = SPLITK ? 16 : 32 * NCBW;  // columns of the block = nrp
   constexpr int TILE = 8 * ND * NC;        // density tile of a pair of steps
   constexpr int PER = (TILE + 511) / 512;  // tile elements per thread
   __shared__ C Kx[2][4][2][ND][64];        // [buffer][row group][step parity][density][lane]
@@ -210,7 +215,7 @@ __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
   const int wv = tid >> 6;
   const int rg = wv & 3;                   // row group: 16 targets
   const int ch = wv >> 2;                  // column half; also the parity of the k-steps it evaluates
-  const int c0 = ch * 16 * NCBW;
+  const int c0 = SPLITK ? 0 : ch * 16 * NCBW;
   const int li = lane & 15, lk = lane >> 4;
   const int i = blockIdx.x * 64 + rg * 16 + li;
   const int ii = i < n ? i : n - 1;
@@ -284,13 +289,14 @@ __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       K[d] = valid ? K[d] : C{0, 0};
-      Kx[buf][rg][ch][d][lane] = K[d];
+      if (!SPLITK) Kx[buf][rg][ch][d][lane] = K[d];
     }
     __syncthreads();
     // every wave has left the previous pair's products: its tile buffer is free
     if (more) store_tile(buf ^ 1, breg);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+      if (SPLITK && h != ch) continue;
       if (2 * sp + h >= nsteps) break;
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
@@ -309,6 +315,42 @@ __global__ __launch_bounds__(512) void sweep_mfma(SweepParams p) {
     sr = srn;
     Ck = Ckn;
     jc = jn;
+  }
+  if constexpr (SPLITK) {
+    // the second wave of each row group hands its complex sums
+    // (T1 - T2, T3 - T1 - T2) to the first through the (now unused) exchange
+    // buffer, [row group][d][r][re, im][lane]; the first adds them to its own
+    // sums folded the same way (kept in T1 and T3)
+    R* red = reinterpret_cast<R*>(&Kx[0][0][0][0][0]);
+    static_assert(4 * ND * 4 * 2 * 64 * sizeof(R) <= sizeof(Kx), "exchange buffer too small");
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const R t1 = T1[d][0][r], t2 = T2[d][0][r], t3 = T3[d][0][r];
+        T1[d][0][r] = t1 - t2;
+        T3[d][0][r] = t3 - t1 - t2;
+        if (ch == 1) {
+          R* o = red + ((rg * ND + d) * 4 + r) * 128 + lane;
+          o[0] = t1 - t2;
+          o[64] = t3 - t1 - t2;
+        }
+      }
+    __syncthreads();
+    if (ch == 1) return;
+    C* part = M::partial(p);
+    const int rbase = blockIdx.x * 64 + rg * 16;
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const R* o = red + ((rg * ND + d) * 4 + r) * 128 + lane;
+        const int row = rbase + M::row(r, lk);
+        if (row < n)
+          part[(((size_t)blockIdx.y * ND + d) * NC + li) * n + row] = C{T1[d][0][r] + o[0], T3[d][0][r] + o[64]};
+      }
+    return;
   }
   C* part = M::partial(p);
   const int rbase = blockIdx.x * 64 + rg * 16;
@@ -729,8 +771,12 @@ static int grid1d(size_t tot) {
 }
 
 template <int OP>
-static void launch_sweep(const SweepParams& sp, int nrp, hipStream_t st) {
+static void launch_sweep(const SweepParams& sp, int nrp, hipStream_t st, bool mfma16 = false) {
   const int n = sp.n;
+  if (mfma16) {  // 16 columns on the matrix cores, split over the k steps
+    sweep_mfma<OP, 1, Mfma64, true><<<dim3((n + 63) / 64, sp.nchunks), 512, 0, st>>>(sp);
+    return;
+  }
   if (nrp <= 4) {
     dim3 grid((n + 255) / 256, sp.nchunks);
     switch (nrp) {
@@ -804,9 +850,10 @@ static int tune_key(int prec, int op, int nrp) { return prec * 1000 + op * 100 +
 // kite at n = 32768:
 //   <= 4 columns (one target row per lane): 8192 blocks from n = 16384 on
 //     (7-20% faster than 2048), 4096 below;
-//   FP64, 5-16 columns: the matrix-core kernel padded to 32 columns on 1024
-//     blocks for hard problems and for 16 columns up to n = 32768 (8-20%
-//     faster than the VALU kernel), else the VALU kernel on 8192 blocks;
+//   FP64, 5-16 columns: the 16-column matrix-core kernel (split over the k
+//     steps) on 1024 blocks for hard problems and for 16 columns up to
+//     n = 32768, on 4096 blocks for 16 soft columns above (10-25% faster
+//     than the VALU kernel), else the VALU kernel on 8192 blocks;
 //   single precision, 5-16 columns: 1024 blocks up to n = 8192 (12%), 2048
 //     above;
 //   32-64 columns: 2048.
@@ -821,6 +868,9 @@ static dp_problem::SweepCfg default_cfg(const dp_problem* p, int prec, int op, i
     } else if ((op == OP_HARD && (nrp == 16 || n <= 32768)) || (nrp == 16 && n <= 32768)) {
       c.mfma = 1;
       c.target_blocks = 1024;
+    } else if (nrp == 16) {
+      c.mfma = 1;
+      c.target_blocks = 4096;
     } else {
       c.mfma = 0;
       c.target_blocks = 8192;
@@ -845,7 +895,8 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
   // matrix-core shape for every multi-column mixed sweep, and for FP64 sweeps
   // of 8-16 columns when the autotuner found it faster than the VALU kernel
   if (prec && nrp > 4 && nrp < 16) nrp = 16;
-  if (!prec && nrp > 4 && nrp < 32 && cfg.mfma == 1) nrp = 32;
+  const bool mfma16 = !prec && nrp > 4 && nrp <= 16 && cfg.mfma == 1;
+  if (mfma16) nrp = 16;
   const bool part32 = prec && nrp > 4;
   const int rows_per_block = nrp <= 4 ? 256 : (part32 ? 128 : 64);
   const int bx = (n + rows_per_block - 1) / rows_per_block;
@@ -914,11 +965,11 @@ static int sweep_group(dp_problem* p, int op, int nrhs, int col0, const cplx* a,
     }
   } else {
     switch (op) {
-      case OP_SOFT: launch_sweep<OP_SOFT>(sp, nrp, st); break;
-      case OP_HARD: launch_sweep<OP_HARD>(sp, nrp, st); break;
-      case OP_S: launch_sweep<OP_S>(sp, nrp, st); break;
-      case OP_D: launch_sweep<OP_D>(sp, nrp, st); break;
-      default: launch_sweep<OP_DP>(sp, nrp, st); break;
+      case OP_SOFT: launch_sweep<OP_SOFT>(sp, nrp, st, mfma16); break;
+      case OP_HARD: launch_sweep<OP_HARD>(sp, nrp, st, mfma16); break;
+      case OP_S: launch_sweep<OP_S>(sp, nrp, st, mfma16); break;
+      case OP_D: launch_sweep<OP_D>(sp, nrp, st, mfma16); break;
+      default: launch_sweep<OP_DP>(sp, nrp, st, mfma16); break;
     }
   }
   clk.stop(st);
