@@ -66,8 +66,13 @@ enum { DP_OP_S = 2, DP_OP_D = 3, DP_OP_DP = 4, DP_OP_DS = 5 };
 
 /* ------------------------------------------------------------------ context */
 /* device: HIP device ordinal.  stream: a hipStream_t to run on (e.g. the
- * caller's current stream) or NULL for a library-owned stream.  Errors:
- * DP_EINVAL (bad ordinal, out == NULL), DP_EDEVICE. */
+ * caller's current stream) or NULL for a library-owned stream.  Device
+ * blocks of 256 MB or more that the context's problems release (Krylov
+ * bases, sweep partial sums) stay with the context, up to 16 GB, and are
+ * reused by later problems on it; dp_ctx_destroy returns them to the pool.
+ * (The contexts of a dp_server keep none: its admission budget counts every
+ * request's memory.)  Errors: DP_EINVAL (bad ordinal, out == NULL),
+ * DP_EDEVICE. */
 int dp_ctx_create(int device, void* stream, dp_ctx** out);
 void dp_ctx_destroy(dp_ctx* ctx);
 const char* dp_last_error(void);

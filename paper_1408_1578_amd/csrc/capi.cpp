@@ -23,6 +23,7 @@ void set_error(const char* fmt, ...) {
 }
 
 static thread_local hipStream_t g_alloc_stream = nullptr;
+static thread_local dp_ctx* g_alloc_ctx = nullptr;
 static thread_local bool g_capturing = false;
 
 std::shared_mutex& pool_capture_mutex() {
@@ -33,8 +34,20 @@ std::shared_mutex& pool_capture_mutex() {
 CaptureScope::CaptureScope() : lk(pool_capture_mutex()) { g_capturing = true; }
 CaptureScope::~CaptureScope() { g_capturing = false; }
 
-AllocStream::AllocStream(hipStream_t s) : prev(g_alloc_stream) { g_alloc_stream = s; }
-AllocStream::~AllocStream() { g_alloc_stream = prev; }
+AllocStream::AllocStream(hipStream_t s, dp_ctx* ctx) : prev(g_alloc_stream), prev_ctx(g_alloc_ctx) {
+  g_alloc_stream = s;
+  g_alloc_ctx = ctx;
+}
+AllocStream::~AllocStream() {
+  g_alloc_stream = prev;
+  g_alloc_ctx = prev_ctx;
+}
+
+// The calling thread's context when it parks large blocks on its own stream.
+static dp_ctx* park_ctx(size_t bytes) {
+  dp_ctx* c = g_alloc_ctx;
+  return c && bytes >= dp_ctx::kParkMin && c->park_cap > 0 && c->stream == g_alloc_stream ? c : nullptr;
+}
 
 // The default memory pool of each device keeps freed memory for reuse
 // (release threshold: never), and reuses a block on another stream only once
@@ -65,6 +78,22 @@ int DevBuf::reserve(size_t want) {
     return DP_EDEVICE;
   }
   release();
+  if (dp_ctx* c = park_ctx(want)) {  // the smallest parked block that fits, up to twice the size
+    std::lock_guard<std::mutex> lk(c->park_mu);
+    size_t best = c->parked.size();
+    for (size_t i = 0; i < c->parked.size(); ++i)
+      if (c->parked[i].second >= want && c->parked[i].second <= 2 * want &&
+          (best == c->parked.size() || c->parked[i].second < c->parked[best].second))
+        best = i;
+    if (best < c->parked.size()) {
+      p = c->parked[best].first;
+      bytes = c->parked[best].second;
+      s = c->stream;
+      c->parked_bytes -= bytes;
+      c->parked.erase(c->parked.begin() + (long)best);
+      return DP_OK;
+    }
+  }
   if (want == 0) want = 8;
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) configure_pool(dev);
@@ -88,8 +117,20 @@ int DevBuf::reserve(size_t want) {
 
 void DevBuf::release() {
   if (p) {
-    std::shared_lock<std::shared_mutex> lk(pool_capture_mutex());
-    (void)hipFreeAsync(p, s);
+    dp_ctx* c = s == g_alloc_stream ? park_ctx(bytes) : nullptr;
+    bool parked = false;
+    if (c) {
+      std::lock_guard<std::mutex> lk(c->park_mu);
+      if (c->parked_bytes + bytes <= c->park_cap) {
+        c->parked.push_back({p, bytes});
+        c->parked_bytes += bytes;
+        parked = true;
+      }
+    }
+    if (!parked) {
+      std::shared_lock<std::shared_mutex> lk(pool_capture_mutex());
+      (void)hipFreeAsync(p, s);
+    }
   }
   p = nullptr;
   bytes = 0;
@@ -191,7 +232,7 @@ using namespace dp;
 
 #define DP_SETDEV(ctx)                    \
   DP_HIP(hipSetDevice((ctx)->device)); \
-  AllocStream alloc_stream_guard_((ctx)->stream)
+  AllocStream alloc_stream_guard_((ctx)->stream, (ctx))
 
 extern "C" {
 
@@ -229,6 +270,8 @@ int dp_ctx_create(int device, void* stream, dp_ctx** out) {
 void dp_ctx_destroy(dp_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  for (auto& b : c->parked) (void)hipFreeAsync(b.first, c->stream);
+  c->parked.clear();
   (void)hipStreamSynchronize(c->stream);
   for (auto& b : c->pin_free) (void)hipHostFree(b.first);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -313,7 +356,7 @@ int dp_problem_create(dp_ctx* ctx, int64_t n, const double* xy, const double* nr
 void dp_problem_destroy(dp_problem* p) {
   if (!p) return;
   (void)hipSetDevice(p->ctx->device);
-  AllocStream alloc_stream_guard_(p->ctx->stream);
+  AllocStream alloc_stream_guard_(p->ctx->stream, p->ctx);
   // the releases below are ordered on the stream after the problem's work:
   // no wait for the device here
   if (p->pc) precond_destroy(p->pc);

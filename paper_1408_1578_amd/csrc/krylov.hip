@@ -323,6 +323,19 @@ static int g1(size_t tot) {
   return (int)(g > 8192 ? 8192 : (g ? g : 1));
 }
 
+__global__ void copy16(const uint4* __restrict__ a, uint4* __restrict__ b, size_t tot) {
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot; q += (size_t)gridDim.x * blockDim.x)
+    b[q] = a[q];
+}
+
+int dev_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return DP_OK;
+  const size_t tot = bytes / 16;
+  copy16<<<g1(tot), 256, 0, st>>>(static_cast<const uint4*>(src), static_cast<uint4*>(dst), tot);
+  DP_HIP(hipGetLastError());
+  return DP_OK;
+}
+
 // ------------------------------------------------ rotation state of a cycle
 // Device state of the per-column least-squares problems.  The first part
 // (the cycle block: residual estimates, scales, norms and flags) is uploaded
@@ -656,7 +669,7 @@ static int gmres_core(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_
   std::vector<double> fn, beta;
   DP_TRY(norms(p, F, nrhs, part, fn));
   DP_HIP(hipMemsetAsync(X, 0, blk * sizeof(cplx), st));
-  DP_HIP(hipMemcpyAsync(Rp, F, blk * sizeof(cplx), hipMemcpyDeviceToDevice, st));
+  DP_TRY(dev_copy(Rp, F, blk * sizeof(cplx), st));
   beta = fn;
   std::vector<char> done(nrhs, 0);
   std::vector<int64_t> its(nrhs, 0);
@@ -900,7 +913,7 @@ int solve(dp_problem* p, int nrhs, const cplx* F, cplx* X, const dp_solve_opts* 
   std::vector<double> fn, rn;
   DP_TRY(norms(p, F, nrhs, part, fn));
   DP_HIP(hipMemsetAsync(X, 0, blk * sizeof(cplx), st));
-  DP_HIP(hipMemcpyAsync(R.p, F, blk * sizeof(cplx), hipMemcpyDeviceToDevice, st));
+  DP_TRY(dev_copy(R.p, F, blk * sizeof(cplx), st));
   std::vector<int64_t> its(nrhs, 0), its_in(nrhs);
   std::vector<double> rel(nrhs, 1.0), rel_in(nrhs), kv(nrhs);
   for (int c = 0; c < nrhs; ++c) rel[c] = fn[c] > 0 ? 1.0 : 0.0;

@@ -1962,9 +1962,9 @@ int precond_apply(dp_problem* p, int nrhs, const cplx* v, cplx* q, int prec) {
     else gsig = sig();
   }
   if (!gx) return eager();
-  DP_HIP(hipMemcpyAsync(P->win.p, v, bn, hipMemcpyDeviceToDevice, st));
+  DP_TRY(dev_copy(P->win.p, v, bn, st));
   DP_HIP(hipGraphLaunch(gx, st));
-  DP_HIP(hipMemcpyAsync(q, P->wq.p, bn, hipMemcpyDeviceToDevice, st));
+  DP_TRY(dev_copy(q, P->wq.p, bn, st));
   return DP_OK;
 }
 

@@ -165,6 +165,9 @@ void worker_main(dp_server* s, int slot) {
   (void)hipSetDevice(s->device);
   dp_ctx* ctx = nullptr;
   const int crc = dp_ctx_create(s->device, nullptr, &ctx);
+  // the admission budget counts every request's blocks: nothing stays parked
+  // with the slot's context between requests
+  if (crc == DP_OK) ctx->park_cap = 0;
   const std::string cerr = crc == DP_OK ? "" : dp_last_error();
   for (;;) {
     std::shared_ptr<Request> r;
