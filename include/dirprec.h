@@ -220,7 +220,8 @@ typedef struct {
                        and whose residuals f - A q are FP64 */
   double inner_tol; /* mixed: relative tolerance of the correction solves, at least the one
                        that takes every column from its current FP64 residual r to
-                       0.3 tol (0.3 tol/r for the worst column); default 1e-5 */
+                       0.3 tol (0.3 tol/r for the worst column); <= 0: sqrt(tol)
+                       within [1e-5, 1e-2] (two corrections share the reduction) */
   int eager;        /* 1: launch the kernels of each Arnoldi step's orthogonalisation
                        and rotation update one by one instead of replaying their
                        captured HIP graph (the same kernels and results); default 0 */

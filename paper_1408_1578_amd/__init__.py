@@ -342,7 +342,7 @@ def dp_precond_export(p):
 
 
 def dp_solve(p, f, q, tol=1e-8, restart=80, max_iters=2000, use_precond=False, precision=DP_PREC_FP64,
-             inner_tol=1e-5, eager=False):
+             inner_tol=0.0, eager=False):
     nr = _cols(f, p.n)
     if _cols(q, p.n) != nr:
         raise ValueError("shape mismatch")
@@ -390,7 +390,7 @@ class Server:
         self._n = {}
 
     def submit(self, b, omega, eta, kind, angles=None, f=None, tol=1e-8, restart=80, max_iters=2000,
-               use_precond=True, precision=DP_PREC_FP64, inner_tol=1e-5):
+               use_precond=True, precision=DP_PREC_FP64, inner_tol=0.0):
         """b: boundary with x (n, 2), nu (n, 2), w (n,), kappa (n,) or None.  angles: plane-wave angles, or
         f: (n, nrhs) complex data.  Returns the request id."""
         xy, xyp = _host(b.x)

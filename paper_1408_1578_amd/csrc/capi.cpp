@@ -526,9 +526,9 @@ int dp_precond_export(dp_problem* p, int64_t* seg_off, int64_t* seg_len, int64_t
 int dp_solve(dp_problem* p, int64_t nrhs, const double* f, double* q, const dp_solve_opts* opts,
              dp_solve_info* info, int64_t* iters, double* relres) {
   DP_CHECK(p && f && q && nrhs >= 1, "dp_solve: bad argument");
-  dp_solve_opts o = {1e-8, 80, 2000, 0, DP_PREC_FP64, 1e-5, 0};
+  dp_solve_opts o = {1e-8, 80, 2000, 0, DP_PREC_FP64, 0.0, 0};
   if (opts) o = *opts;
-  if (o.inner_tol <= 0) o.inner_tol = 1e-5;
+  if (o.inner_tol <= 0) o.inner_tol = default_inner_tol(o.tol);
   DP_CHECK(o.tol > 0 && o.restart >= 1 && o.restart <= 1000 && o.max_iters >= 1, "dp_solve: bad options");
   DP_CHECK(o.precision == DP_PREC_FP64 || o.precision == DP_PREC_MIXED, "dp_solve: precision %d", o.precision);
   if (o.use_precond && !p->pc) {

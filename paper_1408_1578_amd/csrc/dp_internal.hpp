@@ -260,11 +260,17 @@ int solve(dp_problem* p, int nrhs, const cplx* f, cplx* q, const dp_solve_opts* 
           int64_t* iters, double* relres);
 // the executable graphs of the Arnoldi steps (problem teardown)
 void krylov_graphs_destroy(dp_problem* p);
-// Device-to-device copy of `bytes` (a multiple of 16) by a kernel on st.  The
-// library's own buffers are never the source or target of the runtime's copy
-// path: releasing a 2.5 GB block that a hipMemcpyAsync had written took 8 ms
-// of host time, against 0.02 ms for one written only by kernels.
+// Device-to-device copy of `bytes` (a multiple of 16) by a kernel on st
+// (16-byte loads and stores, a grid-stride loop).
 int dev_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+// Default relative tolerance of the FP32 correction solves of a mixed solve to
+// `tol`: sqrt(tol), so that two corrections share the reduction evenly (the
+// second asks for 0.3 tol over the FP64 residual the first left), kept within
+// [1e-5, 1e-2]: below 1e-5 a correction stops gaining in FP64 terms.
+inline double default_inner_tol(double tol) {
+  const double t = __builtin_sqrt(tol);
+  return t < 1e-5 ? 1e-5 : (t > 1e-2 ? 1e-2 : t);
+}
 // precond
 int precond_build(dp_problem* p, const dp_precond_opts* o);
 // prec 1: single-precision tables and vectors (FP64 in and out)

@@ -283,7 +283,7 @@ int dp_server_submit(dp_server* s, const dp_request* rq, int64_t* id) {
   if (r->opts.tol <= 0) r->opts.tol = 1e-8;
   if (r->opts.restart <= 0) r->opts.restart = 80;
   if (r->opts.max_iters <= 0) r->opts.max_iters = 2000;
-  if (r->opts.inner_tol <= 0) r->opts.inner_tol = 1e-5;
+  if (r->opts.inner_tol <= 0) r->opts.inner_tol = dp::default_inner_tol(r->opts.tol);
   r->mem = estimate_bytes(*r);
   std::lock_guard<std::mutex> lk(s->mu);
   if (r->mem > s->budget) {
