@@ -1104,7 +1104,7 @@ __global__ __launch_bounds__(1024) void level_solve(cplx* x, const int* __restri
 // gather zp[k] = z[perm_in[k]], forward solve with L (unit diagonal),
 // backward solve with U, scatter u[perm_out[b]] = u'[b].  Both solves are
 // one stream of steps of 64 slot records (col, row, value): a lane group of
-// 4, 16 or 64 lanes (chosen per level, coded in the top bits of col) works
+// 1, 4, 16 or 64 lanes (chosen per level, coded in the top bits of col) works
 // through rows of a dependency level one after another, one entry per lane
 // per step, and the step that ends a row (row >= 0) writes x[row] = sum of
 // value * x[col] over the row's slots (lane sums by DPP moves only).  A row's slots
@@ -1113,7 +1113,15 @@ __global__ __launch_bounds__(1024) void level_solve(cplx* x, const int* __restri
 // one level are independent, and a level's steps come after all steps of the
 // levels it depends on.  One wave executes its LDS accesses in program order,
 // so no barrier is needed, and the slot loads run 32 steps ahead.
+// Steps go in batches of kTriBatch that never span two levels (each level's
+// steps are padded to a multiple of the batch with empty steps of its lane
+// width): no step of a batch reads an element another step of it writes, so
+// the batch's LDS reads are issued together, then its accumulations, its
+// lane sums (independent chains, one width for the batch) and its writes.
+// (Skipping the sums of batches in which no row ends cost more than it saved.)
 constexpr int kSlotAhead = 32;  // steps the slot loads run ahead (one wave per CU: registers to spare)
+constexpr int kTriBatch = 4;    // steps per batch (divides kSlotAhead)
+static_assert(kSlotAhead % kTriBatch == 0, "batches must tile the prefetch round");
 
 // Value of the lane given by a DPP control: quad permutations 0xB1 (l ^ 1)
 // and 0x4E (l ^ 2), rotations within a row of 16 lanes 0x124 (by 4) and
@@ -1152,41 +1160,78 @@ __global__ __launch_bounds__(64) void tri_solve_wave(const C* __restrict__ z, C*
 #pragma unroll
   for (int q = 0; q < D; ++q) ring[q] = slots[(size_t)q * 64 + lane];
   C acc = {0, 0};
+  // the lane holding a row's total: the lane itself for one lane per row,
+  // the first of its group of 4 or 16 lanes, or lane 48 (row 3) for a
+  // 64-lane row
+  const bool head4 = (lane & 3) == 0, head16 = (lane & 15) == 0, head64 = lane == 48;
   for (int s0 = 0; s0 < nsteps; s0 += D) {
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-      const Slot<C> r = ring[q];
-      ring[q] = slots[(size_t)(s0 + q + D) * 64 + lane];
-      const C xv = xs[r.col & 0x3fffffff];
-      acc.re = fma(r.re, xv.re, fma(-r.im, xv.im, acc.re));
-      acc.im = fma(r.re, xv.im, fma(r.im, xv.re, acc.im));
-      // the step's lanes per row (4, 16 or 64) are in bits 30..31 of col
-      const int wcode = __builtin_amdgcn_readfirstlane((int)((unsigned)r.col >> 30));
-      C tot = acc;
-      tot.re += dpp_sum<0xB1>(tot.re);  // lanes 4g + (l ^ 1)
-      tot.im += dpp_sum<0xB1>(tot.im);
-      tot.re += dpp_sum<0x4E>(tot.re);  // lanes 4g + (l ^ 2)
-      tot.im += dpp_sum<0x4E>(tot.im);
-      if (wcode) {                        // 16 lanes: rotations by 4 and 8 within the row
-        tot.re += dpp_sum<0x124>(tot.re);
-        tot.im += dpp_sum<0x124>(tot.im);
-        tot.re += dpp_sum<0x128>(tot.re);
-        tot.im += dpp_sum<0x128>(tot.im);
-        if (wcode > 1) {                  // 64 lanes: rows 1, 3 += rows 0, 2; then rows 2, 3 += row 1
-          tot.re += dpp_sum<0x142, 0xA>(tot.re);
-          tot.im += dpp_sum<0x142, 0xA>(tot.im);
-          tot.re += dpp_sum<0x143, 0xC>(tot.re);
-          tot.im += dpp_sum<0x143, 0xC>(tot.im);
+    for (int q0 = 0; q0 < D; q0 += kTriBatch) {
+      constexpr int B = kTriBatch;
+      Slot<C> r[B];
+      C xv[B], tot[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) r[b] = ring[q0 + b];
+#pragma unroll
+      for (int b = 0; b < B; ++b) xv[b] = xs[r[b].col & 0x3fffffff];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        acc.re = fma(r[b].re, xv[b].re, fma(-r[b].im, xv[b].im, acc.re));
+        acc.im = fma(r[b].re, xv[b].im, fma(r[b].im, xv[b].re, acc.im));
+        tot[b] = acc;
+        const bool fin = r[b].row >= 0;
+        acc.re = fin ? 0 : acc.re;
+        acc.im = fin ? 0 : acc.im;
+      }
+      // lane sums and writes only for a batch in which some row ends (the
+      // steps of a long row before its last one just accumulate)
+      // the batch's lanes per row (1, 4, 16 or 64) are in bits 30..31 of col
+      const int wcode = __builtin_amdgcn_readfirstlane((int)((unsigned)r[0].col >> 30));
+      if (wcode) {  // 4 lanes: quad permutations
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          tot[b].re += dpp_sum<0xB1>(tot[b].re);  // lanes 4g + (l ^ 1)
+          tot[b].im += dpp_sum<0xB1>(tot[b].im);
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          tot[b].re += dpp_sum<0x4E>(tot[b].re);  // lanes 4g + (l ^ 2)
+          tot[b].im += dpp_sum<0x4E>(tot[b].im);
+        }
+        if (wcode > 1) {  // 16 lanes: rotations by 4 and 8 within the row
+#pragma unroll
+          for (int b = 0; b < B; ++b) {
+            tot[b].re += dpp_sum<0x124>(tot[b].re);
+            tot[b].im += dpp_sum<0x124>(tot[b].im);
+          }
+#pragma unroll
+          for (int b = 0; b < B; ++b) {
+            tot[b].re += dpp_sum<0x128>(tot[b].re);
+            tot[b].im += dpp_sum<0x128>(tot[b].im);
+          }
+          if (wcode > 2) {  // 64 lanes: rows 1, 3 += rows 0, 2; then rows 2, 3 += row 1
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+              tot[b].re += dpp_sum<0x142, 0xA>(tot[b].re);
+              tot[b].im += dpp_sum<0x142, 0xA>(tot[b].im);
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+              tot[b].re += dpp_sum<0x143, 0xC>(tot[b].re);
+              tot[b].im += dpp_sum<0x143, 0xC>(tot[b].im);
+            }
+          }
         }
       }
-      // the lane holding the row's total: the first of its group of 4 or 16
-      // lanes, or lane 48 (row 3) for a 64-lane row
-      const int wlane = wcode == 0 ? (lane & 3) : (wcode == 1 ? (lane & 15) : (lane == 48 ? 0 : 1));
+      const bool head = wcode == 0 ? true : (wcode == 1 ? head4 : (wcode == 2 ? head16 : head64));
       // branch-free: lanes that do not finish a row write the spare element xs[NW]
-      const bool fin = r.row >= 0;
-      xs[fin && wlane == 0 ? r.row : NW] = tot;
-      acc.re = fin ? 0 : acc.re;
-      acc.im = fin ? 0 : acc.im;
+#pragma unroll
+      for (int b = 0; b < B; ++b) xs[r[b].row >= 0 && head ? r[b].row : NW] = tot[b];
+      // the ring entries are reloaded after their last use, so that each
+      // load can write the registers it replaces (no copies, and no wait for
+      // the newest loads, at the end of a round)
+#pragma unroll
+      for (int b = 0; b < B; ++b) ring[q0 + b] = slots[(size_t)(s0 + q0 + b + D) * 64 + lane];
     }
   }
 #pragma unroll 32
@@ -1195,9 +1240,10 @@ __global__ __launch_bounds__(64) void tri_solve_wave(const C* __restrict__ z, C*
 
 // Step stream of the forward (L) then backward (U) solve: within each level,
 // rows sorted by slot count are dealt longest first to the least-loaded lane
-// group, with 4, 16 or 64 lanes per row, whichever takes the fewest steps
-// (long rows alone in a level use the whole wave); padding slots have column
-// 0, value 0 and row -1.
+// group, with 1, 4, 16 or 64 lanes per row, whichever takes the fewest steps
+// (long rows alone in a level use the whole wave); each level's steps are
+// padded to whole batches of kTriBatch.  Padding slots have column 0 (with the
+// level's width code), value 0 and row -1.
 template <class C>
 static int build_slots(const SparseLU& lu, std::vector<Slot<C>>& out) {
   using R = decltype(C{}.re);
@@ -1222,10 +1268,11 @@ static int build_slots(const SparseLU& lu, std::vector<Slot<C>>& out) {
       std::sort(rows.begin(), rows.end(), [](const auto& a, const auto& b) {
         return a.first != b.first ? a.first > b.first : a.second < b.second;
       });
-      // lanes per row W in {4, 16, 64}: the one with the fewest steps
-      int best_w = 4, best_st = INT32_MAX;
+      // lanes per row W in {1, 4, 16, 64}: the one with the fewest steps
+      // once they are padded to whole batches
+      int best_w = 1, best_st = INT32_MAX;
       std::vector<std::vector<int>> best_grp;
-      for (int W : {4, 16, 64}) {
+      for (int W : {1, 4, 16, 64}) {
         const int ng = 64 / W;
         std::vector<std::vector<int>> grp(ng);
         std::vector<int> load(ng, 0);
@@ -1234,7 +1281,7 @@ static int build_slots(const SparseLU& lu, std::vector<Slot<C>>& out) {
           grp[g].push_back(r);
           load[g] += (cnt + W - 1) / W;
         }
-        const int nst = *std::max_element(load.begin(), load.end());
+        const int nst = (*std::max_element(load.begin(), load.end()) + kTriBatch - 1) / kTriBatch * kTriBatch;
         if (nst < best_st) {
           best_st = nst;
           best_w = W;
@@ -1242,7 +1289,7 @@ static int build_slots(const SparseLU& lu, std::vector<Slot<C>>& out) {
         }
       }
       const int W = best_w, nst = best_st;
-      const int wcode = W == 4 ? 0 : (W == 16 ? 1 : 2);
+      const int wcode = W == 1 ? 0 : (W == 4 ? 1 : (W == 16 ? 2 : 3));
       const size_t base = out.size();
       out.resize(base + (size_t)nst * 64, Slot<C>{wcode << 30, -1, 0, 0});
       for (int g = 0; g < 64 / W; ++g) {
