@@ -117,7 +117,10 @@ __global__ __launch_bounds__(256) void panel_pivot(cplx* A, int n, int k0, int k
 
 // Column c of the panel below the diagonal: l = a/pivot, and the rank-1
 // update of the panel's later columns; partials of the next column's pivot
-// search over the updated rows (when want_next).
+// search over the updated rows (when want_next).  A thread takes its row's
+// later columns 16 at a time, all loads before the stores: one column after
+// another, each load waited for the previous column's store (A may alias).
+constexpr int kUpdChunk = 16;
 __global__ __launch_bounds__(256) void panel_update(cplx* A, int n, int k0, int kb, int c, const cplx* inv_p,
                                                     double* pv, int* pi, int want_next) {
   __shared__ cplx prow[kNB];
@@ -133,13 +136,23 @@ __global__ __launch_bounds__(256) void panel_update(cplx* A, int n, int k0, int 
     const cplx a = A[(size_t)c * n + r];
     const cplx l = cmul(a, inv);
     A[(size_t)c * n + r] = l;
-    for (int jj = j + 1; jj < kb; ++jj) {
-      cplx& x = A[(size_t)(k0 + jj) * n + r];
-      const cplx u = prow[jj];
-      x = {x.re - (l.re * u.re - l.im * u.im), x.im - (l.re * u.im + l.im * u.re)};
+    cplx next = {0.0, 0.0};  // the updated entry of column c + 1
+    for (int j0 = j + 1; j0 < kb; j0 += kUpdChunk) {
+      cplx x[kUpdChunk];
+#pragma unroll
+      for (int u = 0; u < kUpdChunk; ++u)
+        if (j0 + u < kb) x[u] = A[(size_t)(k0 + j0 + u) * n + r];
+#pragma unroll
+      for (int u = 0; u < kUpdChunk; ++u)
+        if (j0 + u < kb) {
+          const cplx w = prow[j0 + u];
+          x[u] = {x[u].re - (l.re * w.re - l.im * w.im), x[u].im - (l.re * w.im + l.im * w.re)};
+          A[(size_t)(k0 + j0 + u) * n + r] = x[u];
+        }
+      if (j0 == j + 1) next = x[0];
     }
     if (want_next) {
-      const double v = cabs2(A[(size_t)(c + 1) * n + r]);
+      const double v = cabs2(next);
       if (better(v, r, bv, bi)) {
         bv = v;
         bi = r;
