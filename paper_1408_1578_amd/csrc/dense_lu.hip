@@ -9,9 +9,13 @@
 // here instead, as dense complex matrices (N_W <= ~40000, 16 N_W^2 bytes of
 // HBM), by the right-looking blocked algorithm with 64-column panels:
 //   1. panel: for each column, pivot search (largest modulus, ties to the
-//      lower row index; deterministic two-stage reduction), row swap within
-//      the panel, scaling, and rank-1 update of the panel's later columns;
-//   2. the panel's row swaps applied to the other columns;
+//      lower row index; deterministic two-stage reduction), scaling, and
+//      rank-1 update of the panel's later columns, in one launch per column;
+//      the pivot rows stay where they are until the panel ends (rows chosen
+//      so far are marked and left out), which is the same elimination with
+//      the row swaps deferred;
+//   2. the panel's row swaps (LAPACK's sequence, derived from the chosen
+//      rows) applied to every column;
 //   3. U12 = L11^{-1} A12 (one wave per column, L11 in LDS);
 //   4. A22 -= L21 U12 on the FP64 matrix cores (v_mfma_f64_16x16x4, complex
 //      products in the 3-multiplication form).
@@ -81,106 +85,128 @@ __global__ __launch_bounds__(256) void col_amax(const cplx* __restrict__ A, int 
   }
 }
 
-// Pivot of column c (one block): reduce the partials, swap rows c and p in the
-// panel's columns k0..k0+kb-1, record ipiv[c] = p and 1/A[c, c].  A zero (or
-// non-finite) pivot column sets *info = c + 1 once and continues with 1/0 = 0.
-__global__ __launch_bounds__(256) void panel_pivot(cplx* A, int n, int k0, int kb, int c, const double* pv,
-                                                   const int* pi, int nparts, int* ipiv, cplx* inv, int* info) {
-  __shared__ double sv[256];
-  __shared__ int si[256];
-  double bv = -1.0;
-  int bi = INT_MAX;
-  for (int q = threadIdx.x; q < nparts; q += 256)
-    if (better(pv[q], pi[q], bv, bi)) {
-      bv = pv[q];
-      bi = pi[q];
-    }
-  sv[threadIdx.x] = bv;
-  si[threadIdx.x] = bi;
-  __syncthreads();
-  reduce_best(sv, si);
-  const bool bad = !(sv[0] > 0.0) || !(sv[0] < 1e300) || si[0] < c || si[0] >= n;
-  const int p = bad ? c : si[0];
-  if (threadIdx.x == 0) {
-    ipiv[c] = p;
-    if (bad && *info == 0) *info = c + 1;
-  }
-  if (p != c && threadIdx.x < kb) {
-    const size_t col = (size_t)(k0 + threadIdx.x) * n;
-    const cplx a = A[col + c], b = A[col + p];
-    A[col + c] = b;
-    A[col + p] = a;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) *inv = crecip(A[(size_t)c * n + c]);
-}
-
-// Column c of the panel below the diagonal: l = a/pivot, and the rank-1
-// update of the panel's later columns; partials of the next column's pivot
-// search over the updated rows (when want_next).  A thread takes its row's
-// later columns 16 at a time, all loads before the stores: one column after
-// another, each load waited for the previous column's store (A may alias).
-constexpr int kUpdChunk = 16;
-__global__ __launch_bounds__(256) void panel_update(cplx* A, int n, int k0, int kb, int c, const cplx* inv_p,
-                                                    double* pv, int* pi, int want_next) {
+// Column c = k0 + j of the panel, in one launch.  Every block reduces the
+// partials of column c (the same pivot row p in each: the largest modulus
+// among the rows not yet chosen in this panel, ties to the lower row index),
+// reads row p's panel entries, and updates its 64 rows among those not yet
+// chosen: l = a/pivot in column c and the rank-1 update of the panel's later
+// columns.  Wave w takes the later columns j + 1 + 16 w .. j + 16 (w + 1) of
+// the block's rows, one row per lane, with every load before any store (one
+// round trip; the matrix may alias, so loads after a store would wait for
+// it); wave 0 also writes l and the partial of column c + 1 over its rows
+// (when want_next) into the other partial buffer.  Row p is not moved:
+// block 0 marks it (mark[p] = c; rows whose mark is below k0 are not chosen
+// in this panel) and records it in plist[j].  A zero or non-finite pivot
+// sets *info = c + 1 once and continues with 1/0 = 0.
+constexpr int kUpdChunk = 16;  // later columns per wave (4 waves cover the 63 of a panel)
+__global__ __launch_bounds__(256) void panel_col(cplx* A, int n, int k0, int kb, int c, const double* pv_in,
+                                                 const int* pi_in, int nparts, double* pv_out, int* pi_out,
+                                                 int* mark, int* plist, int* info, int want_next) {
   __shared__ cplx prow[kNB];
   __shared__ double sv[256];
   __shared__ int si[256];
+  __shared__ int sp;
   const int j = c - k0;
-  if (threadIdx.x < kb) prow[threadIdx.x] = A[(size_t)(k0 + threadIdx.x) * n + c];
-  __syncthreads();
-  const cplx inv = *inv_p;
+  const int tid = threadIdx.x;
   double bv = -1.0;
   int bi = INT_MAX;
-  for (int r = c + 1 + blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
-    const cplx a = A[(size_t)c * n + r];
-    const cplx l = cmul(a, inv);
-    A[(size_t)c * n + r] = l;
-    cplx next = {0.0, 0.0};  // the updated entry of column c + 1
-    for (int j0 = j + 1; j0 < kb; j0 += kUpdChunk) {
-      cplx x[kUpdChunk];
-#pragma unroll
-      for (int u = 0; u < kUpdChunk; ++u)
-        if (j0 + u < kb) x[u] = A[(size_t)(k0 + j0 + u) * n + r];
-#pragma unroll
-      for (int u = 0; u < kUpdChunk; ++u)
-        if (j0 + u < kb) {
-          const cplx w = prow[j0 + u];
-          x[u] = {x[u].re - (l.re * w.re - l.im * w.im), x[u].im - (l.re * w.im + l.im * w.re)};
-          A[(size_t)(k0 + j0 + u) * n + r] = x[u];
-        }
-      if (j0 == j + 1) next = x[0];
+  for (int q = tid; q < nparts; q += 256)
+    if (better(pv_in[q], pi_in[q], bv, bi)) {
+      bv = pv_in[q];
+      bi = pi_in[q];
     }
-    if (want_next) {
-      const double v = cabs2(next);
-      if (better(v, r, bv, bi)) {
-        bv = v;
-        bi = r;
+  sv[tid] = bv;
+  si[tid] = bi;
+  __syncthreads();
+  reduce_best(sv, si);
+  const bool inrange = si[0] >= k0 && si[0] < n;
+  const bool bad = !(sv[0] > 0.0) || !(sv[0] < 1e300) || !inrange;
+  if (tid == 0) {
+    int p = si[0];
+    if (!inrange) {  // no finite candidate: the first row not yet chosen (one exists: n - c >= 1)
+      p = k0;
+      while (p < n - 1 && mark[p] >= k0) ++p;
+    }
+    sp = p;
+  }
+  __syncthreads();
+  const int p = sp;
+  if (tid < kb) prow[tid] = A[(size_t)(k0 + tid) * n + p];
+  __syncthreads();
+  const cplx inv = crecip(prow[j]);
+  const int lane = tid & 63, w = tid >> 6;
+  const int j0 = j + 1 + kUpdChunk * w;  // this wave's first later column
+  double nb = -1.0;
+  int ni = INT_MAX;
+  const int r0 = (w == 0 || j0 < kb) ? k0 + blockIdx.x * 64 + lane : n;  // waves without columns skip
+  for (int r = r0; r < n; r += gridDim.x * 64) {
+    if (r == p || mark[r] >= k0) continue;
+    const cplx a = A[(size_t)c * n + r];
+    cplx x[kUpdChunk];
+#pragma unroll
+    for (int u = 0; u < kUpdChunk; ++u)
+      if (j0 + u < kb) x[u] = A[(size_t)(k0 + j0 + u) * n + r];
+    const cplx l = cmul(a, inv);
+    if (w == 0) A[(size_t)c * n + r] = l;
+#pragma unroll
+    for (int u = 0; u < kUpdChunk; ++u)
+      if (j0 + u < kb) {
+        const cplx v = prow[j0 + u];
+        x[u] = {x[u].re - (l.re * v.re - l.im * v.im), x[u].im - (l.re * v.im + l.im * v.re)};
+        A[(size_t)(k0 + j0 + u) * n + r] = x[u];
+      }
+    if (w == 0 && want_next) {  // column c + 1 is this wave's first
+      const double v = cabs2(x[0]);
+      if (better(v, r, nb, ni)) {
+        nb = v;
+        ni = r;
       }
     }
   }
-  sv[threadIdx.x] = bv;
-  si[threadIdx.x] = bi;
+  __syncthreads();  // every thread is past its reads of the first reduction
+  sv[tid] = nb;
+  si[tid] = ni;
   __syncthreads();
   reduce_best(sv, si);
-  if (threadIdx.x == 0) {
-    pv[blockIdx.x] = sv[0];
-    pi[blockIdx.x] = si[0];
+  if (tid == 0) {
+    pv_out[blockIdx.x] = sv[0];
+    pi_out[blockIdx.x] = si[0];
+    if (blockIdx.x == 0) {
+      mark[p] = c;
+      plist[j] = p;
+      if (bad && *info == 0) *info = c + 1;
+    }
   }
 }
 
-// the panel's swaps (rows c <-> ipiv[c], c = k0..k0+kb-1, in order) on every
-// column outside the panel; one thread per column
-__global__ __launch_bounds__(256) void laswp(cplx* A, int n, int k0, int kb, const int* __restrict__ ipiv) {
-  const int ncol = n - kb;
-  for (int t = blockIdx.x * 256 + threadIdx.x; t < ncol; t += gridDim.x * 256) {
-    const size_t col = (size_t)(t < k0 ? t : t + kb) * n;
-    for (int c = k0; c < k0 + kb; ++c) {
-      const int p = ipiv[c];
-      if (p != c) {
-        const cplx a = A[col + c], b = A[col + p];
+// The panel's row swaps on every column (one thread per column).  LAPACK's
+// sequence swaps row c = k0 + j with the row that holds plist[j] at step j,
+// q_j = ipiv[c]: the chosen row is still at its own index unless that index
+// is a position k0 + i filled at an earlier step i < j, which sent its row to
+// q_i (so follow q_i, which lies beyond k0 + i, until it is not such a
+// position).  Each block derives the sequence (thread 0, in LDS); block 0
+// stores it in ipiv.
+__global__ __launch_bounds__(256) void laswp(cplx* A, int n, int k0, int kb, const int* __restrict__ plist,
+                                             int* ipiv) {
+  __shared__ int q[kNB];
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < kb; ++j) {
+      int pos = plist[j];
+      // each hop goes to a later step, so at most j hops
+      for (int h = 0; h < j && pos >= k0 && pos < k0 + j; ++h) pos = q[pos - k0];
+      q[j] = pos;
+    }
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < kb) ipiv[k0 + threadIdx.x] = q[threadIdx.x];
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < n; t += gridDim.x * 256) {
+    const size_t col = (size_t)t * n;
+    for (int j = 0; j < kb; ++j) {
+      const int c = k0 + j, pr = q[j];
+      if (pr != c) {
+        const cplx a = A[col + c], b = A[col + pr];
         A[col + c] = b;
-        A[col + p] = a;
+        A[col + pr] = a;
       }
     }
   }
@@ -512,25 +538,27 @@ int DenseLU::assemble(hipStream_t st, int n_, const std::vector<int>& rows, cons
 int DenseLU::factor(hipStream_t st) {
   cplx* A = a.as<cplx>();
   DP_TRY(ipiv.reserve((size_t)n * sizeof(int)));
-  DP_TRY(work.reserve(kParts * (sizeof(double) + sizeof(int)) + 64));
-  double* pv = work.as<double>();
-  int* pi = reinterpret_cast<int*>(pv + kParts);
-  cplx* inv = reinterpret_cast<cplx*>(pi + kParts);
-  int* info = reinterpret_cast<int*>(inv + 1);
+  // two partial buffers (kParts doubles, kParts ints each), the singularity
+  // flag, the panel's chosen rows and the row marks
+  const size_t wbytes = 2 * kParts * (sizeof(double) + sizeof(int)) + (1 + kNB + (size_t)n) * sizeof(int);
+  DP_TRY(work.reserve(wbytes));
+  double* pvb[2] = {work.as<double>(), work.as<double>() + kParts};
+  int* pib[2] = {reinterpret_cast<int*>(pvb[1] + kParts), reinterpret_cast<int*>(pvb[1] + kParts) + kParts};
+  int* info = pib[1] + kParts;
+  int* plist = info + 1;
+  int* mark = plist + kNB;
   DP_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
+  DP_HIP(hipMemsetAsync(mark, 0xFF, (size_t)n * sizeof(int), st));  // -1: never chosen
   int* ip = ipiv.as<int>();
   for (int k0 = 0; k0 < n; k0 += kNB) {
     const int kb = std::min(kNB, n - k0);
-    int parts = nblocks(n - k0, kParts);
-    col_amax<<<parts, 256, 0, st>>>(A, n, k0, pv, pi);
-    for (int j = 0; j < kb; ++j) {
-      const int c = k0 + j;
-      panel_pivot<<<1, 256, 0, st>>>(A, n, k0, kb, c, pv, pi, parts, ip, inv, info);
-      const int g = nblocks(n - c - 1, kParts);
-      panel_update<<<g, 256, 0, st>>>(A, n, k0, kb, c, inv, pv, pi, j + 1 < kb ? 1 : 0);
-      parts = g;
-    }
-    if (n > kb) laswp<<<nblocks(n - kb, 4096), 256, 0, st>>>(A, n, k0, kb, ip);
+    // 64 rows per panel_col block; col_amax's partials are as many
+    const int parts = (int)std::min<int64_t>(kParts, ((int64_t)n - k0 + 63) / 64);
+    col_amax<<<parts, 256, 0, st>>>(A, n, k0, pvb[0], pib[0]);
+    for (int j = 0; j < kb; ++j)
+      panel_col<<<parts, 256, 0, st>>>(A, n, k0, kb, k0 + j, pvb[j & 1], pib[j & 1], parts, pvb[(j + 1) & 1],
+                                       pib[(j + 1) & 1], mark, plist, info, j + 1 < kb ? 1 : 0);
+    laswp<<<nblocks(n, 4096), 256, 0, st>>>(A, n, k0, kb, plist, ip);
     const int rest = n - k0 - kb;
     if (rest > 0) {
       trsm_lower_unit<<<std::min(1024, (rest + 3) / 4), 256, 0, st>>>(A + (size_t)k0 * n + k0, n,

@@ -12,7 +12,7 @@ struct DenseLU {
   DevBuf a;     // n x n column-major: unit lower L below the diagonal, U on and above
   DevBuf ipiv;  // row swapped with row c at step c
   DevBuf perm;  // (P z)[i] = z[perm[i]]
-  DevBuf work;  // pivot-search partials, 1/pivot, singularity flag
+  DevBuf work;  // pivot-search partials (two buffers), singularity flag, a panel's pivot rows, row marks
   static constexpr int kSB = 256;  // block size of the solves
   int nsb = 0;                     // diagonal blocks
   DevBuf dinvL, dinvU;  // -(L_bb)^{-1}, -(U_bb)^{-1} per diagonal block (kSB x kSB, column-major)
