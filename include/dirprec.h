@@ -53,7 +53,7 @@ enum {
   DP_EINVAL = -1,     /* invalid argument (see dp_last_error) */
   DP_ENOMEM = -2,     /* device allocation failed */
   DP_EDEVICE = -3,    /* HIP runtime error */
-  DP_ESINGULAR = -4,  /* zero pivot in the sparse LU of floor(W) */
+  DP_ESINGULAR = -4,  /* zero pivot in the LU of floor(W) */
   DP_ESTATE = -5      /* call order violated (e.g. apply before build) */
 };
 
@@ -343,6 +343,16 @@ void dp_server_destroy(dp_server* s);
  * _host: host arrays evaluated by the same source compiled for the CPU. */
 int dp_hankel_dev(dp_ctx* ctx, int64_t m, const double* z, double* out);
 int dp_hankel_host(int64_t m, const double* z, double* out);
+
+/* The dense device LU with partial pivoting that factors floor(W) when its
+ * sparse factors would fill in (Sec. 2.2), on a given matrix: a is a host
+ * n x n complex matrix (column-major, interleaved re/im, 1 <= n <= 8192).
+ * On DP_OK, lu (host, n x n, same layout) holds the unit lower L below the
+ * diagonal and U on and above, and perm (host, n) the row order: row i of
+ * L U is row perm[i] of a.  Pivots: the largest modulus in the column, ties
+ * to the lower row index.  DP_ESINGULAR when a pivot column is zero or not
+ * finite (lu and perm then untouched).  Synchronous. */
+int dp_dense_lu_test(dp_ctx* ctx, int64_t n, const double* a, double* lu, int64_t* perm);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,7 @@ EXPORTED = [
     "dp_problem_destroy", "dp_problem_kappa", "dp_rhs_plane_wave", "dp_matvec", "dp_matvec_mixed", "dp_layer_apply",
     "dp_precond_build", "dp_precond_apply", "dp_precond_apply_mixed", "dp_precond_apply_noalloc",
     "dp_precond_get_info", "dp_precond_export",
-    "dp_solve", "dp_hankel_dev", "dp_hankel_host",
+    "dp_solve", "dp_hankel_dev", "dp_hankel_host", "dp_dense_lu_test",
     "dp_autotune", "dp_server_create", "dp_server_submit", "dp_server_wait", "dp_server_get_stats", "dp_server_destroy",
 ]
 
@@ -141,6 +141,7 @@ def lib():
         "dp_solve": (ci, [vp, i64, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp, vp]),
         "dp_hankel_dev": (ci, [vp, i64, vp, vp]),
         "dp_hankel_host": (ci, [i64, vp, vp]),
+        "dp_dense_lu_test": (ci, [vp, i64, vp, vp, vp]),
         "dp_autotune": (ci, [vp, i64, ci, ctypes.POINTER(TuneInfo)]),
         "dp_server_create": (ci, [ci, ctypes.POINTER(ServerOpts), pp]),
         "dp_server_submit": (ci, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]),
@@ -376,6 +377,22 @@ def dp_hankel_host(z):
     _check("dp_hankel_host", lib().dp_hankel_host(za.size, zp, out.ctypes.data_as(ctypes.c_void_p)))
     out = out.reshape(-1, 4)
     return out[:, 0] + 1j * out[:, 1], out[:, 2] + 1j * out[:, 3]
+
+
+def dp_dense_lu_test(ctx, a):
+    """Dense device LU of the (n, n) complex matrix a: (rc, lu, perm) with
+    lu = L below the diagonal (unit) and U on and above, a[perm] = L U;
+    rc is DP_OK or DP_ESINGULAR (other errors raise)."""
+    a = np.asfortranarray(np.asarray(a, np.complex128))
+    n = a.shape[0]
+    if a.shape != (n, n):
+        raise ValueError("square matrix expected")
+    lu = np.zeros((n, n), np.complex128, order="F")
+    perm = np.zeros(n, np.int64)
+    rc = lib().dp_dense_lu_test(ctx.h, n, a.ctypes.data_as(ctypes.c_void_p), lu.ctypes.data_as(ctypes.c_void_p),
+                                perm.ctypes.data_as(ctypes.c_void_p))
+    _check("dp_dense_lu_test", rc, allow=(DP_ESINGULAR,))
+    return rc, lu, perm
 
 
 class Server:

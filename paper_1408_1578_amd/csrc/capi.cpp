@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 
+#include "dense_lu.hpp"
 #include "dp_internal.hpp"
 
 namespace dp {
@@ -550,6 +551,42 @@ int dp_hankel_dev(dp_ctx* ctx, int64_t m, const double* z, double* out) {
   DP_TRY(hankel_eval_dev(m, z, out, ctx->stream));
   DP_HIP(hipStreamSynchronize(ctx->stream));
   return DP_OK;
+}
+
+int dp_dense_lu_test(dp_ctx* ctx, int64_t n, const double* a, double* lu, int64_t* perm) {
+  DP_CHECK(ctx && a && lu && perm && n >= 1 && n <= 8192, "dp_dense_lu_test: bad argument");
+  DP_SETDEV(ctx);
+  hipStream_t st = ctx->stream;
+  const int nn = (int)n;
+  std::vector<int> rows, cols;
+  std::vector<cplx> vals;
+  const cplx* ac = reinterpret_cast<const cplx*>(a);
+  for (int c = 0; c < nn; ++c)
+    for (int r = 0; r < nn; ++r) {
+      const cplx v = ac[(size_t)c * nn + r];
+      if (v.re != 0.0 || v.im != 0.0) {  // NaN entries are kept too
+        rows.push_back(r);
+        cols.push_back(c);
+        vals.push_back(v);
+      }
+    }
+  DenseLU d;
+  int rc = d.assemble(st, nn, rows, cols, vals);
+  if (rc == DP_OK) rc = d.factor(st);
+  if (rc == DP_OK) {
+    std::vector<int> pm(nn);
+    if (hipMemcpyAsync(lu, d.a.p, (size_t)nn * nn * sizeof(cplx), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(pm.data(), d.perm.p, (size_t)nn * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("dp_dense_lu_test: copy of the factors failed");
+      rc = DP_EDEVICE;
+    } else {
+      for (int i = 0; i < nn; ++i) perm[i] = pm[i];
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  d.release();
+  return rc;
 }
 
 int dp_hankel_host(int64_t m, const double* z, double* out) {
