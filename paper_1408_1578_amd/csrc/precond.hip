@@ -29,6 +29,7 @@
 #include <system_error>
 #include <thread>
 #include <mutex>
+#include <queue>
 #include <vector>
 
 #include "dp_internal.hpp"
@@ -1275,13 +1276,19 @@ static int build_slots(const SparseLU& lu, std::vector<Slot<C>>& out) {
       for (int W : {1, 4, 16, 64}) {
         const int ng = 64 / W;
         std::vector<std::vector<int>> grp(ng);
-        std::vector<int> load(ng, 0);
+        // least-loaded group first, ties to the lower group index
+        std::priority_queue<std::pair<int, int>, std::vector<std::pair<int, int>>, std::greater<>> heap;
+        for (int g = 0; g < ng; ++g) heap.push({0, g});
+        int maxload = 0;
         for (const auto& [cnt, r] : rows) {
-          const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+          auto [ld, g] = heap.top();
+          heap.pop();
           grp[g].push_back(r);
-          load[g] += (cnt + W - 1) / W;
+          ld += (cnt + W - 1) / W;
+          maxload = std::max(maxload, ld);
+          heap.push({ld, g});
         }
-        const int nst = (*std::max_element(load.begin(), load.end()) + kTriBatch - 1) / kTriBatch * kTriBatch;
+        const int nst = (maxload + kTriBatch - 1) / kTriBatch * kTriBatch;
         if (nst < best_st) {
           best_st = nst;
           best_w = W;
