@@ -565,6 +565,7 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
                   bool sync) {
     if (st + 2 < nsteps) dma(st + 2, Btn, Ssn, Csn);
     const int jb = j0 + 32 * st;
+    const int lim = j1 - jb;  // sources at k-index jj >= lim lie past the chunk
     constexpr int CP = NCB >= 2 ? 2 : 1;
     constexpr int NG = NCB / CP;
     uint4 bb[2][CP][4];
@@ -591,10 +592,11 @@ __global__ __launch_bounds__(512) void sweep_mfma16(SweepParams p) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int jj = 4 * (2 * e2 + h) + lk;  // k-index 8 lk + e holds source 4 e + lk
-        const int j = jb + jj;
         const double2 xy = sxy[jj];
         const float4 nw = snw[jj];
-        pair_kernel_far32v<OP>(t, tf, xy.x, xy.y, nw.x, nw.y, nw.z, Cs[31 + ti - jj], j >= j1, f, K[h]);
+        // jj >= lim, with the step's constant part moved to the scalar side
+        const bool past = lk >= lim - 4 * (2 * e2 + h);
+        pair_kernel_far32v<OP>(t, tf, xy.x, xy.y, nw.x, nw.y, nw.z, Cs[31 + ti - jj], past, f, K[h]);
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
