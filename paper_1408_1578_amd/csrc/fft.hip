@@ -15,9 +15,10 @@ namespace dp {
 
 constexpr int kFftLds = 4096;  // complex elements per block
 // threads per block of the LDS passes, and elements per block of the
-// four-step derivative's passes (at n = 32768 x 64 columns: 106 us per
-// derivative against 116 with 256 threads and 4096-element blocks; more
-// blocks in flight per CU hide more of the load latency)
+// column and row passes (at n = 32768 x 64 columns: 106 us per derivative
+// against 116 with 256 threads and 4096-element blocks; Bluestein's
+// length-65536 transforms for n = 24576: 427 us per derivative against 447;
+// more blocks in flight per CU hide more of the load latency)
 constexpr int kFftThreads = 512;
 constexpr int kFftTile = 2048;
 
@@ -227,16 +228,18 @@ static void fft_run(cplx* d, int N, const cplx* tw, int nb, int dir, hipStream_t
   const int log2n = logn - log1;
   const int n1 = 1 << log1, n2 = 1 << log2n;
   auto col = [&](int dirc) {
-    int lines = kFftLds / n1;
+    int lines = kFftTile / n1;
     if (lines > n2) lines = n2;
+    if (lines < 1) lines = 1;
     dim3 g(n2 / lines, nb);
     fft_col_pass<<<g, kFftThreads, (size_t)n1 * lines * sizeof(cplx), st>>>(d, d, N, n1, n2, log1, lines, tw, dirc,
                                                                      n2 > 1, nullptr);
   };
   auto row = [&](int dirc) {
     if (n2 == 1) return;
-    int lines = kFftLds / n2;
+    int lines = kFftTile / n2;
     if (lines > n1) lines = n1;
+    if (lines < 1) lines = 1;
     dim3 g(n1 / lines, nb);
     fft_row_pass<<<g, kFftThreads, (size_t)n2 * lines * sizeof(cplx), st>>>(d, N, n2, log2n, lines, tw, dirc);
   };
