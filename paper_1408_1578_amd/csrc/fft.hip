@@ -363,6 +363,149 @@ __global__ void blu_post(const cplx* __restrict__ a, cplx* __restrict__ out, con
   }
 }
 
+// Fused passes of a Bluestein derivative when M = n1 n2 takes the four-step
+// path (n2 > 1): five passes instead of the thirteen of the separate
+// transforms and pointwise kernels, with the same operations in the same
+// order.  Column pass modes (each block: `lines` lines j2 over j1):
+//   kBluPre : a = forward column transform of in conj(c) (zero for j >= n);
+//   kBluMid : inverse column transform, the step between the convolutions
+//             (blu_mid), forward column transform, in place on a;
+//   kBluPost: inverse column transform, out = c a (divided by the speed
+//             with src), j < n.
+enum { kBluPre = 0, kBluMid = 1, kBluPost = 2 };
+template <int MODE>
+__global__ __launch_bounds__(kFftThreads) void blu_col(const cplx* __restrict__ in, cplx* a, cplx* __restrict__ out,
+                                                       const cplx* __restrict__ chirp, const SrcRec* __restrict__ src,
+                                                       int n, int M, int n1, int n2, int logn1, int lines,
+                                                       const cplx* __restrict__ tw) {
+  extern __shared__ cplx sbuf[];
+  const size_t b = blockIdx.y;
+  const int j2_0 = blockIdx.x * lines;
+  const int loglines = __builtin_ctz(lines);
+  cplx* ab = a + b * M;
+  for (int t = threadIdx.x; t < n1 * lines; t += blockDim.x) {
+    const int l = t & (lines - 1), j1 = t >> loglines;
+    const int j = n2 * j1 + j2_0 + l;
+    cplx v;
+    if (MODE == kBluPre) {
+      v = {0.0, 0.0};
+      if (j < n) {
+        const cplx x = in[b * n + j], c = chirp[j];
+        v = {x.re * c.re + x.im * c.im, x.im * c.re - x.re * c.im};
+      }
+    } else {  // inverse: pre-twiddle e^{+2 pi i j2 k1/M} (k1 = j1 here)
+      v = ab[j];
+      cplx w = tw[((j2_0 + l) * j1) & (M - 1)];
+      w.im = -w.im;
+      v = cmul(v, w);
+    }
+    sbuf[bitrev(j1, logn1) * lines + l] = v;
+  }
+  __syncthreads();
+  if (MODE != kBluPre) {
+    lds_fft(sbuf, n1, lines, loglines, tw, M, +1);
+    if (MODE == kBluMid) {
+      // natural index k = n2 k1 + j2 at sbuf[k1 lines + l]: the step between
+      // the convolutions, then into bit-reversed order for the forward
+      // transform (every element read before any is overwritten)
+      constexpr int PER = kFftLds / kFftThreads;
+      cplx tmp[PER];
+      int dst[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int t = threadIdx.x + kFftThreads * q;
+        dst[q] = -1;
+        if (t < n1 * lines) {
+          const int l = t & (lines - 1), k1 = t >> loglines;
+          const int k = n2 * k1 + j2_0 + l;
+          cplx v = {0.0, 0.0};
+          if (k < n) {
+            const cplx c = chirp[k], y = sbuf[k1 * lines + l];
+            const cplx X = {y.re * c.re + y.im * c.im, y.im * c.re - y.re * c.im};
+            const int m = (k < n / 2) ? k : ((k == n / 2) ? 0 : k - n);
+            const double f = (double)m / n;
+            const cplx U = {-f * X.im, f * X.re};
+            v = cmul(U, c);
+          }
+          tmp[q] = v;
+          dst[q] = bitrev(k1, logn1) * lines + l;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        if (dst[q] >= 0) sbuf[dst[q]] = tmp[q];
+      __syncthreads();
+    }
+  }
+  if (MODE != kBluPost) lds_fft(sbuf, n1, lines, loglines, tw, M, -1);
+  for (int t = threadIdx.x; t < n1 * lines; t += blockDim.x) {
+    const int l = t & (lines - 1), k1 = t >> loglines;
+    const int o = n2 * k1 + j2_0 + l;
+    cplx v = sbuf[k1 * lines + l];
+    if (MODE == kBluPost) {
+      if (o < n) {
+        v = cmul(chirp[o], v);
+        if (src) {
+          const double r = 1.0 / src[o].sp;
+          v = {v.re * r, v.im * r};
+        }
+        out[b * n + o] = v;
+      }
+    } else {  // forward: post-twiddle e^{-2 pi i j2 k1/M}
+      v = cmul(v, tw[((j2_0 + l) * k1) & (M - 1)]);
+      ab[o] = v;
+    }
+  }
+}
+
+// Row pass of a Bluestein convolution: per line (fixed k1) the forward
+// transform over k2, a *= B (conj B with conjB) / M at the spectrum
+// positions n2 k1 + k2 (the layout B itself has), and the inverse transform.
+__global__ __launch_bounds__(kFftThreads) void blu_row_conv(cplx* a, int M, int n2, int logn2, int lines,
+                                                            const cplx* __restrict__ tw, const cplx* __restrict__ B,
+                                                            int conjB) {
+  extern __shared__ cplx sbuf[];
+  const size_t b = blockIdx.y;
+  const int k1_0 = blockIdx.x * lines;
+  const int loglines = __builtin_ctz(lines);
+  cplx* base = a + b * M + (size_t)k1_0 * n2;
+  const cplx* Bb = B + (size_t)k1_0 * n2;
+  for (int t = threadIdx.x; t < n2 * lines; t += blockDim.x) {
+    const int e = t & (n2 - 1), l = t >> logn2;
+    sbuf[bitrev(e, logn2) * lines + l] = base[(size_t)l * n2 + e];
+  }
+  __syncthreads();
+  lds_fft(sbuf, n2, lines, loglines, tw, M, -1);
+  constexpr int PER = kFftLds / kFftThreads;  // n2 * lines <= kFftLds
+  const double s = 1.0 / M;
+  cplx tmp[PER];
+  int dst[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + kFftThreads * q;
+    dst[q] = -1;
+    if (t < n2 * lines) {
+      const int e = t & (n2 - 1), l = t >> logn2;
+      cplx w = Bb[(size_t)l * n2 + e];
+      if (conjB) w.im = -w.im;
+      const cplx v = cmul(sbuf[e * lines + l], w);
+      tmp[q] = {v.re * s, v.im * s};
+      dst[q] = bitrev(e, logn2) * lines + l;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+    if (dst[q] >= 0) sbuf[dst[q]] = tmp[q];
+  __syncthreads();
+  lds_fft(sbuf, n2, lines, loglines, tw, M, +1);
+  for (int t = threadIdx.x; t < n2 * lines; t += blockDim.x) {
+    const int e = t & (n2 - 1), l = t >> logn2;
+    base[(size_t)l * n2 + e] = sbuf[e * lines + l];
+  }
+}
+
 int bluestein_init(dp_problem* p) {
   const int n = (int)p->n;
   int M = 1;
@@ -389,6 +532,27 @@ static int bluestein_derivative(dp_problem* p, const cplx* in, cplx* out, int nb
   const cplx* c = p->blu_chirp.as<cplx>();
   const cplx* B = p->blu_B.as<cplx>();
   const cplx* tw = p->blu_tw.as<cplx>();
+  const SrcRec* sp = divide ? p->src.as<SrcRec>() : nullptr;
+  const int logM = ilog2(M);
+  const int log1 = logM <= 12 ? logM : (logM + 1) / 2;
+  const int n1 = 1 << log1, n2 = 1 << (logM - log1);
+  if (n2 > 1) {  // four-step transforms: the fused passes
+    int lc = kFftTile / n1;
+    if (lc > n2) lc = n2;
+    if (lc < 1) lc = 1;
+    int lr = kFftTile / n2;
+    if (lr > n1) lr = n1;
+    if (lr < 1) lr = 1;
+    const dim3 gc(n2 / lc, nb), gr(n1 / lr, nb);
+    const size_t ldc = (size_t)n1 * lc * sizeof(cplx), ldr = (size_t)n2 * lr * sizeof(cplx);
+    blu_col<kBluPre><<<gc, kFftThreads, ldc, st>>>(in, a, nullptr, c, nullptr, n, M, n1, n2, log1, lc, tw);
+    blu_row_conv<<<gr, kFftThreads, ldr, st>>>(a, M, n2, logM - log1, lr, tw, B, 0);
+    blu_col<kBluMid><<<gc, kFftThreads, ldc, st>>>(nullptr, a, nullptr, c, nullptr, n, M, n1, n2, log1, lc, tw);
+    blu_row_conv<<<gr, kFftThreads, ldr, st>>>(a, M, n2, logM - log1, lr, tw, B, 1);
+    blu_col<kBluPost><<<gc, kFftThreads, ldc, st>>>(nullptr, a, out, c, sp, n, M, n1, n2, log1, lc, tw);
+    DP_HIP(hipGetLastError());
+    return DP_OK;
+  }
   const int gM = grid_for((size_t)M * nb);
   blu_premul<<<gM, 256, 0, st>>>(in, a, c, n, M, nb);
   fft_run(a, M, tw, nb, -1, st);
@@ -398,7 +562,7 @@ static int bluestein_derivative(dp_problem* p, const cplx* in, cplx* out, int nb
   fft_run(a, M, tw, nb, -1, st);
   blu_mul<<<gM, 256, 0, st>>>(a, B, M, nb, 1);
   fft_run(a, M, tw, nb, +1, st);
-  blu_post<<<grid_for((size_t)n * nb), 256, 0, st>>>(a, out, c, divide ? p->src.as<SrcRec>() : nullptr, n, M, nb);
+  blu_post<<<grid_for((size_t)n * nb), 256, 0, st>>>(a, out, c, sp, n, M, nb);
   DP_HIP(hipGetLastError());
   return DP_OK;
 }
