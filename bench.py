@@ -52,7 +52,7 @@ FLOPS_MFMA16_PER_COL = 24
 # bytes the copy moves).  They describe the current kernels in that
 # configuration; another configuration or a changed kernel must be measured
 # again before they are reported.
-TRAFFIC_FP64_SWEEP = 1.1280e9 + 0.2706e9
+TRAFFIC_FP64_SWEEP = 1.1280e9 + 0.2705e9
 TRAFFIC_FP32_SWEEP = 0.3025e9 + 0.2684e9
 
 # Algorithmic FP64 flops of one ordered pair in the sound-hard sweep (far-field
