@@ -19,6 +19,8 @@
 //   3. U12 = L11^{-1} A12 (one wave per column, L11 in LDS);
 //   4. A22 -= L21 U12 on the FP64 matrix cores (v_mfma_f64_16x16x4, complex
 //      products in the 3-multiplication form).
+// Panels go in pairs: the right panel's columns are updated by the left one
+// alone, and the trailing matrix takes one update with K = 128 per pair.
 // After the factorisation the 256 x 256 diagonal blocks of L and U are
 // inverted (with the same kernels); the solves apply the row permutation,
 // then blocked forward and backward substitution made of matrix-core products
@@ -550,21 +552,46 @@ int DenseLU::factor(hipStream_t st) {
   DP_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
   DP_HIP(hipMemsetAsync(mark, 0xFF, (size_t)n * sizeof(int), st));  // -1: never chosen
   int* ip = ipiv.as<int>();
-  for (int k0 = 0; k0 < n; k0 += kNB) {
-    const int kb = std::min(kNB, n - k0);
-    // 64 rows per panel_col block; col_amax's partials are as many
-    const int parts = (int)std::min<int64_t>(kParts, ((int64_t)n - k0 + 63) / 64);
+  // one 64-column panel: pivots and eliminations, then its row swaps on
+  // every column
+  auto panel = [&](int k0, int kb) {
+    const int parts = (int)std::min<int64_t>(kParts, ((int64_t)n - k0 + 63) / 64);  // 64 rows per panel_col block
     col_amax<<<parts, 256, 0, st>>>(A, n, k0, pvb[0], pib[0]);
     for (int j = 0; j < kb; ++j)
       panel_col<<<parts, 256, 0, st>>>(A, n, k0, kb, k0 + j, pvb[j & 1], pib[j & 1], parts, pvb[(j + 1) & 1],
                                        pib[(j + 1) & 1], mark, plist, info, j + 1 < kb ? 1 : 0);
     laswp<<<nblocks(n, 4096), 256, 0, st>>>(A, n, k0, kb, plist, ip);
-    const int rest = n - k0 - kb;
+  };
+  // X = L^{-1} X for the unit lower block of the panel at k0 (kb x kb) and the
+  // kb x ncols block of rows k0.. and columns c0..
+  auto trsm = [&](int k0, int kb, int c0, int ncols) {
+    trsm_lower_unit<<<std::min(1024, (ncols + 3) / 4), 256, 0, st>>>(A + (size_t)k0 * n + k0, n,
+                                                                      A + (size_t)c0 * n + k0, n, kb, ncols);
+  };
+  // Blocks of two panels (128 columns): the left panel, the update of the
+  // right panel's columns only, the right panel, the U rows of both on the
+  // trailing columns, and one trailing update with K = 128 (half the passes
+  // over the trailing matrix of an update per panel).
+  for (int K0 = 0; K0 < n; K0 += 2 * kNB) {
+    const int KB = std::min(2 * kNB, n - K0);
+    const int kb = std::min(kNB, KB), kb2 = KB - kb;
+    panel(K0, kb);
+    if (kb2 > 0) {
+      trsm(K0, kb, K0 + kb, kb2);
+      launch_gemm_sub(st, A + (size_t)K0 * n + K0 + kb, n, A + (size_t)(K0 + kb) * n + K0, n,
+                      A + (size_t)(K0 + kb) * n + K0 + kb, n, n - K0 - kb, kb2, kb);
+      panel(K0 + kb, kb2);
+    }
+    const int rest = n - K0 - KB;
     if (rest > 0) {
-      trsm_lower_unit<<<std::min(1024, (rest + 3) / 4), 256, 0, st>>>(A + (size_t)k0 * n + k0, n,
-                                                                       A + (size_t)(k0 + kb) * n + k0, n, kb, rest);
-      launch_gemm_sub(st, A + (size_t)k0 * n + k0 + kb, n, A + (size_t)(k0 + kb) * n + k0, n,
-                      A + (size_t)(k0 + kb) * n + k0 + kb, n, rest, rest, kb);
+      trsm(K0, kb, K0 + KB, rest);
+      if (kb2 > 0) {
+        launch_gemm_sub(st, A + (size_t)K0 * n + K0 + kb, n, A + (size_t)(K0 + KB) * n + K0, n,
+                        A + (size_t)(K0 + KB) * n + K0 + kb, n, kb2, rest, kb);
+        trsm(K0 + kb, kb2, K0 + KB, rest);
+      }
+      launch_gemm_sub(st, A + (size_t)K0 * n + K0 + KB, n, A + (size_t)(K0 + KB) * n + K0, n,
+                      A + (size_t)(K0 + KB) * n + K0 + KB, n, rest, rest, KB);
     }
     DP_HIP(hipGetLastError());
   }
