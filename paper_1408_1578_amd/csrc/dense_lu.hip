@@ -19,8 +19,9 @@
 //   3. U12 = L11^{-1} A12 (one wave per column, L11 in LDS);
 //   4. A22 -= L21 U12 on the FP64 matrix cores (v_mfma_f64_16x16x4, complex
 //      products in the 3-multiplication form).
-// Panels go in pairs: the right panel's columns are updated by the left one
-// alone, and the trailing matrix takes one update with K = 128 per pair.
+// Panels go in blocks of two or four: a panel's columns are updated by the
+// block's earlier panels before it is factored, and the trailing matrix takes
+// one update with K = 128 or 256 per block.
 // After the factorisation the 256 x 256 diagonal blocks of L and U are
 // inverted (with the same kernels); the solves apply the row permutation,
 // then blocked forward and backward substitution made of matrix-core products
@@ -37,6 +38,12 @@ namespace {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNB = 64;       // panel width and solve block
+// panels per block of the factorisation: 4 (trailing updates with K = 256)
+// from n = kPanels4Min on, else 2 (K = 128).  Setup times with a dense
+// floor(W), pairs against blocks of four: 37.5 / 38.8 ms at n = 3490, 90.5 /
+// 90.5 at 6861, 318 / 294 at 13563 (the small products of a four-panel block
+// cost more than the saved passes over a small trailing matrix).
+constexpr int kPanels4Min = 8192;
 constexpr int kParts = 1024;  // largest number of pivot-search partials
 
 __device__ __forceinline__ double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
@@ -568,28 +575,40 @@ int DenseLU::factor(hipStream_t st) {
     trsm_lower_unit<<<std::min(1024, (ncols + 3) / 4), 256, 0, st>>>(A + (size_t)k0 * n + k0, n,
                                                                       A + (size_t)c0 * n + k0, n, kb, ncols);
   };
-  // Blocks of two panels (128 columns): the left panel, the update of the
-  // right panel's columns only, the right panel, the U rows of both on the
-  // trailing columns, and one trailing update with K = 128 (half the passes
-  // over the trailing matrix of an update per panel).
-  for (int K0 = 0; K0 < n; K0 += 2 * kNB) {
-    const int KB = std::min(2 * kNB, n - K0);
-    const int kb = std::min(kNB, KB), kb2 = KB - kb;
-    panel(K0, kb);
-    if (kb2 > 0) {
-      trsm(K0, kb, K0 + kb, kb2);
-      launch_gemm_sub(st, A + (size_t)K0 * n + K0 + kb, n, A + (size_t)(K0 + kb) * n + K0, n,
-                      A + (size_t)(K0 + kb) * n + K0 + kb, n, n - K0 - kb, kb2, kb);
-      panel(K0 + kb, kb2);
+  // U rows of the first np_ panels of the block at K0 (all 64 wide) on the
+  // columns c0..c0 + nc - 1: block forward substitution, panel by panel
+  auto bsub = [&](int K0, int np_, int c0, int nc) {
+    for (int h = 0; h < np_; ++h) {
+      const int off = K0 + h * kNB;
+      trsm(off, kNB, c0, nc);
+      const int below = (np_ - 1 - h) * kNB;
+      if (below > 0)
+        launch_gemm_sub(st, A + (size_t)off * n + off + kNB, n, A + (size_t)c0 * n + off, n,
+                        A + (size_t)c0 * n + off + kNB, n, below, nc, kNB);
+    }
+  };
+  // Blocks of kPanels panels.  Before a panel is factored, its columns take
+  // the block's earlier panels: their U rows by block forward substitution,
+  // then one update of the rows below with K = 64 (earlier panels).  After
+  // the block, the trailing columns take the U rows of all its panels and one
+  // update with K = 64 kPanels: a half or a quarter of the passes over the
+  // trailing matrix of one update per panel.
+  const int kPanels = n >= kPanels4Min ? 4 : 2;
+  for (int K0 = 0; K0 < n; K0 += kPanels * kNB) {
+    const int KB = std::min(kPanels * kNB, n - K0);
+    int np_ = 0;
+    for (int c = K0; c < K0 + KB; c += kNB, ++np_) {
+      const int w = std::min(kNB, K0 + KB - c);
+      if (np_ > 0) {
+        bsub(K0, np_, c, w);
+        launch_gemm_sub(st, A + (size_t)K0 * n + c, n, A + (size_t)c * n + K0, n, A + (size_t)c * n + c, n, n - c,
+                        w, c - K0);
+      }
+      panel(c, w);
     }
     const int rest = n - K0 - KB;
-    if (rest > 0) {
-      trsm(K0, kb, K0 + KB, rest);
-      if (kb2 > 0) {
-        launch_gemm_sub(st, A + (size_t)K0 * n + K0 + kb, n, A + (size_t)(K0 + KB) * n + K0, n,
-                        A + (size_t)(K0 + KB) * n + K0 + kb, n, kb2, rest, kb);
-        trsm(K0 + kb, kb2, K0 + KB, rest);
-      }
+    if (rest > 0) {  // the block's panels are all full
+      bsub(K0, np_, K0 + KB, rest);
       launch_gemm_sub(st, A + (size_t)K0 * n + K0 + KB, n, A + (size_t)(K0 + KB) * n + K0, n,
                       A + (size_t)(K0 + KB) * n + K0 + KB, n, rest, rest, KB);
     }

@@ -8,6 +8,8 @@ factors would fill in), on given matrices through dp_dense_lu_test.
 - L U reproduces the rows of the matrix in the returned order.
 - A zero or non-finite pivot column gives DP_ESINGULAR, and the library keeps
   working afterwards.
+- At n = 8192 (blocks of four panels) the row order of a shuffled, diagonally
+  dominant banded L0 U0 is recovered exactly, with factors L0 and U0.
 """
 import numpy as np
 import pytest
@@ -83,3 +85,29 @@ def test_dense_lu_singular_reports(ctx, bad):
     assert rc == dp.DP_OK
     L = np.tril(lu, -1) + np.eye(70)
     assert np.abs(L @ np.triu(lu) - B[perm]).max() <= 1e-12 * np.abs(B).max()
+
+
+def test_dense_lu_four_panel_blocks_recover_row_order(ctx):
+    # n = 8192 takes the blocks of four panels.  The rows of a diagonally
+    # dominant banded product L0 U0 (unit L0 with entries ~0.01, U0 with
+    # diagonal ~10 and entries ~0.1) are shuffled: at every step the row of the
+    # next diagonal is the largest candidate by a wide margin, so partial
+    # pivoting undoes the shuffle exactly and the factors are L0 and U0.
+    import scipy.sparse as sp
+    n, bw = 8192, 8
+    rng = np.random.default_rng(9)
+
+    def band(k, s):
+        return s * (rng.standard_normal(n - k) + 1j * rng.standard_normal(n - k))
+
+    L0 = sp.eye(n, dtype=np.complex128) + sp.diags([band(k, 0.01) for k in range(1, bw + 1)],
+                                                   [-k for k in range(1, bw + 1)])
+    U0 = sp.diags([10.0 + rng.random(n)] + [band(k, 0.1) for k in range(1, bw + 1)], list(range(bw + 1)))
+    shuf = rng.permutation(n)
+    A = (L0 @ U0).tocsr()[shuf].toarray()
+    rc, lu, perm = dp.dp_dense_lu_test(ctx, A)
+    del A
+    assert rc == dp.DP_OK
+    assert np.array_equal(shuf[perm], np.arange(n))
+    ref = (L0 - sp.eye(n) + U0).toarray()
+    assert np.abs(lu - ref).max() <= 1e-12 * 10
