@@ -106,8 +106,33 @@ __global__ __launch_bounds__(256) void col_amax(const cplx* __restrict__ A, int 
 // (when want_next) into the other partial buffer.  Row p is not moved:
 // block 0 marks it (mark[p] = c; rows whose mark is below k0 are not chosen
 // in this panel) and records it in plist[j].  A zero or non-finite pivot
-// sets *info = c + 1 once and continues with 1/0 = 0.
+// sets *info = c + 1 once and continues with 1/0 = 0.  A thread requests its
+// first row's entries before the pivot is known (they do not depend on it),
+// and the block's barriers order LDS only, so those loads run while the
+// partials are reduced and the pivot row is read.
 constexpr int kUpdChunk = 16;  // later columns per wave (4 waves cover the 63 of a panel)
+
+// Block barrier for LDS only: the block's LDS accesses before it are complete,
+// while its global loads may stay in flight across it (a full __syncthreads
+// waits for those too).
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// reduce_best with LDS-only barriers
+__device__ __forceinline__ void reduce_best_lds(double* sv, int* si) {
+  const int t = threadIdx.x;
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s && better(sv[t + s], si[t + s], sv[t], si[t])) {
+      sv[t] = sv[t + s];
+      si[t] = si[t + s];
+    }
+    lds_sync();
+  }
+}
+
 __global__ __launch_bounds__(256) void panel_col(cplx* A, int n, int k0, int kb, int c, const double* pv_in,
                                                  const int* pi_in, int nparts, double* pv_out, int* pi_out,
                                                  int* mark, int* plist, int* info, int want_next) {
@@ -117,17 +142,38 @@ __global__ __launch_bounds__(256) void panel_col(cplx* A, int n, int k0, int kb,
   __shared__ int sp;
   const int j = c - k0;
   const int tid = threadIdx.x;
-  double bv = -1.0;
-  int bi = INT_MAX;
-  for (int q = tid; q < nparts; q += 256)
+  const int lane = tid & 63, w = tid >> 6;
+  const int j0 = j + 1 + kUpdChunk * w;                                  // this wave's first later column
+  const int r0 = (w == 0 || j0 < kb) ? k0 + blockIdx.x * 64 + lane : n;  // waves without columns skip
+  const int rstep = gridDim.x * 64;
+  // this thread's first partial, then the first row's mark and entries,
+  // requested before the pivot is known (they do not depend on it): loads
+  // complete in order, so the partial comes first, and the row's entries
+  // arrive while the partials are reduced
+  // (straight-line, with the indices clamped to valid entries, so that the
+  // wait for the partial does not have to assume the row's loads were skipped)
+  const int q0 = tid < nparts ? tid : nparts - 1;  // nparts >= 1
+  double bv = pv_in[q0];
+  int bi = pi_in[q0];
+  if (tid >= nparts) {
+    bv = -1.0;
+    bi = INT_MAX;
+  }
+  const int rr = r0 < n ? r0 : n - 1;
+  const int mk0 = mark[rr];
+  const cplx a0 = A[(size_t)c * n + rr];
+  cplx x0[kUpdChunk];
+#pragma unroll
+  for (int u = 0; u < kUpdChunk; ++u) x0[u] = A[(size_t)(k0 + min(j0 + u, kb - 1)) * n + rr];
+  for (int q = tid + 256; q < nparts; q += 256)
     if (better(pv_in[q], pi_in[q], bv, bi)) {
       bv = pv_in[q];
       bi = pi_in[q];
     }
   sv[tid] = bv;
   si[tid] = bi;
-  __syncthreads();
-  reduce_best(sv, si);
+  lds_sync();
+  reduce_best_lds(sv, si);
   const bool inrange = si[0] >= k0 && si[0] < n;
   const bool bad = !(sv[0] > 0.0) || !(sv[0] < 1e300) || !inrange;
   if (tid == 0) {
@@ -138,23 +184,16 @@ __global__ __launch_bounds__(256) void panel_col(cplx* A, int n, int k0, int kb,
     }
     sp = p;
   }
-  __syncthreads();
+  lds_sync();
   const int p = sp;
   if (tid < kb) prow[tid] = A[(size_t)(k0 + tid) * n + p];
-  __syncthreads();
+  lds_sync();
   const cplx inv = crecip(prow[j]);
-  const int lane = tid & 63, w = tid >> 6;
-  const int j0 = j + 1 + kUpdChunk * w;  // this wave's first later column
   double nb = -1.0;
   int ni = INT_MAX;
-  const int r0 = (w == 0 || j0 < kb) ? k0 + blockIdx.x * 64 + lane : n;  // waves without columns skip
-  for (int r = r0; r < n; r += gridDim.x * 64) {
-    if (r == p || mark[r] >= k0) continue;
-    const cplx a = A[(size_t)c * n + r];
-    cplx x[kUpdChunk];
-#pragma unroll
-    for (int u = 0; u < kUpdChunk; ++u)
-      if (j0 + u < kb) x[u] = A[(size_t)(k0 + j0 + u) * n + r];
+  // l = a/pivot in column c (wave 0), the rank-1 update of this wave's
+  // columns, and the candidate of column c + 1 (wave 0, its first column)
+  auto row = [&](int r, const cplx a, cplx (&x)[kUpdChunk]) {
     const cplx l = cmul(a, inv);
     if (w == 0) A[(size_t)c * n + r] = l;
 #pragma unroll
@@ -164,19 +203,29 @@ __global__ __launch_bounds__(256) void panel_col(cplx* A, int n, int k0, int kb,
         x[u] = {x[u].re - (l.re * v.re - l.im * v.im), x[u].im - (l.re * v.im + l.im * v.re)};
         A[(size_t)(k0 + j0 + u) * n + r] = x[u];
       }
-    if (w == 0 && want_next) {  // column c + 1 is this wave's first
+    if (w == 0 && want_next) {
       const double v = cabs2(x[0]);
       if (better(v, r, nb, ni)) {
         nb = v;
         ni = r;
       }
     }
+  };
+  if (r0 < n && r0 != p && mk0 < k0) row(r0, a0, x0);
+  for (int r = r0 + rstep; r < n; r += rstep) {  // more rows than 64 per block (n - k0 > 65536)
+    if (r == p || mark[r] >= k0) continue;
+    const cplx a = A[(size_t)c * n + r];
+    cplx x[kUpdChunk];
+#pragma unroll
+    for (int u = 0; u < kUpdChunk; ++u)
+      if (j0 + u < kb) x[u] = A[(size_t)(k0 + j0 + u) * n + r];
+    row(r, a, x);
   }
-  __syncthreads();  // every thread is past its reads of the first reduction
+  lds_sync();  // every thread is past its reads of the first reduction
   sv[tid] = nb;
   si[tid] = ni;
-  __syncthreads();
-  reduce_best(sv, si);
+  lds_sync();
+  reduce_best_lds(sv, si);
   if (tid == 0) {
     pv_out[blockIdx.x] = sv[0];
     pi_out[blockIdx.x] = si[0];
